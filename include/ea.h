@@ -1,0 +1,150 @@
+/*
+ * ea.h -- C ABI of the MI355X (gfx950) library for checkerboard Metropolis
+ * ageing simulations of the three-dimensional +-J Edwards-Anderson model
+ * (Manssen & Hartmann, "Ageing at the Spin-Glass/Ferromagnet Transition:
+ * Monte Carlo Simulation using GPUs").
+ *
+ * Model (Sec. II, eq. 1): N = L^3 Ising spins on a periodic cubic lattice,
+ * H = -sum_<ij> J_ij S_i S_j with i.i.d. couplings J = +-1.  In this library
+ * p is the probability of an antiferromagnetic coupling, P(J = -1) = p (the
+ * paper's p is the ferromagnetic fraction, 1 - p here).  A run is one
+ * coupling realisation ("sample") with two replicas that start from
+ * independent random spins (quench from infinite temperature) and evolve
+ * with independent thermal noise.
+ *
+ * Dynamics (Sec. III, eq. 9): single-spin-flip Metropolis on the two
+ * checkerboard sub-lattices.  Colour c(x,y,z) = (x+y+z) & 1.  A sweep is two
+ * half-steps; replica r updates colour r in the first and colour 1-r in the
+ * second (the interlaced order of Fig. 1).  A site whose flip changes the
+ * energy by dE <= 0 flips; dE = 4k > 0 flips iff its random word u is below
+ * thr_k = floor(exp(-4k/T) 2^32) (0 at T = 0).  The random word of a site is
+ * word (h & 3) of the Philox4x32-10 block with key = seed and counter
+ * (h >> 2, t, tag << 8 | colour << 1 | replica, sample), where
+ * h = (x >> 1) + (L/2)(y + L z) is the site's index inside its colour, t the
+ * 0-based sweep index and tag 0.  Couplings use tag 1 (counter word 1 = bond
+ * direction, replica 0; J = -1 iff u < floor(p 2^32) compared in 64 bits),
+ * initial spins tag 2 (S = -1 iff the top bit of u is set).  Results
+ * therefore depend only on (L, p, T, seed, sample, schedule), never on the
+ * launch configuration.
+ *
+ * Conventions of the ABI:
+ *   - every call returns ea_status; EA_OK = 0, errors are negative and
+ *     ea_last_error() returns a message for the calling thread;
+ *   - handles are owned by the caller from *_create until *_destroy
+ *     (destroy accepts NULL);
+ *   - host arrays are owned by the caller and must have the documented size;
+ *   - device memory is owned by the library unless ea_config.dev_buf is
+ *     given, in which case the library carves its arrays from that buffer
+ *     (at least ea_footprint() bytes, 256-byte aligned, outliving the handle);
+ *   - work is enqueued on ea_config.stream (a hipStream_t; NULL means the
+ *     library creates and owns one); ea_sweep and ea_snapshot return without
+ *     waiting, every call that hands data to the host synchronises that
+ *     stream;
+ *   - a handle is used by one host thread at a time.
+ * Spin and coupling arrays exchanged with the host are int8 +-1 in canonical
+ * order s = x + L (y + L z); couplings are laid out [s][d], J[3 s + d]
+ * coupling s to s + e_d (d = 0, 1, 2 for x, y, z), the "left/up" bonds of
+ * Sec. III.
+ */
+#ifndef EA_H
+#define EA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    EA_OK = 0,
+    EA_ERR_ARG = -1,     /* an argument is out of range or inconsistent */
+    EA_ERR_NOMEM = -2,   /* device or host allocation failed */
+    EA_ERR_DEVICE = -3,  /* a HIP call failed */
+    EA_ERR_STATE = -4,   /* the call does not fit the handle's state */
+    EA_ERR_BUSY = -5     /* a queue is full; retry later */
+} ea_status;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *ea_last_error(void);
+
+/* Library version string. */
+const char *ea_version(void);
+
+typedef struct ea_sim ea_sim;
+
+typedef struct {
+    int32_t L;            /* side length: multiple of 8, 8..256 */
+    double p;             /* P(J = -1), in [0, 1] */
+    double T;             /* temperature >= 0, finite (J = 1, k_B = 1) */
+    uint64_t seed;        /* Philox key */
+    uint32_t sample;      /* disorder sample index (counter word 3) */
+    int32_t n_tw_slots;   /* number of reference configurations S(t_w), 0..64 */
+    void *stream;         /* hipStream_t to enqueue on, or NULL */
+    void *dev_buf;        /* optional caller-owned device buffer, or NULL */
+    size_t dev_buf_bytes; /* its size in bytes */
+} ea_config;
+
+/* Observables at the current time t, integer sums over the N sites (the
+ * paper's normalised quantities are these divided by N):
+ *   unsat[r]    unsatisfied bonds of replica r; energy E_r = 2 unsat[r] - 3N (eq. 1)
+ *   mag[r]      sum_s S_r(s)
+ *   overlap     sum_s S_0(s) S_1(s)  (N q, eq. 2)
+ *   autocorr    [2][n_tw]: sum_s S_r(s,t) S_r(s,tw_k)  (N C(t - tw_k, tw_k), eq. 7)
+ *   c4          [3][rmax+1]: sum_s q(s) q(s + rho e_d), q = S_0 S_1, rho = 0..rmax
+ *               (N C4(rho e_d, t), eq. 3)
+ *   tw          [n_tw]: time at which each slot was taken (0 if never);
+ *               a slot that was never taken reports autocorr 0
+ * The caller provides tw/autocorr (n_tw = the handle's slot count, or 0 and
+ * NULL to skip) and c4 (rmax = L/2, or NULL to skip). */
+typedef struct {
+    uint64_t t;
+    int64_t unsat[2];
+    int64_t mag[2];
+    int64_t overlap;
+    int32_t n_tw;
+    uint64_t *tw;
+    int64_t *autocorr;
+    int32_t rmax;
+    int64_t *c4;
+} ea_obs;
+
+/* Device bytes a run of side L with n_tw snapshot slots needs. */
+ea_status ea_footprint(int32_t L, int32_t n_tw, size_t *bytes);
+
+/* Acceptance thresholds of eq. (9): out[k-1] for dE = 4k, k = 1..3. */
+ea_status ea_thresholds(double T, uint32_t out[3]);
+
+/* Create a run and generate its couplings and initial spins on the device
+ * (t = 0).  EA_ERR_ARG for L not a multiple of 8 or outside 8..256, p outside
+ * [0,1] or NaN, T negative or not finite, n_tw_slots outside 0..64, or a
+ * dev_buf smaller than ea_footprint(). */
+ea_status ea_create(int32_t L, double p, double T, uint64_t seed, ea_sim **out);
+ea_status ea_create_ex(const ea_config *cfg, ea_sim **out);
+void ea_destroy(ea_sim *sim);
+
+/* Advance both replicas by n sweeps (t += n); asynchronous.  EA_ERR_ARG if
+ * t + n would reach 2^32 (the sweep index is one counter word). */
+ea_status ea_sweep(ea_sim *sim, uint64_t n);
+
+/* Store the current spins as reference S(t_w) in slot k, t_w = t. */
+ea_status ea_snapshot(ea_sim *sim, int32_t slot);
+
+/* Measure the observables at the current time (synchronises). */
+ea_status ea_measure(ea_sim *sim, ea_obs *out);
+
+ea_status ea_time(const ea_sim *sim, uint64_t *t);
+/* Set the sweep counter (resume from a checkpoint taken at time t). */
+ea_status ea_set_time(ea_sim *sim, uint64_t t);
+ea_status ea_sync(ea_sim *sim);
+
+/* Spins of replica r (0 or 1) as int8 +-1 [N], and couplings [3N]. */
+ea_status ea_get_spins(ea_sim *sim, int32_t r, int8_t *pm1);
+ea_status ea_set_spins(ea_sim *sim, int32_t r, const int8_t *pm1);
+ea_status ea_get_bonds(ea_sim *sim, int8_t *pm1);
+ea_status ea_set_bonds(ea_sim *sim, const int8_t *pm1);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

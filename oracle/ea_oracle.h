@@ -62,7 +62,8 @@ typedef struct eao_sim eao_sim;
  *   unsat[r]      number of unsatisfied bonds of replica r; E_r = 2 unsat - 3N
  *   mag[r]        sum_s S_r(s)
  *   overlap       sum_s S_0(s) S_1(s)                         (eq. 2, times N)
- *   autocorr[r*n_slots + k]  sum_s S_r(s,t) S_r(s,tw_k)        (eq. 7, times N)
+ *   autocorr[r*n_slots + k]  sum_s S_r(s,t) S_r(s,tw_k)        (eq. 7, times N);
+ *                            0 for a slot that was never taken
  *   c4[d*(L/2+1) + rho]      sum_s q(s) q(s + rho e_d), q = S_0 S_1 (eq. 3, times N)
  * The caller owns the arrays (autocorr: 2*n_slots, c4: 3*(L/2+1)). */
 typedef struct {

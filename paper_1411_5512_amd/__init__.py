@@ -1,0 +1,169 @@
+"""MI355X (gfx950) checkerboard Metropolis ageing simulations of the 3D +-J
+Edwards-Anderson model (Manssen & Hartmann, arXiv:1411.5512).
+
+Python face of the C ABI in ``include/ea.h``: :class:`Sim` wraps one run (a
+coupling sample with two replicas).  PyTorch, when importable with a GPU,
+supplies the stream the library enqueues on and the device buffer it carves
+its arrays from; all simulation work runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import abi
+from .abi import EAError
+
+__all__ = ["Sim", "EAError", "thresholds", "footprint", "version"]
+
+
+def version() -> str:
+    return abi.lib().ea_version().decode()
+
+
+def thresholds(T: float) -> np.ndarray:
+    out = np.zeros(3, dtype=np.uint32)
+    abi.check(abi.lib().ea_thresholds(float(T), abi.ptr(out, ctypes.c_uint32)))
+    return out
+
+
+def footprint(L: int, n_tw: int = 0) -> int:
+    out = ctypes.c_size_t(0)
+    abi.check(abi.lib().ea_footprint(int(L), int(n_tw), ctypes.byref(out)))
+    return int(out.value)
+
+
+def _torch_stream_and_buffer(nbytes: int, use_torch: bool):
+    if not use_torch:
+        return None, None
+    try:
+        import torch
+    except ImportError:
+        return None, None
+    if not torch.cuda.is_available():
+        return None, None
+    stream = torch.cuda.current_stream()
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    return stream, buf
+
+
+class Obs:
+    """Integer observables of one measurement (see ``ea_obs`` in ea.h)."""
+
+    __slots__ = ("t", "unsat", "mag", "overlap", "tw", "autocorr", "c4")
+
+    def __init__(self, t, unsat, mag, overlap, tw, autocorr, c4):
+        self.t, self.unsat, self.mag, self.overlap = t, unsat, mag, overlap
+        self.tw, self.autocorr, self.c4 = tw, autocorr, c4
+
+    def energy_per_spin(self, N: int) -> np.ndarray:
+        return (2 * self.unsat - 3 * N) / N
+
+
+class Sim:
+    """One run: L^3 lattice, couplings with P(J=-1) = p, two replicas at T."""
+
+    def __init__(self, L: int, p: float, T: float, seed: int, sample: int = 0,
+                 n_slots: int = 0, use_torch: bool = True):
+        self.L, self.p, self.T = int(L), float(p), float(T)
+        self.seed, self.sample, self.n_slots = int(seed), int(sample), int(n_slots)
+        self.N = self.L ** 3
+        self._h = None
+        cfg = abi.Config()
+        cfg.L, cfg.p, cfg.T = self.L, self.p, self.T
+        cfg.seed, cfg.sample, cfg.n_tw_slots = self.seed, self.sample, self.n_slots
+        need = footprint(self.L, self.n_slots) if 8 <= self.L <= 256 and self.L % 8 == 0 \
+            and 0 <= self.n_slots <= 64 else 0
+        self._stream, self._buf = _torch_stream_and_buffer(need, use_torch and need > 0)
+        if self._stream is not None:
+            cfg.stream = ctypes.c_void_p(self._stream.cuda_stream)
+            base = self._buf.data_ptr()
+            aligned = (base + 255) & ~255
+            cfg.dev_buf = ctypes.c_void_p(aligned)
+            cfg.dev_buf_bytes = need
+        h = ctypes.c_void_p()
+        abi.check(abi.lib().ea_create_ex(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+
+    # -- lifetime -------------------------------------------------------
+    def close(self):
+        if self._h is not None and self._h.value:
+            abi.lib().ea_destroy(self._h)
+        self._h = None
+        self._buf = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- dynamics -------------------------------------------------------
+    @property
+    def stream(self):
+        return self._stream
+
+    @property
+    def time(self) -> int:
+        t = ctypes.c_uint64(0)
+        abi.check(abi.lib().ea_time(self._h, ctypes.byref(t)))
+        return int(t.value)
+
+    def set_time(self, t: int):
+        abi.check(abi.lib().ea_set_time(self._h, int(t)))
+
+    def sweep(self, n: int = 1):
+        abi.check(abi.lib().ea_sweep(self._h, int(n)))
+
+    def snapshot(self, slot: int):
+        abi.check(abi.lib().ea_snapshot(self._h, int(slot)))
+
+    def sync(self):
+        abi.check(abi.lib().ea_sync(self._h))
+
+    def measure(self, c4: bool = True, autocorr: bool = True) -> Obs:
+        o = abi.Obs()
+        tw = np.zeros(max(self.n_slots, 1), dtype=np.uint64)
+        ac = np.zeros((2, max(self.n_slots, 1)), dtype=np.int64)
+        c4a = np.zeros((3, self.L // 2 + 1), dtype=np.int64)
+        if autocorr and self.n_slots > 0:
+            o.n_tw = self.n_slots
+            o.tw = abi.ptr(tw, ctypes.c_uint64)
+            o.autocorr = abi.ptr(ac, ctypes.c_int64)
+        if c4:
+            o.rmax = self.L // 2
+            o.c4 = abi.ptr(c4a, ctypes.c_int64)
+        abi.check(abi.lib().ea_measure(self._h, ctypes.byref(o)))
+        ns = self.n_slots
+        return Obs(int(o.t), np.array(o.unsat[:], dtype=np.int64), np.array(o.mag[:], dtype=np.int64),
+                   int(o.overlap), tw[:ns].copy(), ac[:, :ns].copy(), c4a if c4 else None)
+
+    # -- state ------------------------------------------------------------
+    def spins(self, r: int) -> np.ndarray:
+        out = np.zeros(self.N, dtype=np.int8)
+        abi.check(abi.lib().ea_get_spins(self._h, int(r), abi.ptr(out, ctypes.c_int8)))
+        return out
+
+    def set_spins(self, r: int, S):
+        S = np.ascontiguousarray(S, dtype=np.int8)
+        if S.size != self.N:
+            raise ValueError("wrong spin count")
+        abi.check(abi.lib().ea_set_spins(self._h, int(r), abi.ptr(S, ctypes.c_int8)))
+
+    def bonds(self) -> np.ndarray:
+        out = np.zeros(3 * self.N, dtype=np.int8)
+        abi.check(abi.lib().ea_get_bonds(self._h, abi.ptr(out, ctypes.c_int8)))
+        return out
+
+    def set_bonds(self, J):
+        J = np.ascontiguousarray(J, dtype=np.int8)
+        if J.size != 3 * self.N:
+            raise ValueError("wrong coupling count")
+        abi.check(abi.lib().ea_set_bonds(self._h, abi.ptr(J, ctypes.c_int8)))

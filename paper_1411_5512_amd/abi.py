@@ -1,0 +1,107 @@
+"""ctypes binding of the C ABI in include/ea.h (argument marshalling only).
+
+Every step of the simulation runs in the gfx950 library ``libea.so``; this
+module loads it, declares the signatures and converts between numpy arrays and
+pointers.  There is no fallback: if the library is missing or cannot be
+loaded, :func:`lib` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libea.so")
+
+EA_OK, EA_ERR_ARG, EA_ERR_NOMEM, EA_ERR_DEVICE, EA_ERR_STATE, EA_ERR_BUSY = 0, -1, -2, -3, -4, -5
+
+
+class EAError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"ea status {status}: {message}")
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_int32),
+        ("p", ctypes.c_double),
+        ("T", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("sample", ctypes.c_uint32),
+        ("n_tw_slots", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
+        ("dev_buf", ctypes.c_void_p),
+        ("dev_buf_bytes", ctypes.c_size_t),
+    ]
+
+
+class Obs(ctypes.Structure):
+    _fields_ = [
+        ("t", ctypes.c_uint64),
+        ("unsat", ctypes.c_int64 * 2),
+        ("mag", ctypes.c_int64 * 2),
+        ("overlap", ctypes.c_int64),
+        ("n_tw", ctypes.c_int32),
+        ("tw", ctypes.POINTER(ctypes.c_uint64)),
+        ("autocorr", ctypes.POINTER(ctypes.c_int64)),
+        ("rmax", ctypes.c_int32),
+        ("c4", ctypes.POINTER(ctypes.c_int64)),
+    ]
+
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "ea_last_error": (ctypes.c_char_p, []),
+    "ea_version": (ctypes.c_char_p, []),
+    "ea_footprint": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    "ea_thresholds": (ctypes.c_int, [ctypes.c_double, ctypes.POINTER(ctypes.c_uint32)]),
+    "ea_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
+                                 ctypes.POINTER(ctypes.c_void_p)]),
+    "ea_create_ex": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_void_p)]),
+    "ea_destroy": (None, [ctypes.c_void_p]),
+    "ea_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "ea_snapshot": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "ea_measure": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Obs)]),
+    "ea_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
+    "ea_set_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "ea_sync": (ctypes.c_int, [ctypes.c_void_p]),
+    "ea_get_spins": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int8)]),
+    "ea_set_spins": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int8)]),
+    "ea_get_bonds": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int8)]),
+    "ea_set_bonds": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int8)]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libea.so (raises if it is missing: there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                              "python paper_1411_5512_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status: int):
+    if status != EA_OK:
+        msg = lib().ea_last_error().decode(errors="replace")
+        raise EAError(status, msg)
+
+
+def ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def exported_names():
+    return list(_SIGS)

@@ -1,0 +1,472 @@
+// ea_api.hip -- host side of the C ABI declared in include/ea.h: argument
+// checks, device memory, layout conversion and kernel dispatch for the plain
+// form (one launch per checkerboard half-step).
+#include "ea.h"
+#include "ea_kernels.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ea_status fail(ea_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define EA_HIP(call)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(EA_ERR_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kMaxSlots = 64;
+constexpr int kMaxL = 256;
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Words per row: the fewest words of at most 32 bits such that every word
+// holds a whole number of 4-site random-word blocks.
+int words_per_row(int R)
+{
+    int rw = (R + 31) / 32;
+    while ((R / 4) % rw != 0) ++rw;
+    return rw;
+}
+
+struct Layout {
+    int L, R, RW, W, rows, plane;
+    size_t spin_words, bond_words, snap_words, meas_count;
+    size_t off_spins, off_bonds, off_snaps, off_meas, total;
+};
+
+Layout make_layout(int L, int n_slots)
+{
+    Layout y{};
+    y.L = L;
+    y.R = L / 2;
+    y.RW = words_per_row(y.R);
+    y.W = y.R / y.RW;
+    y.rows = L * L;
+    y.plane = y.rows * y.RW;
+    y.spin_words = 4 * (size_t)y.plane;
+    y.bond_words = 6 * (size_t)y.plane;
+    y.snap_words = (size_t)n_slots * y.spin_words;
+    y.meas_count = ea::M_AUTO + 2 * (size_t)kMaxSlots + 3 * (size_t)(y.R + 1);
+    y.off_spins = 0;
+    y.off_bonds = align256(y.off_spins + 4 * y.spin_words);
+    y.off_snaps = align256(y.off_bonds + 4 * y.bond_words);
+    y.off_meas = align256(y.off_snaps + 4 * y.snap_words);
+    y.total = align256(y.off_meas + 8 * y.meas_count);
+    return y;
+}
+
+bool valid_L(int L) { return L >= 8 && L <= kMaxL && L % 8 == 0; }
+
+}  // namespace
+
+struct ea_sim {
+    Layout lay;
+    double p = 0, T = 0;
+    uint64_t seed = 0;
+    uint32_t sample = 0;
+    int n_slots = 0;
+    uint32_t thr[3] = {0, 0, 0};
+    uint64_t pcut = 0;
+    uint64_t t = 0;
+    std::vector<uint64_t> snap_t;
+    std::vector<char> snap_taken;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    char *buf = nullptr;
+    bool own_buf = false;
+    ea::Lattice lat{};
+    uint32_t *snaps = nullptr;
+    unsigned long long *meas = nullptr;
+    std::vector<unsigned long long> host_meas;
+
+    ea::Geom geom() const
+    {
+        ea::Geom g;
+        g.L = lay.L;
+        g.R = lay.R;
+        g.RW = lay.RW;
+        g.rows = lay.rows;
+        g.plane = lay.plane;
+        return g;
+    }
+};
+
+namespace {
+
+uint32_t key_lo(const ea_sim *s) { return (uint32_t)(s->seed & 0xffffffffu); }
+uint32_t key_hi(const ea_sim *s) { return (uint32_t)(s->seed >> 32); }
+
+unsigned blocks_for(size_t n, unsigned bs = 256) { return (unsigned)((n + bs - 1) / bs); }
+
+// Dispatch a runtime word width to the kernel template instantiated for it.
+#define EA_DISPATCH_W(W, ...)                                             \
+    switch (W) {                                                          \
+    case 4: { constexpr int WW = 4; __VA_ARGS__; } break;                 \
+    case 8: { constexpr int WW = 8; __VA_ARGS__; } break;                 \
+    case 12: { constexpr int WW = 12; __VA_ARGS__; } break;               \
+    case 16: { constexpr int WW = 16; __VA_ARGS__; } break;               \
+    case 20: { constexpr int WW = 20; __VA_ARGS__; } break;               \
+    case 24: { constexpr int WW = 24; __VA_ARGS__; } break;               \
+    case 28: { constexpr int WW = 28; __VA_ARGS__; } break;               \
+    case 32: { constexpr int WW = 32; __VA_ARGS__; } break;               \
+    default: return fail(EA_ERR_STATE, "unsupported word width %d", W);  \
+    }
+
+ea_status launch_init(ea_sim *s)
+{
+    ea::Geom g = s->geom();
+    dim3 grid(blocks_for(g.plane), 5, 2);
+    EA_DISPATCH_W(s->lay.W, hipLaunchKernelGGL((ea::init_kernel<WW>), grid, dim3(256), 0, s->stream,
+                                                s->lat, g, key_lo(s), key_hi(s), s->sample, s->pcut));
+    EA_HIP(hipGetLastError());
+    return EA_OK;
+}
+
+ea_status launch_half_step(ea_sim *s, int half, uint32_t t)
+{
+    ea::Geom g = s->geom();
+    dim3 grid(blocks_for(g.plane), 2, 1);
+    EA_DISPATCH_W(s->lay.W,
+                  hipLaunchKernelGGL((ea::half_step_kernel<WW>), grid, dim3(256), 0, s->stream, s->lat, g,
+                                      half, t, key_lo(s), key_hi(s), s->sample, s->thr[0], s->thr[1],
+                                      s->thr[2]));
+    return EA_OK;
+}
+
+void host_thresholds(double T, uint32_t out[3])
+{
+    for (int k = 1; k <= 3; ++k) {
+        if (!(T > 0.0)) {
+            out[k - 1] = 0;
+            continue;
+        }
+        const double v = std::floor(std::exp(-4.0 * k / T) * 4294967296.0);
+        out[k - 1] = v >= 4294967295.0 ? 0xffffffffu : (uint32_t)v;
+    }
+}
+
+// Host-side conversion between canonical int8 +-1 arrays and packed planes.
+struct SiteAddr {
+    int c;
+    size_t word;
+    int bit;
+};
+
+SiteAddr address_of(const Layout &y, int64_t s)
+{
+    const int L = y.L;
+    const int x = (int)(s % L), yy = (int)((s / L) % L), z = (int)(s / ((int64_t)L * L));
+    SiteAddr a;
+    a.c = (x + yy + z) & 1;
+    const int xh = x >> 1;
+    const int row = yy + L * z;
+    a.word = (size_t)row * y.RW + (size_t)(xh / y.W);
+    a.bit = xh % y.W;
+    return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ea_last_error(void) { return g_last_error.c_str(); }
+
+const char *ea_version(void) { return "ea-mi355x 0.1 (gfx950)"; }
+
+ea_status ea_footprint(int32_t L, int32_t n_tw, size_t *bytes)
+{
+    if (!bytes) return fail(EA_ERR_ARG, "bytes is NULL");
+    if (!valid_L(L)) return fail(EA_ERR_ARG, "L=%d must be a multiple of 8 in [8, %d]", L, kMaxL);
+    if (n_tw < 0 || n_tw > kMaxSlots) return fail(EA_ERR_ARG, "n_tw=%d outside [0, %d]", n_tw, kMaxSlots);
+    *bytes = make_layout(L, n_tw).total;
+    return EA_OK;
+}
+
+ea_status ea_thresholds(double T, uint32_t out[3])
+{
+    if (!out) return fail(EA_ERR_ARG, "out is NULL");
+    if (!(T >= 0.0) || !std::isfinite(T)) return fail(EA_ERR_ARG, "T=%g must be finite and >= 0", T);
+    host_thresholds(T, out);
+    return EA_OK;
+}
+
+ea_status ea_create(int32_t L, double p, double T, uint64_t seed, ea_sim **out)
+{
+    ea_config cfg{};
+    cfg.L = L;
+    cfg.p = p;
+    cfg.T = T;
+    cfg.seed = seed;
+    return ea_create_ex(&cfg, out);
+}
+
+ea_status ea_create_ex(const ea_config *cfg, ea_sim **out)
+{
+    if (!cfg || !out) return fail(EA_ERR_ARG, "NULL argument");
+    *out = nullptr;
+    if (!valid_L(cfg->L)) return fail(EA_ERR_ARG, "L=%d must be a multiple of 8 in [8, %d]", cfg->L, kMaxL);
+    if (!(cfg->p >= 0.0 && cfg->p <= 1.0)) return fail(EA_ERR_ARG, "p=%g outside [0, 1]", cfg->p);
+    if (!(cfg->T >= 0.0) || !std::isfinite(cfg->T))
+        return fail(EA_ERR_ARG, "T=%g must be finite and >= 0", cfg->T);
+    if (cfg->n_tw_slots < 0 || cfg->n_tw_slots > kMaxSlots)
+        return fail(EA_ERR_ARG, "n_tw_slots=%d outside [0, %d]", cfg->n_tw_slots, kMaxSlots);
+
+    Layout lay = make_layout(cfg->L, cfg->n_tw_slots);
+    if (cfg->dev_buf) {
+        if (cfg->dev_buf_bytes < lay.total)
+            return fail(EA_ERR_ARG, "dev_buf holds %zu bytes, %zu needed", cfg->dev_buf_bytes, lay.total);
+        if (((uintptr_t)cfg->dev_buf & 255) != 0) return fail(EA_ERR_ARG, "dev_buf is not 256-byte aligned");
+    }
+
+    ea_sim *s = new (std::nothrow) ea_sim();
+    if (!s) return fail(EA_ERR_NOMEM, "host allocation failed");
+    s->lay = lay;
+    s->p = cfg->p;
+    s->T = cfg->T;
+    s->seed = cfg->seed;
+    s->sample = cfg->sample;
+    s->n_slots = cfg->n_tw_slots;
+    s->snap_t.assign((size_t)s->n_slots, 0);
+    s->snap_taken.assign((size_t)s->n_slots, 0);
+    s->host_meas.assign(lay.meas_count, 0);
+    host_thresholds(cfg->T, s->thr);
+    s->pcut = (uint64_t)std::floor(std::ldexp(cfg->p, 32));
+
+    hipError_t e;
+    if (cfg->stream) {
+        s->stream = (hipStream_t)cfg->stream;
+    } else {
+        e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete s;
+            return fail(EA_ERR_DEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+        }
+        s->own_stream = true;
+    }
+    if (cfg->dev_buf) {
+        s->buf = (char *)cfg->dev_buf;
+    } else {
+        e = hipMalloc((void **)&s->buf, lay.total);
+        if (e != hipSuccess) {
+            ea_destroy(s);
+            return fail(EA_ERR_NOMEM, "hipMalloc(%zu): %s", lay.total, hipGetErrorString(e));
+        }
+        s->own_buf = true;
+    }
+    s->lat.spins = (uint32_t *)(s->buf + lay.off_spins);
+    s->lat.bonds = (uint32_t *)(s->buf + lay.off_bonds);
+    s->snaps = (uint32_t *)(s->buf + lay.off_snaps);
+    s->meas = (unsigned long long *)(s->buf + lay.off_meas);
+
+    ea_status st = launch_init(s);
+    if (st != EA_OK) {
+        ea_destroy(s);
+        return st;
+    }
+    if (s->n_slots > 0) {
+        hipLaunchKernelGGL(ea::zero_u64_kernel, dim3(blocks_for(lay.snap_words / 2)), dim3(256), 0, s->stream,
+                           (unsigned long long *)s->snaps, lay.snap_words / 2);
+    }
+    *out = s;
+    return EA_OK;
+}
+
+void ea_destroy(ea_sim *s)
+{
+    if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    if (s->own_buf && s->buf) (void)hipFree(s->buf);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+ea_status ea_sweep(ea_sim *s, uint64_t n)
+{
+    if (!s) return fail(EA_ERR_ARG, "sim is NULL");
+    if (s->t + n >= (1ull << 32) || n >= (1ull << 32))
+        return fail(EA_ERR_ARG, "t + n = %llu would reach 2^32", (unsigned long long)(s->t + n));
+    for (uint64_t i = 0; i < n; ++i) {
+        const uint32_t t = (uint32_t)(s->t + i);
+        ea_status st = launch_half_step(s, 0, t);
+        if (st != EA_OK) return st;
+        st = launch_half_step(s, 1, t);
+        if (st != EA_OK) return st;
+    }
+    EA_HIP(hipGetLastError());
+    s->t += n;
+    return EA_OK;
+}
+
+ea_status ea_snapshot(ea_sim *s, int32_t slot)
+{
+    if (!s) return fail(EA_ERR_ARG, "sim is NULL");
+    if (slot < 0 || slot >= s->n_slots) return fail(EA_ERR_ARG, "slot %d outside [0, %d)", slot, s->n_slots);
+    const size_t n = s->lay.spin_words;
+    hipLaunchKernelGGL(ea::copy_words_kernel, dim3(blocks_for(n)), dim3(256), 0, s->stream,
+                       s->snaps + (size_t)slot * n, s->lat.spins, n);
+    EA_HIP(hipGetLastError());
+    s->snap_t[(size_t)slot] = s->t;
+    s->snap_taken[(size_t)slot] = 1;
+    return EA_OK;
+}
+
+ea_status ea_measure(ea_sim *s, ea_obs *out)
+{
+    if (!s || !out) return fail(EA_ERR_ARG, "NULL argument");
+    const Layout &y = s->lay;
+    if (out->autocorr && out->n_tw != s->n_slots)
+        return fail(EA_ERR_ARG, "n_tw=%d but the run has %d slots", out->n_tw, s->n_slots);
+    if (out->c4 && out->rmax != y.R) return fail(EA_ERR_ARG, "rmax=%d but L/2=%d", out->rmax, y.R);
+    ea::Geom g = s->geom();
+    const size_t c4_base = ea::M_AUTO + 2 * (size_t)kMaxSlots;
+    const size_t n_count = c4_base + 3 * (size_t)(y.R + 1);
+    hipLaunchKernelGGL(ea::zero_u64_kernel, dim3(blocks_for(n_count)), dim3(256), 0, s->stream, s->meas, n_count);
+    const int slots = out->autocorr ? s->n_slots : 0;
+    EA_DISPATCH_W(y.W, hipLaunchKernelGGL((ea::measure_kernel<WW>), dim3(blocks_for(2 * (size_t)g.plane)),
+                                           dim3(256), 0, s->stream, s->lat, g, s->snaps, slots, s->meas));
+    if (out->c4) {
+        dim3 grid(blocks_for(2 * (size_t)g.rows), 3 * (unsigned)(y.R + 1), 1);
+        EA_DISPATCH_W(y.W, hipLaunchKernelGGL((ea::c4_kernel<WW>), grid, dim3(256), 0, s->stream,
+                                               s->lat, g, s->meas + c4_base));
+    }
+    EA_HIP(hipGetLastError());
+    EA_HIP(hipMemcpyAsync(s->host_meas.data(), s->meas, n_count * sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, s->stream));
+    EA_HIP(hipStreamSynchronize(s->stream));
+
+    const int64_t N = (int64_t)y.L * y.L * y.L;
+    const unsigned long long *m = s->host_meas.data();
+    out->t = s->t;
+    for (int r = 0; r < 2; ++r) {
+        out->unsat[r] = (int64_t)m[ea::M_UNSAT + r];
+        out->mag[r] = N - 2 * (int64_t)m[ea::M_DOWN + r];
+    }
+    out->overlap = N - 2 * (int64_t)m[ea::M_QDIFF];
+    if (out->autocorr) {
+        for (int r = 0; r < 2; ++r)
+            for (int k = 0; k < s->n_slots; ++k)
+                out->autocorr[r * s->n_slots + k] =
+                    s->snap_taken[(size_t)k] ? N - 2 * (int64_t)m[ea::M_AUTO + 2 * k + r] : 0;
+        if (out->tw)
+            for (int k = 0; k < s->n_slots; ++k) out->tw[k] = s->snap_t[(size_t)k];
+    }
+    if (out->c4)
+        for (int i = 0; i < 3 * (y.R + 1); ++i) out->c4[i] = N - 2 * (int64_t)m[c4_base + i];
+    return EA_OK;
+}
+
+ea_status ea_time(const ea_sim *s, uint64_t *t)
+{
+    if (!s || !t) return fail(EA_ERR_ARG, "NULL argument");
+    *t = s->t;
+    return EA_OK;
+}
+
+ea_status ea_set_time(ea_sim *s, uint64_t t)
+{
+    if (!s) return fail(EA_ERR_ARG, "sim is NULL");
+    if (t >= (1ull << 32)) return fail(EA_ERR_ARG, "t=%llu must be below 2^32", (unsigned long long)t);
+    s->t = t;
+    return EA_OK;
+}
+
+ea_status ea_sync(ea_sim *s)
+{
+    if (!s) return fail(EA_ERR_ARG, "sim is NULL");
+    EA_HIP(hipStreamSynchronize(s->stream));
+    return EA_OK;
+}
+
+ea_status ea_get_spins(ea_sim *s, int32_t r, int8_t *pm1)
+{
+    if (!s || !pm1) return fail(EA_ERR_ARG, "NULL argument");
+    if (r < 0 || r > 1) return fail(EA_ERR_ARG, "replica %d not 0 or 1", r);
+    const Layout &y = s->lay;
+    std::vector<uint32_t> words(2 * (size_t)y.plane);
+    EA_HIP(hipMemcpyAsync(words.data(), s->lat.spins + (size_t)r * 2 * y.plane, words.size() * 4,
+                          hipMemcpyDeviceToHost, s->stream));
+    EA_HIP(hipStreamSynchronize(s->stream));
+    const int64_t N = (int64_t)y.L * y.L * y.L;
+    for (int64_t i = 0; i < N; ++i) {
+        SiteAddr a = address_of(y, i);
+        const uint32_t bit = (words[(size_t)a.c * y.plane + a.word] >> a.bit) & 1u;
+        pm1[i] = bit ? (int8_t)-1 : (int8_t)1;
+    }
+    return EA_OK;
+}
+
+ea_status ea_set_spins(ea_sim *s, int32_t r, const int8_t *pm1)
+{
+    if (!s || !pm1) return fail(EA_ERR_ARG, "NULL argument");
+    if (r < 0 || r > 1) return fail(EA_ERR_ARG, "replica %d not 0 or 1", r);
+    const Layout &y = s->lay;
+    const int64_t N = (int64_t)y.L * y.L * y.L;
+    std::vector<uint32_t> words(2 * (size_t)y.plane, 0u);
+    for (int64_t i = 0; i < N; ++i) {
+        if (pm1[i] != 1 && pm1[i] != -1) return fail(EA_ERR_ARG, "spin %lld is %d, not +-1", (long long)i, pm1[i]);
+        SiteAddr a = address_of(y, i);
+        if (pm1[i] == -1) words[(size_t)a.c * y.plane + a.word] |= 1u << a.bit;
+    }
+    EA_HIP(hipMemcpyAsync(s->lat.spins + (size_t)r * 2 * y.plane, words.data(), words.size() * 4,
+                          hipMemcpyHostToDevice, s->stream));
+    EA_HIP(hipStreamSynchronize(s->stream));
+    return EA_OK;
+}
+
+ea_status ea_get_bonds(ea_sim *s, int8_t *pm1)
+{
+    if (!s || !pm1) return fail(EA_ERR_ARG, "NULL argument");
+    const Layout &y = s->lay;
+    std::vector<uint32_t> words(y.bond_words);
+    EA_HIP(hipMemcpyAsync(words.data(), s->lat.bonds, words.size() * 4, hipMemcpyDeviceToHost, s->stream));
+    EA_HIP(hipStreamSynchronize(s->stream));
+    const int64_t N = (int64_t)y.L * y.L * y.L;
+    for (int64_t i = 0; i < N; ++i) {
+        SiteAddr a = address_of(y, i);
+        for (int d = 0; d < 3; ++d) {
+            const uint32_t bit = (words[((size_t)d * 2 + a.c) * y.plane + a.word] >> a.bit) & 1u;
+            pm1[3 * i + d] = bit ? (int8_t)-1 : (int8_t)1;
+        }
+    }
+    return EA_OK;
+}
+
+ea_status ea_set_bonds(ea_sim *s, const int8_t *pm1)
+{
+    if (!s || !pm1) return fail(EA_ERR_ARG, "NULL argument");
+    const Layout &y = s->lay;
+    const int64_t N = (int64_t)y.L * y.L * y.L;
+    std::vector<uint32_t> words(y.bond_words, 0u);
+    for (int64_t i = 0; i < N; ++i) {
+        SiteAddr a = address_of(y, i);
+        for (int d = 0; d < 3; ++d) {
+            const int8_t v = pm1[3 * i + d];
+            if (v != 1 && v != -1) return fail(EA_ERR_ARG, "coupling %lld is %d, not +-1", (long long)(3 * i + d), v);
+            if (v == -1) words[((size_t)d * 2 + a.c) * y.plane + a.word] |= 1u << a.bit;
+        }
+    }
+    EA_HIP(hipMemcpyAsync(s->lat.bonds, words.data(), words.size() * 4, hipMemcpyHostToDevice, s->stream));
+    EA_HIP(hipStreamSynchronize(s->stream));
+    return EA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,191 @@
+// ea_device.h -- device-side building blocks shared by the gfx950 kernels:
+// the counter-based random words, the packed lattice layout and the
+// bit-sliced Metropolis decision.
+//
+// Packed layout.  Each colour c of each replica is stored as L*L rows, one
+// per (y, z), row index y + L z.  A row holds the R = L/2 sites of colour c
+// with that (y, z), ordered by xh = x >> 1 (so x = 2 xh + ((y + z + c) & 1)),
+// split into RW words of W bits (R = W RW, W a multiple of 4, at most 32);
+// bit b of word w is the site xh = W w + b, and bits W..31 are zero.  Spins
+// carry 1 for S = -1, couplings 1 for J = -1; a site's three couplings to its
+// +x, +y, +z neighbours ("left/up" bonds, Sec. III) live in three planes
+// laid out like the spins of the site's colour.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ea {
+
+// ---------------------------------------------------------------------------
+// Counter-based random words: Philox4x32-10 (Salmon et al., SC'11).  The key
+// is the run's seed, the counter names what the words are for; see ea.h for
+// the keying.  Key and the upper counter words are wave-uniform, so the
+// compiler keeps them (and the first round's product of word 2) in SGPRs.
+
+struct Words4 {
+    uint32_t v[4];
+};
+
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+__device__ __forceinline__ Words4 philox10(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                           uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t m0 = (uint64_t)x0 * 0xD2511F53u;
+        const uint64_t m2 = (uint64_t)x2 * 0xCD9E8D57u;
+        const uint32_t y0 = xor3((uint32_t)(m2 >> 32), x1, k0);
+        const uint32_t y2 = xor3((uint32_t)(m0 >> 32), x3, k1);
+        x1 = (uint32_t)m2;
+        x3 = (uint32_t)m0;
+        x0 = y0;
+        x2 = y2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    Words4 r;
+    r.v[0] = x0;
+    r.v[1] = x1;
+    r.v[2] = x2;
+    r.v[3] = x3;
+    return r;
+}
+
+enum : uint32_t { TAG_METRO = 0u, TAG_BOND = 1u, TAG_INIT = 2u };
+
+__device__ __forceinline__ uint32_t counter_word2(uint32_t tag, uint32_t colour, uint32_t replica)
+{
+    return (tag << 8) | (colour << 1) | replica;
+}
+
+// ---------------------------------------------------------------------------
+// Packed-row helpers.
+
+template <int W>
+__device__ __forceinline__ constexpr uint32_t word_mask()
+{
+    return W >= 32 ? 0xffffffffu : ((1u << W) - 1u);
+}
+
+// Word w of a row shifted so that bit b holds site xh - 1 (periodic in R):
+// cur = word w, prev = word w-1 (mod RW).
+template <int W>
+__device__ __forceinline__ uint32_t take_minus1(uint32_t cur, uint32_t prev)
+{
+    return ((cur << 1) | (prev >> (W - 1))) & word_mask<W>();
+}
+
+// Word w of a row shifted so that bit b holds site xh + 1: next = word w+1.
+template <int W>
+__device__ __forceinline__ uint32_t take_plus1(uint32_t cur, uint32_t next)
+{
+    return (cur >> 1) | ((next & 1u) << (W - 1));
+}
+
+__device__ __forceinline__ int wrap(int v, int L)
+{
+    return v < 0 ? v + L : (v >= L ? v - L : v);
+}
+
+// ---------------------------------------------------------------------------
+// Bit-sliced Metropolis decision for W sites of one colour (eq. 9).
+//
+// a1..a6 hold, per site, whether each of its six bonds is unsatisfied
+// (J S_i S_j = -1).  With n unsatisfied bonds the flip costs dE = 12 - 4n:
+// n >= 3 always flips, n = 2, 1, 0 flip iff the site's word is below
+// thr1, thr2, thr3.  The counter is reduced with two full adders:
+// n = s + 2 (c0 + c1 + c2), so "any" = (c0|c1|c2) means n >= 2 and
+// "always" = maj(c0,c1,c2) | (any & s) means n >= 3.
+struct Decision {
+    uint32_t always;  // n >= 3
+    uint32_t any;     // n >= 2
+    uint32_t odd;     // n odd
+};
+
+__device__ __forceinline__ Decision classify(uint32_t a1, uint32_t a2, uint32_t a3, uint32_t a4,
+                                             uint32_t a5, uint32_t a6)
+{
+    const uint32_t s1 = xor3(a1, a2, a3);
+    const uint32_t c1 = (a1 & a2) | (a3 & (a1 | a2));
+    const uint32_t s2 = xor3(a4, a5, a6);
+    const uint32_t c2 = (a4 & a5) | (a6 & (a4 | a5));
+    const uint32_t s = s1 ^ s2;
+    const uint32_t c0 = s1 & s2;
+    const uint32_t any = c0 | c1 | c2;
+    const uint32_t two = (c0 & c1) | (c2 & (c0 | c1));
+    Decision d;
+    d.any = any;
+    d.odd = s;
+    d.always = two | (any & s);
+    return d;
+}
+
+// Per-site acceptance, branch-free and without lane masks (a compare that
+// writes VCC followed by a select that reads it costs wait states on gfx950).
+// For site bit I the threshold is picked with two sign-extended bit fields:
+// any -> thr1 (n = 2), else odd -> thr2 (n = 1), else thr3 (n = 0); sites
+// with n >= 3 are covered by the "always" mask.  The unsigned comparison
+// u < thr is the sign bit of (~u & thr) | ((~u | thr) & (u - thr)) (Hacker's
+// Delight, unsigned comparison predicates), and a funnel shift appends that
+// bit to the accept word, so sites are visited from the highest bit down.
+//
+// v_bitop3_b32 truth tables are indexed by (src0 << 2) | (src1 << 1) | src2.
+constexpr int kBitopSelect = 0xCA;   // src0 ? src1 : src2, bitwise
+constexpr int kBitopBelow = 0x8E;    // (~u & t) | ((~u | t) & d) for (u, t, d)
+
+template <int I>
+__device__ __forceinline__ uint32_t bit_as_mask(uint32_t word)
+{
+    // Written as an instruction so that the compiler does not rebuild it as
+    // a compare and a lane-mask select.
+    uint32_t m;
+    asm("v_bfe_i32 %0, %1, %2, 1" : "=v"(m) : "v"(word), "i"(I));
+    return m;
+}
+
+template <int I>
+__device__ __forceinline__ uint32_t accept_site(uint32_t accept, uint32_t u, const Decision &d,
+                                                uint32_t thr1, uint32_t thr2, uint32_t thr3)
+{
+    const uint32_t m_any = bit_as_mask<I>(d.any);
+    const uint32_t m_odd = bit_as_mask<I>(d.odd);
+    const uint32_t t = __builtin_amdgcn_bitop3_b32(m_any, thr1,
+                                                   __builtin_amdgcn_bitop3_b32(m_odd, thr2, thr3, kBitopSelect),
+                                                   kBitopSelect);
+    const uint32_t below = __builtin_amdgcn_bitop3_b32(u, t, u - t, kBitopBelow);
+    return __builtin_amdgcn_alignbit(accept, below, 31);
+}
+
+// Blocks J = W/4-1 down to 0: block J covers sites 4J..4J+3 and has counter
+// word 0 equal to quad0 + J.
+template <int J>
+__device__ __forceinline__ uint32_t accept_blocks(uint32_t accept, const Decision &d, uint32_t quad0,
+                                                  uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                                  uint32_t k1, uint32_t thr1, uint32_t thr2, uint32_t thr3)
+{
+    const Words4 u = philox10(quad0 + (uint32_t)J, c1, c2, c3, k0, k1);
+    accept = accept_site<4 * J + 3>(accept, u.v[3], d, thr1, thr2, thr3);
+    accept = accept_site<4 * J + 2>(accept, u.v[2], d, thr1, thr2, thr3);
+    accept = accept_site<4 * J + 1>(accept, u.v[1], d, thr1, thr2, thr3);
+    accept = accept_site<4 * J + 0>(accept, u.v[0], d, thr1, thr2, thr3);
+    if constexpr (J > 0)
+        return accept_blocks<J - 1>(accept, d, quad0, c1, c2, c3, k0, k1, thr1, thr2, thr3);
+    else
+        return accept;
+}
+
+// Flip mask of one packed word of W sites (bits W..31 stay zero).
+template <int W>
+__device__ __forceinline__ uint32_t flip_mask(const Decision &d, uint32_t quad0, uint32_t c1,
+                                              uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,
+                                              uint32_t thr1, uint32_t thr2, uint32_t thr3)
+{
+    return d.always | accept_blocks<W / 4 - 1>(0u, d, quad0, c1, c2, c3, k0, k1, thr1, thr2, thr3);
+}
+
+}  // namespace ea

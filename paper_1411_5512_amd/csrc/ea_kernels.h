@@ -1,0 +1,256 @@
+// ea_kernels.h -- gfx950 kernels of the plain form: initial state, one
+// checkerboard half-step per launch, snapshots and the measurement
+// reductions.  Layout and random words are described in ea_device.h.
+#pragma once
+
+#include "ea_device.h"
+
+namespace ea {
+
+// Geometry of one packed lattice, passed by value to every kernel.
+struct Geom {
+    int L;       // side length
+    int R;       // sites of one colour per row, L / 2
+    int RW;      // words per row
+    int rows;    // L * L
+    int plane;   // words per colour plane, rows * RW
+};
+
+// Device pointers of one run.
+struct Lattice {
+    uint32_t *spins;  // [replica 2][colour 2][plane]
+    uint32_t *bonds;  // [direction 3][colour 2][plane]
+};
+
+__device__ __forceinline__ size_t plane_off(const Geom &g, int a, int c)
+{
+    return ((size_t)a * 2 + (size_t)c) * (size_t)g.plane;
+}
+
+// --------------------------------------------------------------------------
+// Initial state (Sec. II): couplings with P(J = -1) = p and two replicas of
+// uniformly random spins.  One thread per (row, word) of one colour; grid.y
+// selects what is drawn: 0..2 the coupling planes of direction d, 3..4 the
+// spins of replica 0 / 1; grid.z the colour.
+template <int W>
+__global__ __launch_bounds__(256) void init_kernel(Lattice lat, Geom g, uint32_t k0, uint32_t k1,
+                                                   uint32_t sample, uint64_t pcut)
+{
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= g.plane) return;
+    const int what = blockIdx.y;
+    const int c = blockIdx.z;
+    const int row = tid / g.RW;
+    const int w = tid - row * g.RW;
+    const uint32_t quad0 = (uint32_t)((row * g.R + w * W) >> 2);
+    const bool is_bond = what < 3;
+    const uint32_t aux = is_bond ? (uint32_t)what : 0u;
+    const uint32_t rep = is_bond ? 0u : (uint32_t)(what - 3);
+    const uint32_t c2 = counter_word2(is_bond ? TAG_BOND : TAG_INIT, (uint32_t)c, rep);
+    uint32_t bits = 0;
+#pragma unroll
+    for (int j = 0; j < W / 4; ++j) {
+        const Words4 u = philox10(quad0 + (uint32_t)j, aux, c2, sample, k0, k1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t bit = is_bond ? (uint32_t)((uint64_t)u.v[q] < pcut) : (u.v[q] >> 31);
+            bits |= bit << (4 * j + q);
+        }
+    }
+    uint32_t *dst = is_bond ? lat.bonds + plane_off(g, what, c) : lat.spins + plane_off(g, what - 3, c);
+    dst[tid] = bits;
+}
+
+// --------------------------------------------------------------------------
+// One checkerboard half-step (Sec. III, eq. 9) of sweep t.  grid.y = replica
+// r, which updates colour c = r ^ half; all six neighbours of a colour-c site
+// have colour 1 - c, so every thread reads the other colour and writes only
+// its own word.  One thread per (row, word).
+template <int W>
+__global__ __launch_bounds__(256) void half_step_kernel(Lattice lat, Geom g, int half, uint32_t t,
+                                                        uint32_t k0, uint32_t k1, uint32_t sample,
+                                                        uint32_t thr1, uint32_t thr2, uint32_t thr3)
+{
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= g.plane) return;
+    const int r = blockIdx.y;
+    const int c = r ^ half;
+    const int row = tid / g.RW;
+    const int w = tid - row * g.RW;
+    const int y = row % g.L;
+    const int z = row / g.L;
+    const int par = (y + z + c) & 1;  // x = 2 xh + par on this row
+    const int wm = w == 0 ? g.RW - 1 : w - 1;
+    const int wp = w == g.RW - 1 ? 0 : w + 1;
+    const int row_ym = wrap(y - 1, g.L) + g.L * z, row_yp = wrap(y + 1, g.L) + g.L * z;
+    const int row_zm = y + g.L * wrap(z - 1, g.L), row_zp = y + g.L * wrap(z + 1, g.L);
+
+    uint32_t *own = lat.spins + plane_off(g, r, c);
+    const uint32_t *oth = lat.spins + plane_off(g, r, c ^ 1);
+    const uint32_t *bx_own = lat.bonds + plane_off(g, 0, c);
+    const uint32_t *by_own = lat.bonds + plane_off(g, 1, c);
+    const uint32_t *bz_own = lat.bonds + plane_off(g, 2, c);
+    const uint32_t *bx_oth = lat.bonds + plane_off(g, 0, c ^ 1);
+    const uint32_t *by_oth = lat.bonds + plane_off(g, 1, c ^ 1);
+    const uint32_t *bz_oth = lat.bonds + plane_off(g, 2, c ^ 1);
+
+    const int base = row * g.RW;
+    const uint32_t S = own[base + w];
+    const uint32_t O = oth[base + w], Om = oth[base + wm], Op = oth[base + wp];
+    const uint32_t Xo = bx_oth[base + w], Xom = bx_oth[base + wm];
+
+    // x neighbours: on even rows (par = 0) the +x neighbour shares xh and the
+    // -x neighbour sits at xh - 1; on odd rows the +x neighbour is at xh + 1
+    // and the -x neighbour shares xh.  The -x bond is stored at the -x site.
+    const uint32_t xp = par ? take_plus1<W>(O, Op) : O;
+    const uint32_t xm = par ? (O ^ Xo) : take_minus1<W>(O ^ Xo, Om ^ Xom);
+    const uint32_t a1 = S ^ xp ^ bx_own[base + w];
+    const uint32_t a2 = S ^ xm;
+    const uint32_t a3 = xor3(S, oth[row_yp * g.RW + w], by_own[base + w]);
+    const uint32_t a4 = xor3(S, oth[row_ym * g.RW + w], by_oth[row_ym * g.RW + w]);
+    const uint32_t a5 = xor3(S, oth[row_zp * g.RW + w], bz_own[base + w]);
+    const uint32_t a6 = xor3(S, oth[row_zm * g.RW + w], bz_oth[row_zm * g.RW + w]);
+
+    const Decision d = classify(a1, a2, a3, a4, a5, a6);
+    const uint32_t quad0 = (uint32_t)((row * g.R + w * W) >> 2);
+    const uint32_t flips = flip_mask<W>(d, quad0, t, counter_word2(TAG_METRO, (uint32_t)c, (uint32_t)r),
+                                        sample, k0, k1, thr1, thr2, thr3);
+    own[base + w] = S ^ flips;
+}
+
+// --------------------------------------------------------------------------
+// Reductions.  Sums are popcounts (number of set bits); the host turns them
+// into the +-1 sums of ea_obs.  Each wave reduces with cross-lane shuffles
+// and adds its total to a 64-bit counter (integer, so the result does not
+// depend on the order of the atomics).
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ void wave_add(unsigned long long *dst, uint32_t v)
+{
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(dst, (unsigned long long)v);
+}
+
+// Counter layout of one measurement (all uint64):
+//   [0,1] unsatisfied bonds of replica 0/1
+//   [2,3] spins with S = -1, replica 0/1
+//   [4]   sites with S_0 != S_1
+//   [5 + 2k + r] sites with S_r(t) != S_r(tw_k)
+// followed by the C4 block: [c4_base + d (R+1) + rho] sites with q(s) != q(s + rho e_d).
+enum { M_UNSAT = 0, M_DOWN = 2, M_QDIFF = 4, M_AUTO = 5 };
+
+// One thread per (colour, row, word) of the whole lattice: grid.x covers
+// 2 * plane threads.  snaps = [slot][replica][colour][plane].
+template <int W>
+__global__ __launch_bounds__(256) void measure_kernel(Lattice lat, Geom g, const uint32_t *snaps,
+                                                      int n_slots, unsigned long long *acc)
+{
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = gid < 2 * g.plane;
+    const int c = live ? gid / g.plane : 0;
+    const int tid = live ? gid - c * g.plane : 0;
+    const int row = tid / g.RW;
+    const int w = tid - row * g.RW;
+    const int y = row % g.L;
+    const int z = row / g.L;
+    const int par = (y + z + c) & 1;
+    const int wp = w == g.RW - 1 ? 0 : w + 1;
+    const int row_yp = wrap(y + 1, g.L) + g.L * z;
+    const int row_zp = y + g.L * wrap(z + 1, g.L);
+    const int base = row * g.RW;
+
+    uint32_t S[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const uint32_t *own = lat.spins + plane_off(g, r, c);
+        const uint32_t *oth = lat.spins + plane_off(g, r, c ^ 1);
+        S[r] = live ? own[base + w] : 0u;
+        uint32_t unsat = 0;
+        if (live) {
+            const uint32_t O = oth[base + w], Op = oth[base + wp];
+            const uint32_t xp = par ? take_plus1<W>(O, Op) : O;
+            unsat = __popc(S[r] ^ xp ^ lat.bonds[plane_off(g, 0, c) + base + w]) +
+                    __popc(xor3(S[r], oth[row_yp * g.RW + w], lat.bonds[plane_off(g, 1, c) + base + w])) +
+                    __popc(xor3(S[r], oth[row_zp * g.RW + w], lat.bonds[plane_off(g, 2, c) + base + w]));
+        }
+        wave_add(acc + M_UNSAT + r, unsat);
+        wave_add(acc + M_DOWN + r, __popc(S[r]));
+    }
+    wave_add(acc + M_QDIFF, __popc(S[0] ^ S[1]));
+    for (int k = 0; k < n_slots; ++k) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const uint32_t ref = live ? snaps[((size_t)k * 2 + r) * 2 * g.plane + plane_off(g, 0, c) + tid] : 0u;
+            wave_add(acc + M_AUTO + 2 * k + r, __popc(S[r] ^ ref));
+        }
+    }
+}
+
+// q = S_0 xor S_1 of word w of a packed row.
+__device__ __forceinline__ uint32_t q_word(const Lattice &lat, const Geom &g, int c, int row, int w)
+{
+    const size_t i = (size_t)row * g.RW + (size_t)w;
+    return lat.spins[plane_off(g, 0, c) + i] ^ lat.spins[plane_off(g, 1, c) + i];
+}
+
+// C4 block (eq. 3): grid.y = d (R+1) + rho, one thread per (colour, row).
+// The partner of site (x,y,z) is (x,y,z) + rho e_d, of colour c ^ (rho & 1).
+// Along y and z it sits at the same half index of the partner row; along x,
+// on a row with x = 2 xh + par, its half index is xh + rho/2 (rho even) or
+// xh + (rho-1)/2 + par (rho odd), modulo R.
+template <int W>
+__global__ __launch_bounds__(256) void c4_kernel(Lattice lat, Geom g, unsigned long long *acc)
+{
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = gid < 2 * g.rows;
+    const int d = blockIdx.y / (g.R + 1);
+    const int rho = blockIdx.y - d * (g.R + 1);
+    uint32_t diff = 0;
+    if (live) {
+        const int c = gid / g.rows;
+        const int row = gid - c * g.rows;
+        const int y = row % g.L;
+        const int z = row / g.L;
+        const int cp = c ^ (rho & 1);
+        if (d == 0) {
+            const int par = (y + z + c) & 1;
+            const int k = (rho & 1) ? (rho - 1) / 2 + par : rho / 2;
+            for (int w = 0; w < g.RW; ++w) {
+                const int start = (w * W + k) % g.R;
+                const int wi = start / W;
+                const int off = start - wi * W;
+                const uint32_t lo = q_word(lat, g, cp, row, wi);
+                const uint32_t hi = q_word(lat, g, cp, row, wi + 1 == g.RW ? 0 : wi + 1);
+                const uint32_t win = off == 0 ? lo : (((lo >> off) | (hi << (W - off))) & word_mask<W>());
+                diff += __popc(q_word(lat, g, c, row, w) ^ win);
+            }
+        } else {
+            const int prow = d == 1 ? (y + rho) % g.L + g.L * z : y + g.L * ((z + rho) % g.L);
+            for (int w = 0; w < g.RW; ++w)
+                diff += __popc(q_word(lat, g, c, row, w) ^ q_word(lat, g, cp, prow, w));
+        }
+    }
+    wave_add(acc + blockIdx.y, diff);
+}
+
+// Plain word copy (snapshots) and fill (clearing counters); kernels rather
+// than runtime memset/memcpy so that the same work can sit in a graph.
+__global__ __launch_bounds__(256) void copy_words_kernel(uint32_t *dst, const uint32_t *src, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(256) void zero_u64_kernel(unsigned long long *dst, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = 0ull;
+}
+
+}  // namespace ea

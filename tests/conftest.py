@@ -18,3 +18,21 @@ def oracle_mod():
     import oracle
     oracle.build()
     return oracle
+
+
+def _gpu_available():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+@pytest.fixture(scope="session")
+def ea_gpu():
+    """The product package, on a machine with a GPU (the library must load)."""
+    if not _gpu_available():
+        pytest.skip("no GPU")
+    import paper_1411_5512_amd as ea
+    ea.abi.lib()  # raises if libea.so is missing: there is no fallback
+    return ea

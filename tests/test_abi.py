@@ -1,0 +1,65 @@
+"""Host-side checks of the C ABI that run without a GPU: the library loads,
+exports every function include/ea.h declares, and its host logic (argument
+checks, thresholds, footprints) behaves as documented."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "ea.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ea_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def ealib():
+    from paper_1411_5512_amd import abi
+    if not os.path.exists(abi.LIB_PATH):
+        pytest.skip("libea.so not built")
+    return abi
+
+
+def test_every_declared_symbol_is_exported(ealib):
+    names = _declared_functions()
+    assert len(names) >= 17
+    lib = ctypes.CDLL(ealib.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing
+    # the binding declares exactly the header's functions
+    assert sorted(ealib.exported_names()) == names
+
+
+def test_thresholds_match_oracle(ealib, oracle_mod):
+    import paper_1411_5512_amd as ea
+    for T in [0.0, 0.3, 0.5, 0.6, 0.7, 0.8, 1.0, 1.2, 4.5, 1e300]:
+        assert list(ea.thresholds(T)) == list(oracle_mod.thresholds(T))
+    with pytest.raises(ea.EAError):
+        ea.thresholds(-1.0)
+    with pytest.raises(ea.EAError):
+        ea.thresholds(float("nan"))
+
+
+def test_footprint_and_bad_arguments(ealib):
+    import paper_1411_5512_amd as ea
+    # bit-packed: 2 replicas x N bits of spins + 3N bits of couplings (plus padding)
+    for L in (16, 64, 128):
+        fp = ea.footprint(L)
+        assert 5 * L ** 3 // 8 <= fp < 5 * L ** 3 // 8 + 4096 + 8 * 2000
+    assert ea.footprint(64, 3) - ea.footprint(64, 0) >= 3 * 2 * 64 ** 3 // 8
+    for L in (0, 4, 12, 260, 264, -8):
+        with pytest.raises(ea.EAError):
+            ea.footprint(L)
+    with pytest.raises(ea.EAError):
+        ea.footprint(16, 65)
+    for args in [(12, 0.5, 0.8), (16, -0.1, 0.8), (16, 1.5, 0.8), (16, 0.5, -0.1),
+                 (16, 0.5, float("inf")), (16, float("nan"), 0.8)]:
+        h = ctypes.c_void_p()
+        st = ealib.lib().ea_create(args[0], args[1], args[2], 1, ctypes.byref(h))
+        assert st == ealib.EA_ERR_ARG and not h.value
+        assert ealib.lib().ea_last_error()

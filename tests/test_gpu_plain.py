@@ -1,0 +1,176 @@
+"""Parity of the plain GPU path (one launch per checkerboard half-step)
+against the CPU oracle: bit-exact couplings, spins and every integer
+observable, on the same seeds and schedules."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _compare_obs(go, oo, ctx):
+    assert go.t == oo.t, ctx
+    assert list(go.unsat) == list(oo.unsat), ctx
+    assert list(go.mag) == list(oo.mag), ctx
+    assert go.overlap == oo.overlap, ctx
+    if oo.autocorr.size:
+        assert np.array_equal(go.autocorr, oo.autocorr), ctx
+    if go.c4 is not None:
+        assert np.array_equal(go.c4, oo.c4), ctx
+
+
+def _compare_state(g, o, ctx):
+    for r in (0, 1):
+        gs, os_ = g.spins(r), o.spins(r)
+        if not np.array_equal(gs, os_):
+            bad = np.flatnonzero(gs != os_)
+            raise AssertionError(f"{ctx}: replica {r} differs at {bad.size} sites, first {bad[:8]}")
+
+
+# L values chosen to exercise every packed-row shape: W = L/2 for L <= 64
+# (one word per row), and multi-word rows for L = 72 (3 x 12), 88 (11 x 4),
+# 96 (2 x 24), 128 (2 x 32).
+@pytest.mark.parametrize("L", [8, 16, 24, 40, 48, 64, 72, 88, 96, 128])
+def test_initial_state_matches_oracle(ea_gpu, oracle_mod, L):
+    _say(f"init L={L}")
+    for p, seed, sample in [(0.5, 1, 0), (0.23, 77, 3)]:
+        g = ea_gpu.Sim(L, p, 0.8, seed=seed, sample=sample)
+        o = oracle_mod.Sim(L, p, 0.8, seed=seed, sample=sample)
+        assert np.array_equal(g.bonds(), o.bonds()), (L, p)
+        _compare_state(g, o, f"L={L} p={p} t=0")
+
+
+@pytest.mark.parametrize("L,p,T,sweeps", [
+    (8, 0.5, 0.8, 40), (16, 0.5, 0.8, 25), (24, 0.3, 0.6, 12), (32, 0.5, 1.0, 10),
+    (40, 0.2, 0.7, 6), (48, 0.5, 0.7, 6), (64, 0.25, 0.7, 4), (72, 0.5, 1.2, 3),
+    (88, 0.5, 0.5, 2), (96, 0.15, 0.7, 2), (128, 0.5, 0.7, 2),
+    (16, 0.0, 0.7, 20), (16, 1.0, 0.7, 20), (16, 0.5, 0.0, 20), (16, 0.5, 3.0, 20),
+])
+def test_sweeps_match_oracle(ea_gpu, oracle_mod, L, p, T, sweeps):
+    _say(f"sweeps L={L} p={p} T={T} n={sweeps}")
+    g = ea_gpu.Sim(L, p, T, seed=5, sample=1, n_slots=1)
+    o = oracle_mod.Sim(L, p, T, seed=5, sample=1, n_slots=1)
+    g.snapshot(0)
+    o.snapshot(0)
+    done = 0
+    for chunk in (1, sweeps - 1):
+        if chunk <= 0:
+            continue
+        g.sweep(chunk)
+        o.sweep(chunk)
+        done += chunk
+        _compare_state(g, o, f"L={L} p={p} T={T} t={done}")
+        _compare_obs(g.measure(), o.measure(), f"L={L} t={done}")
+
+
+def test_small_config_full_run(ea_gpu, oracle_mod):
+    """L = 16, p = 0.5, T = 0.8, 1000 sweeps; measure at 10, 100, 1000 with
+    t_w = 100 and C4 for r = 0..8 along the three axes."""
+    _say("config L=16 1000 sweeps")
+    L, p, T = 16, 0.5, 0.8
+    g = ea_gpu.Sim(L, p, T, seed=1, n_slots=1)
+    o = oracle_mod.Sim(L, p, T, seed=1, n_slots=1)
+    t = 0
+    for target in (10, 100, 1000):
+        g.sweep(target - t)
+        o.sweep(target - t)
+        t = target
+        if t == 100:
+            g.snapshot(0)
+            o.snapshot(0)
+        _compare_obs(g.measure(), o.measure(), f"t={t}")
+        _compare_state(g, o, f"t={t}")
+    go = g.measure()
+    assert go.c4.shape == (3, 9) and np.all(go.c4[:, 0] == L ** 3)
+
+
+def test_gauge_transformed_run_on_gpu(ea_gpu, oracle_mod):
+    """Couplings and spins set through the ABI: a random gauge transform of
+    the run gives the transformed trajectory (exact)."""
+    L, p, T = 24, 0.5, 0.7
+    N = L ** 3
+    rng = np.random.default_rng(3)
+    eps = rng.choice(np.array([-1, 1], dtype=np.int8), size=N)
+    s = np.arange(N)
+    x, y, z = s % L, (s // L) % L, s // (L * L)
+    nbs = [((x + 1) % L) + L * (y + L * z), x + L * (((y + 1) % L) + L * z),
+           x + L * (y + L * ((z + 1) % L))]
+    a = ea_gpu.Sim(L, p, T, seed=9)
+    b = ea_gpu.Sim(L, p, T, seed=9)
+    J = a.bonds().reshape(-1, 3)
+    Jg = np.stack([eps * J[:, d] * eps[nbs[d]] for d in range(3)], axis=1).astype(np.int8)
+    b.set_bonds(Jg.reshape(-1))
+    assert np.array_equal(b.bonds(), Jg.reshape(-1))
+    for r in (0, 1):
+        b.set_spins(r, eps * a.spins(r))
+    a.sweep(30)
+    b.sweep(30)
+    for r in (0, 1):
+        assert np.array_equal(b.spins(r), eps * a.spins(r))
+    oa, ob = a.measure(), b.measure()
+    assert list(oa.unsat) == list(ob.unsat) and oa.overlap == ob.overlap
+    assert np.array_equal(oa.c4, ob.c4)
+    # and the untransformed GPU run agrees with the oracle
+    o = oracle_mod.Sim(L, p, T, seed=9)
+    o.sweep(30)
+    for r in (0, 1):
+        assert np.array_equal(a.spins(r), o.spins(r))
+
+
+def test_windowed_parity_mid_size(ea_gpu, oracle_mod):
+    """L = 64, p = 0.5, T = 0.7: the oracle, started from the GPU state at
+    t0, reproduces the GPU state after a window of sweeps (the random words
+    are keyed by the absolute sweep index)."""
+    L, p, T = 64, 0.5, 0.7
+    g = ea_gpu.Sim(L, p, T, seed=1)
+    for t0, k in [(0, 3), (1000, 3), (20000, 2)]:
+        g.sweep(t0 - g.time)
+        o = oracle_mod.Sim(L, p, T, seed=1)
+        for r in (0, 1):
+            o.set_spins(r, g.spins(r))
+        o.set_time(t0)
+        g.sweep(k)
+        o.sweep(k)
+        _say(f"window L=64 t0={t0} k={k}")
+        _compare_state(g, o, f"window t0={t0}")
+        _compare_obs(g.measure(), o.measure(), f"window t0={t0}")
+
+
+def test_resume_and_determinism(ea_gpu):
+    L = 32
+    a = ea_gpu.Sim(L, 0.5, 0.8, seed=4)
+    b = ea_gpu.Sim(L, 0.5, 0.8, seed=4)
+    a.sweep(50)
+    b.sweep(20)
+    b.sweep(30)
+    for r in (0, 1):
+        assert np.array_equal(a.spins(r), b.spins(r))
+    c = ea_gpu.Sim(L, 0.5, 0.8, seed=4)
+    for r in (0, 1):
+        c.set_spins(r, a.spins(r))
+    c.set_time(50)
+    a.sweep(25)
+    c.sweep(25)
+    for r in (0, 1):
+        assert np.array_equal(a.spins(r), c.spins(r))
+
+
+def test_errors_on_gpu(ea_gpu):
+    g = ea_gpu.Sim(16, 0.5, 0.8, seed=1, n_slots=2)
+    with pytest.raises(ea_gpu.EAError):
+        g.snapshot(2)
+    with pytest.raises(ea_gpu.EAError):
+        g.snapshot(-1)
+    g.set_time((1 << 32) - 5)
+    with pytest.raises(ea_gpu.EAError):
+        g.sweep(5)
+    g.sweep(4)
+    assert g.time == (1 << 32) - 1
+    with pytest.raises(ea_gpu.EAError):
+        g.set_spins(0, np.zeros(16 ** 3, dtype=np.int8))
