@@ -123,6 +123,11 @@ ea_status ea_create(int32_t L, double p, double T, uint64_t seed, ea_sim **out);
 ea_status ea_create_ex(const ea_config *cfg, ea_sim **out);
 void ea_destroy(ea_sim *sim);
 
+/* Restart the run in place for another disorder sample: regenerate the
+ * couplings and both replicas' initial spins for (seed, sample), set t = 0
+ * and forget every snapshot; asynchronous, allocates nothing. */
+ea_status ea_reset(ea_sim *sim, uint64_t seed, uint32_t sample);
+
 /* Advance both replicas by n sweeps (t += n); asynchronous.  EA_ERR_ARG if
  * t + n would reach 2^32 (the sweep index is one counter word). */
 ea_status ea_sweep(ea_sim *sim, uint64_t n);

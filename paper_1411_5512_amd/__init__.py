@@ -43,8 +43,11 @@ def _torch_stream_and_buffer(nbytes: int, use_torch: bool):
         return None, None
     if not torch.cuda.is_available():
         return None, None
-    stream = torch.cuda.current_stream()
+    # a stream of its own (default priority): graphs cannot be captured on the
+    # legacy default stream, and timing events must sit on the run's stream
+    stream = torch.cuda.Stream()
     buf = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    torch.cuda.current_stream().synchronize()
     return stream, buf
 
 
@@ -118,6 +121,11 @@ class Sim:
 
     def set_time(self, t: int):
         abi.check(abi.lib().ea_set_time(self._h, int(t)))
+
+    def reset(self, seed: int, sample: int = 0):
+        """Restart in place for another sample (no allocation)."""
+        abi.check(abi.lib().ea_reset(self._h, int(seed), int(sample)))
+        self.seed, self.sample = int(seed), int(sample)
 
     def sweep(self, n: int = 1):
         abi.check(abi.lib().ea_sweep(self._h, int(n)))

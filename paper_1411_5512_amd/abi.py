@@ -62,6 +62,7 @@ _SIGS = {
                                  ctypes.POINTER(ctypes.c_void_p)]),
     "ea_create_ex": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_void_p)]),
     "ea_destroy": (None, [ctypes.c_void_p]),
+    "ea_reset": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32]),
     "ea_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
     "ea_snapshot": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "ea_measure": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Obs)]),

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -50,7 +51,7 @@ int words_per_row(int R)
 struct Layout {
     int L, R, RW, W, rows, plane;
     size_t spin_words, bond_words, snap_words, meas_count;
-    size_t off_spins, off_bonds, off_snaps, off_meas, total;
+    size_t off_spins, off_bonds, off_snaps, off_meas, off_ctl, total;
 };
 
 Layout make_layout(int L, int n_slots)
@@ -70,7 +71,8 @@ Layout make_layout(int L, int n_slots)
     y.off_bonds = align256(y.off_spins + 4 * y.spin_words);
     y.off_snaps = align256(y.off_bonds + 4 * y.bond_words);
     y.off_meas = align256(y.off_snaps + 4 * y.snap_words);
-    y.total = align256(y.off_meas + 8 * y.meas_count);
+    y.off_ctl = align256(y.off_meas + 8 * y.meas_count);
+    y.total = align256(y.off_ctl + 256);
     return y;
 }
 
@@ -96,7 +98,11 @@ struct ea_sim {
     ea::Lattice lat{};
     uint32_t *snaps = nullptr;
     unsigned long long *meas = nullptr;
+    uint32_t *t_dev = nullptr;  // device copy of the sweep counter base
     std::vector<unsigned long long> host_meas;
+    // captured graph of kGraphSweeps sweeps (built on first use)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
 
     ea::Geom geom() const
     {
@@ -141,14 +147,52 @@ ea_status launch_init(ea_sim *s)
     return EA_OK;
 }
 
-ea_status launch_half_step(ea_sim *s, int half, uint32_t t)
+ea_status launch_half_step(ea_sim *s, int half, uint32_t t_off)
 {
     ea::Geom g = s->geom();
     dim3 grid(blocks_for(g.plane), 2, 1);
     EA_DISPATCH_W(s->lay.W,
                   hipLaunchKernelGGL((ea::half_step_kernel<WW>), grid, dim3(256), 0, s->stream, s->lat, g,
-                                      half, t, key_lo(s), key_hi(s), s->sample, s->thr[0], s->thr[1],
-                                      s->thr[2]));
+                                      half, s->t_dev, t_off, key_lo(s), key_hi(s), s->sample, s->thr[0],
+                                      s->thr[1], s->thr[2]));
+    return EA_OK;
+}
+
+// Sweeps per captured graph: long enough to amortise the replay, short
+// enough that the remainder loop stays small.
+constexpr uint32_t kGraphSweeps = 64;
+
+// Enqueue sweeps t_dev + 0 .. t_dev + n-1 as plain launches.
+ea_status launch_sweeps(ea_sim *s, uint32_t n)
+{
+    for (uint32_t i = 0; i < n; ++i) {
+        ea_status st = launch_half_step(s, 0, i);
+        if (st != EA_OK) return st;
+        st = launch_half_step(s, 1, i);
+        if (st != EA_OK) return st;
+    }
+    return EA_OK;
+}
+
+// Capture kGraphSweeps sweeps followed by the counter advance.
+ea_status build_graph(ea_sim *s)
+{
+    EA_HIP(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+    ea_status st = launch_sweeps(s, kGraphSweeps);
+    hipLaunchKernelGGL(ea::advance_u32_kernel, dim3(1), dim3(64), 0, s->stream, s->t_dev, kGraphSweeps);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(s->stream, &graph);
+    if (st != EA_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return fail(EA_ERR_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&s->graph_exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return fail(EA_ERR_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    s->graph = graph;
     return EA_OK;
 }
 
@@ -276,6 +320,7 @@ ea_status ea_create_ex(const ea_config *cfg, ea_sim **out)
     s->lat.bonds = (uint32_t *)(s->buf + lay.off_bonds);
     s->snaps = (uint32_t *)(s->buf + lay.off_snaps);
     s->meas = (unsigned long long *)(s->buf + lay.off_meas);
+    s->t_dev = (uint32_t *)(s->buf + lay.off_ctl);
 
     ea_status st = launch_init(s);
     if (st != EA_OK) {
@@ -294,9 +339,27 @@ void ea_destroy(ea_sim *s)
 {
     if (!s) return;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
+    if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
     if (s->own_buf && s->buf) (void)hipFree(s->buf);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
+}
+
+ea_status ea_reset(ea_sim *s, uint64_t seed, uint32_t sample)
+{
+    if (!s) return fail(EA_ERR_ARG, "sim is NULL");
+    s->seed = seed;
+    s->sample = sample;
+    s->t = 0;
+    std::fill(s->snap_t.begin(), s->snap_t.end(), 0);
+    std::fill(s->snap_taken.begin(), s->snap_taken.end(), 0);
+    // the captured sweeps bake the key into their arguments
+    if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+    s->graph_exec = nullptr;
+    s->graph = nullptr;
+    return launch_init(s);
 }
 
 ea_status ea_sweep(ea_sim *s, uint64_t n)
@@ -304,13 +367,19 @@ ea_status ea_sweep(ea_sim *s, uint64_t n)
     if (!s) return fail(EA_ERR_ARG, "sim is NULL");
     if (s->t + n >= (1ull << 32) || n >= (1ull << 32))
         return fail(EA_ERR_ARG, "t + n = %llu would reach 2^32", (unsigned long long)(s->t + n));
-    for (uint64_t i = 0; i < n; ++i) {
-        const uint32_t t = (uint32_t)(s->t + i);
-        ea_status st = launch_half_step(s, 0, t);
-        if (st != EA_OK) return st;
-        st = launch_half_step(s, 1, t);
-        if (st != EA_OK) return st;
+    if (n == 0) return EA_OK;
+    hipLaunchKernelGGL(ea::set_u32_kernel, dim3(1), dim3(64), 0, s->stream, s->t_dev, (uint32_t)s->t);
+    uint64_t left = n;
+    if (left >= kGraphSweeps) {
+        if (!s->graph_exec) {
+            ea_status st = build_graph(s);
+            if (st != EA_OK) return st;
+        }
+        for (; left >= kGraphSweeps; left -= kGraphSweeps) EA_HIP(hipGraphLaunch(s->graph_exec, s->stream));
+        // the graph advanced the device counter by kGraphSweeps per replay
     }
+    ea_status st = launch_sweeps(s, (uint32_t)left);
+    if (st != EA_OK) return st;
     EA_HIP(hipGetLastError());
     s->t += n;
     return EA_OK;

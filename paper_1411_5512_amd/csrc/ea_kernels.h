@@ -62,17 +62,20 @@ __global__ __launch_bounds__(256) void init_kernel(Lattice lat, Geom g, uint32_t
 }
 
 // --------------------------------------------------------------------------
-// One checkerboard half-step (Sec. III, eq. 9) of sweep t.  grid.y = replica
-// r, which updates colour c = r ^ half; all six neighbours of a colour-c site
-// have colour 1 - c, so every thread reads the other colour and writes only
-// its own word.  One thread per (row, word).
+// One checkerboard half-step (Sec. III, eq. 9) of sweep t = *t_base + t_off
+// (the base lives on the device so that a captured graph of sweeps can be
+// replayed).  grid.y = replica r, which updates colour c = r ^ half; all six
+// neighbours of a colour-c site have colour 1 - c, so every thread reads the
+// other colour and writes only its own word.  One thread per (row, word).
 template <int W>
-__global__ __launch_bounds__(256) void half_step_kernel(Lattice lat, Geom g, int half, uint32_t t,
+__global__ __launch_bounds__(256) void half_step_kernel(Lattice lat, Geom g, int half,
+                                                        const uint32_t *__restrict__ t_base, uint32_t t_off,
                                                         uint32_t k0, uint32_t k1, uint32_t sample,
                                                         uint32_t thr1, uint32_t thr2, uint32_t thr3)
 {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     if (tid >= g.plane) return;
+    const uint32_t t = *t_base + t_off;
     const int r = blockIdx.y;
     const int c = r ^ half;
     const int row = tid / g.RW;
@@ -251,6 +254,17 @@ __global__ __launch_bounds__(256) void zero_u64_kernel(unsigned long long *dst, 
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = 0ull;
+}
+
+// Device-side sweep counter: set it, or advance it after a block of sweeps.
+__global__ void set_u32_kernel(uint32_t *dst, uint32_t v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = v;
+}
+
+__global__ void advance_u32_kernel(uint32_t *dst, uint32_t k)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst += k;
 }
 
 }  // namespace ea
