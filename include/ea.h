@@ -19,11 +19,12 @@
  * energy by dE <= 0 flips; dE = 4k > 0 flips iff its random word u is below
  * thr_k = floor(exp(-4k/T) 2^32) (0 at T = 0).  The random word of a site is
  * word (h & 3) of the Philox4x32-10 block with key = seed and counter
- * (h >> 2, t, tag << 8 | colour << 1 | replica, sample), where
+ * (t, h >> 2, tag << 8 | colour << 1 | replica, sample), where
  * h = (x >> 1) + (L/2)(y + L z) is the site's index inside its colour, t the
- * 0-based sweep index and tag 0.  Couplings use tag 1 (counter word 1 = bond
- * direction, replica 0; J = -1 iff u < floor(p 2^32) compared in 64 bits),
- * initial spins tag 2 (S = -1 iff the top bit of u is set).  Results
+ * 0-based sweep index and tag 0.  Couplings use tag 1 (counter word 0 = bond
+ * direction d, replica 0; J = -1 iff u < floor(p 2^32) compared in 64 bits),
+ * initial spins tag 2 (counter word 0 = 0; S = -1 iff the top bit of u is
+ * set).  Results
  * therefore depend only on (L, p, T, seed, sample, schedule), never on the
  * launch configuration.
  *

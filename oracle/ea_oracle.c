@@ -58,8 +58,8 @@ uint32_t eao_site_word(uint64_t seed, uint32_t sample, uint32_t tag, uint32_t au
 {
     uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
     uint32_t ctr[4];
-    ctr[0] = (uint32_t)(h >> 2);
-    ctr[1] = aux;
+    ctr[0] = aux;
+    ctr[1] = (uint32_t)(h >> 2);
     ctr[2] = (tag << 8) | ((uint32_t)colour << 1) | (uint32_t)replica;
     ctr[3] = sample;
     uint32_t out[4];

@@ -20,7 +20,8 @@
  *   - colour c(s) = (x+y+z) & 1, half index h(s) = (x>>1) + (L/2)(y + L z).
  *   - sweep t (0-based) is: replica r updates colour r, then colour 1-r.
  *   - random words: Philox4x32-10, key = (seed lo, seed hi), counter =
- *     (h>>2, aux, tag<<8 | colour<<1 | replica, sample), word h & 3.
+ *     (aux, h>>2, tag<<8 | colour<<1 | replica, sample), word h & 3, where aux
+ *     is the sweep index (tag 0), the bond direction (tag 1) or 0 (tag 2).
  *   - acceptance of dE = 4k > 0 iff u < thr_k, thr_k = floor(exp(-4k/T) 2^32)
  *     (clamped to 2^32-1; 0 at T = 0).  dE <= 0 is always accepted.
  */

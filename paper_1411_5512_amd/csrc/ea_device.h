@@ -162,30 +162,31 @@ __device__ __forceinline__ uint32_t accept_site(uint32_t accept, uint32_t u, con
 }
 
 // Blocks J = W/4-1 down to 0: block J covers sites 4J..4J+3 and has counter
-// word 0 equal to quad0 + J.
+// word 1 equal to quad0 + J; words 0, 2, 3 (sweep, tag/colour/replica,
+// sample) are wave-uniform, so the first rounds run largely on the SALU.
 template <int J>
-__device__ __forceinline__ uint32_t accept_blocks(uint32_t accept, const Decision &d, uint32_t quad0,
-                                                  uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+__device__ __forceinline__ uint32_t accept_blocks(uint32_t accept, const Decision &d, uint32_t c0,
+                                                  uint32_t quad0, uint32_t c2, uint32_t c3, uint32_t k0,
                                                   uint32_t k1, uint32_t thr1, uint32_t thr2, uint32_t thr3)
 {
-    const Words4 u = philox10(quad0 + (uint32_t)J, c1, c2, c3, k0, k1);
+    const Words4 u = philox10(c0, quad0 + (uint32_t)J, c2, c3, k0, k1);
     accept = accept_site<4 * J + 3>(accept, u.v[3], d, thr1, thr2, thr3);
     accept = accept_site<4 * J + 2>(accept, u.v[2], d, thr1, thr2, thr3);
     accept = accept_site<4 * J + 1>(accept, u.v[1], d, thr1, thr2, thr3);
     accept = accept_site<4 * J + 0>(accept, u.v[0], d, thr1, thr2, thr3);
     if constexpr (J > 0)
-        return accept_blocks<J - 1>(accept, d, quad0, c1, c2, c3, k0, k1, thr1, thr2, thr3);
+        return accept_blocks<J - 1>(accept, d, c0, quad0, c2, c3, k0, k1, thr1, thr2, thr3);
     else
         return accept;
 }
 
 // Flip mask of one packed word of W sites (bits W..31 stay zero).
 template <int W>
-__device__ __forceinline__ uint32_t flip_mask(const Decision &d, uint32_t quad0, uint32_t c1,
+__device__ __forceinline__ uint32_t flip_mask(const Decision &d, uint32_t c0, uint32_t quad0,
                                               uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,
                                               uint32_t thr1, uint32_t thr2, uint32_t thr3)
 {
-    return d.always | accept_blocks<W / 4 - 1>(0u, d, quad0, c1, c2, c3, k0, k1, thr1, thr2, thr3);
+    return d.always | accept_blocks<W / 4 - 1>(0u, d, c0, quad0, c2, c3, k0, k1, thr1, thr2, thr3);
 }
 
 }  // namespace ea

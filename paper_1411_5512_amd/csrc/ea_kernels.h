@@ -50,7 +50,7 @@ __global__ __launch_bounds__(256) void init_kernel(Lattice lat, Geom g, uint32_t
     uint32_t bits = 0;
 #pragma unroll
     for (int j = 0; j < W / 4; ++j) {
-        const Words4 u = philox10(quad0 + (uint32_t)j, aux, c2, sample, k0, k1);
+        const Words4 u = philox10(aux, quad0 + (uint32_t)j, c2, sample, k0, k1);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const uint32_t bit = is_bond ? (uint32_t)((uint64_t)u.v[q] < pcut) : (u.v[q] >> 31);
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(256) void half_step_kernel(Lattice lat, Geom g, int
 
     const Decision d = classify(a1, a2, a3, a4, a5, a6);
     const uint32_t quad0 = (uint32_t)((row * g.R + w * W) >> 2);
-    const uint32_t flips = flip_mask<W>(d, quad0, t, counter_word2(TAG_METRO, (uint32_t)c, (uint32_t)r),
+    const uint32_t flips = flip_mask<W>(d, t, quad0, counter_word2(TAG_METRO, (uint32_t)c, (uint32_t)r),
                                         sample, k0, k1, thr1, thr2, thr3);
     own[base + w] = S ^ flips;
 }

@@ -54,11 +54,11 @@ def test_philox_matches_rocrand(oracle_mod, rocrand_probe):
 
 def test_site_word_keying(oracle_mod):
     """The site word is word (h & 3) of the block at counter
-    (h>>2, aux, tag<<8 | colour<<1 | replica, sample) under key = seed."""
+    (aux, h>>2, tag<<8 | colour<<1 | replica, sample) under key = seed."""
     seed = 0x123456789ABCDEF
     for (sample, tag, aux, colour, rep, h) in [(0, 0, 0, 0, 0, 0), (3, 0, 99, 1, 1, 4097),
                                                (7, 1, 2, 1, 0, 13), (0, 2, 0, 0, 1, 6)]:
-        blk = oracle_mod.philox4x32_10([h >> 2, aux, (tag << 8) | (colour << 1) | rep, sample],
+        blk = oracle_mod.philox4x32_10([aux, h >> 2, (tag << 8) | (colour << 1) | rep, sample],
                                        [seed & 0xffffffff, seed >> 32])
         assert oracle_mod.site_word(seed, sample, tag, aux, colour, rep, h) == int(blk[h & 3])
 
