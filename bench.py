@@ -1,18 +1,23 @@
 #!/usr/bin/env python3
-"""Throughput benchmark: picoseconds per attempted spin flip on one MI355X.
+"""Throughput benchmark: picoseconds per attempted spin flip on one MI355X,
+batched form against the plain form.
 
-A step is one complete run of the mid-size workload through the C-ABI
-library: regenerate the couplings and initial spins on the device, then
-10^5 red/black Metropolis sweeps of an L = 64 sample with two replicas
-(p = 0.5, T = 0.7), snapshots at t_w in {10^2, 10^3, 10^4} and 20
-log-spaced measurements of energy, magnetisation, overlap, C(t, t_w) and
-C4(r).  ps/flip = step time / (sweeps x L^3 x 2 replicas).
+Batched workload (the timed step): 256 independent disorder samples with two
+replicas each, L drawn from {24, 32, 48, 64}, p from {0.5, 0.3, 0.2}, T from
+{0.6, 0.8, 1.0} (seeds 0..255), 10^5 red/black Metropolis sweeps each with 20
+log-spaced measurements of energy, magnetisation, overlap, C(t, t_w), C4(r)
+and snapshots at t_w in {10^2, 10^3, 10^4}.  A step regenerates every job's
+couplings and initial spins on the device and runs all jobs to the end in
+one persistent launch.  ps/flip = step time / sum_jobs(sweeps x L^3 x 2).
 
-Printed as one JSON line, with
-  roofline      the half-step kernel's achieved integer-ALU rate (algorithmic
-                lane-ops per launch over its event-timed average duration)
-                against the chip's peak;
-  cpu_baseline  the CPU oracle timed on a bounded sample of the same run.
+Plain workload (reported beside it): one L = 64 sample, p = 0.5, T = 0.7,
+the same schedule shape, one kernel launch per half-step.
+
+One JSON line is printed, with
+  roofline      the dominant kernel's achieved integer-ALU rate (algorithmic
+                lane-ops per launch over its event-timed duration) against the
+                chip's peak;
+  cpu_baseline  the CPU oracle timed on a bounded sample of the plain run.
 """
 from __future__ import annotations
 
@@ -40,8 +45,8 @@ def log(msg: str):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_job(sim, job):
-    """One full run of the job on an already allocated sim (synchronous)."""
+def run_plain_job(sim, job):
+    """One full plain run on an already allocated sim (synchronous)."""
     sim.reset(job.seed, job.sample)
     t = 0
     for te, slots, meas in job.events():
@@ -65,9 +70,42 @@ def cpu_baseline(job, sweeps: int):
     o.sweep(sweeps)
     dt = time.perf_counter() - t0
     flips = sweeps * 2 * job.L ** 3
-    return {"value": dt / flips * 1e12, "unit": "ps/flip", "cores": 1, "kind": "oracle",
-            "sample": f"L={job.L} p={job.p} T={job.T} seed={job.seed}: the first {sweeps} sweeps "
-                      f"of the run ({flips} attempted flips, {dt:.1f} s, single thread)"}
+    return {"value": round(dt / flips * 1e12, 1), "unit": "ps/flip", "cores": 1, "kind": "oracle",
+            "sample": f"plain run L={job.L} p={job.p} T={job.T} seed={job.seed}: its first {sweeps} sweeps "
+                      f"({flips} attempted flips, {dt:.1f} s, one thread)"}
+
+
+def bench_plain(ea, torch, job, steps: int, burst: int):
+    sim = ea.Sim(job.L, job.p, job.T, seed=job.seed, sample=job.sample, n_slots=len(job.tw))
+    stream = sim.stream
+    run_plain_job(sim, job)  # warm-up: builds the captured graph
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for i in range(steps):
+        run_plain_job(sim, job)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - w0) * 1e3 / steps
+    # a burst of half-step launches timed with events on the run's stream
+    sim.reset(job.seed, job.sample)
+    sim.sweep(64)
+    b0 = torch.cuda.Event(enable_timing=True)
+    b1 = torch.cuda.Event(enable_timing=True)
+    b0.record(stream)
+    sim.sweep(burst)
+    b1.record(stream)
+    torch.cuda.synchronize()
+    avg_launch_us = b0.elapsed_time(b1) * 1e3 / (2 * burst)
+    sim.close()
+    return {
+        "workload": f"L={job.L} p={job.p} T={job.T}, 1 sample x 2 replicas, {job.n_sweeps} sweeps, "
+                    f"{len(job.meas_t)} measurements, tw={job.tw}; one launch per half-step",
+        "ps_per_flip": round(ms * 1e-3 / job.flips * 1e12, 4),
+        "ms_per_step": round(ms, 3),
+        "steps": steps,
+        "half_step_avg_us": round(avg_launch_us, 3),
+        "half_step_alu_frac": round(ALG_OPS_PER_FLIP * job.L ** 3 / (avg_launch_us * 1e-6) / 1e12
+                                    / VALU_PEAK_TOPS, 5),
+    }
 
 
 def main():
@@ -75,10 +113,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--sweeps", type=int, default=100_000, help="sweeps per run (step)")
-    ap.add_argument("--burst", type=int, default=2048, help="sweeps in the kernel-timing burst")
+    ap.add_argument("--jobs", type=int, default=256, help="jobs in the batched workload")
+    ap.add_argument("--sweeps", type=int, default=100_000, help="sweeps per job")
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--burst", type=int, default=2048, help="sweeps in the plain kernel-timing burst")
     ap.add_argument("--cpu-sweeps", type=int, default=60, help="oracle sweeps for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -94,48 +135,47 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
 
-    job = wl.mid_job(args.sweeps)
-    sim = ea.Sim(job.L, job.p, job.T, seed=job.seed, sample=job.sample, n_slots=len(job.tw))
-    stream = sim.stream
-    flips_per_step = job.flips
+    jobs = wl.batch_jobs(n_jobs=args.jobs, n_sweeps=args.sweeps)
+    flips_per_step = sum(j.flips for j in jobs)
+    batch = ea.Batch(jobs)
+    stream = batch.stream
 
     for i in range(args.warmup):
-        run_job(sim, job)
+        batch.reset()
+        batch.run()
         log(f"warmup {i + 1}/{args.warmup} done")
 
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
+    run_ms = []
     w0 = time.perf_counter()
     for i in range(args.steps):
-        run_job(sim, job)
-        log(f"step {i + 1}/{args.steps} done")
-    ev1.record(stream)
+        batch.reset()
+        ev0.record(stream)
+        batch.run()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        run_ms.append(ev0.elapsed_time(ev1))
+        log(f"step {i + 1}/{args.steps} done ({run_ms[-1]:.1f} ms in the batch launch)")
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
-    dev_ms = ev0.elapsed_time(ev1)
     ms_per_step = wall * 1e3 / args.steps
     ps_per_flip = ms_per_step * 1e-3 / flips_per_step * 1e12
+    launch_s = sum(run_ms) / len(run_ms) * 1e-3
+    achieved = ALG_OPS_PER_FLIP * flips_per_step / launch_s / 1e12
 
-    # Sweeps only (no measurement or reset), for the roofline: a burst of
-    # half-step launches timed with events on the run's stream.
-    sim.reset(job.seed, job.sample)
-    sim.sweep(64)
-    b0 = torch.cuda.Event(enable_timing=True)
-    b1 = torch.cuda.Event(enable_timing=True)
-    b0.record(stream)
-    sim.sweep(args.burst)
-    b1.record(stream)
-    torch.cuda.synchronize()
-    burst_ms = b0.elapsed_time(b1)
-    launches = 2 * args.burst
-    avg_launch_s = burst_ms * 1e-3 / launches
-    flips_per_launch = job.L ** 3  # N/2 sites in each of the two replicas
-    achieved = ALG_OPS_PER_FLIP * flips_per_launch / avg_launch_s / 1e12
-    sweeps_only_ps = burst_ms * 1e-3 / (args.burst * 2 * job.L ** 3) * 1e12
-    log(f"step {ms_per_step:.1f} ms ({ps_per_flip:.3f} ps/flip); half-step avg {avg_launch_s * 1e6:.2f} us")
+    # the results are on the device; read them back once, outside the timing,
+    # and check the identity C(t_w, t_w) = 1 on every job
+    for j, job in enumerate(jobs):
+        for k, t in enumerate(job.meas_t):
+            if t in job.tw:
+                o = batch.result(j, k, c4=False)
+                slot = job.tw.index(t)
+                assert list(o.autocorr[:, slot]) == [job.L ** 3] * 2, (j, k)
+    n_results = sum(len(j.meas_t) for j in jobs)
 
+    Ls = sorted({j.L for j in jobs})
     out = {
         "metric": METRIC,
         "value": round(ps_per_flip, 4),
@@ -150,30 +190,38 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {
-            "workload": f"plain form, mid size: L={job.L}, p={job.p}, T={job.T}, 1 sample x 2 replicas, "
-                        f"{job.n_sweeps} sweeps, {len(job.meas_t)} measurements, tw={job.tw}",
-            "form": "plain (one launch per half-step, sweeps replayed from a captured graph)",
-            "L": job.L, "p": job.p, "T": job.T, "sweeps": job.n_sweeps,
+            "workload": f"batched form: {len(jobs)} samples x 2 replicas, L in {Ls}, p in {{0.5,0.3,0.2}}, "
+                        f"T in {{0.6,0.8,1.0}}, seeds 0..{len(jobs) - 1}, {args.sweeps} sweeps each, "
+                        f"20 log-spaced measurements + tw {{1e2,1e3,1e4}}, one persistent launch",
+            "form": "batched",
+            "jobs": len(jobs),
+            "sweeps": args.sweeps,
             "flips_per_step": flips_per_step,
+            "measurements_per_step": n_results,
         },
-        "device_ms_per_step": round(dev_ms / args.steps, 3),
-        "sweeps_only_ps_per_flip": round(sweeps_only_ps, 4),
         "roofline": {
             "bound": "alu",
-            "kernel": "half_step_kernel<32>",
-            "achieved": round(achieved, 4),
+            "kernel": "batch_kernel",
+            "achieved": round(achieved, 3),
             "peak": round(VALU_PEAK_TOPS, 2),
             "unit": "Tops/s (32-bit lane-ops)",
-            "frac": round(achieved / VALU_PEAK_TOPS, 5),
+            "frac": round(achieved / VALU_PEAK_TOPS, 4),
             "traffic": None,
-            "avg_launch_us": round(avg_launch_s * 1e6, 3),
+            "launch_ms": round(launch_s * 1e3, 3),
             "alg_ops_per_flip": ALG_OPS_PER_FLIP,
-            "flips_per_launch": flips_per_launch,
+            "flips_per_launch": flips_per_step,
         },
     }
+    batch.close()
+
+    if not args.no_plain:
+        log("plain form ...")
+        plain = bench_plain(ea, torch, wl.mid_job(args.sweeps), args.plain_steps, args.burst)
+        out["plain"] = plain
+        out["batched_speedup_vs_plain"] = round(plain["ps_per_flip"] / ps_per_flip, 2)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(job, args.cpu_sweeps)
+        out["cpu_baseline"] = cpu_baseline(wl.mid_job(args.sweeps), args.cpu_sweeps)
     print(json.dumps(out), flush=True)
 
 

@@ -150,6 +150,58 @@ ea_status ea_set_spins(ea_sim *sim, int32_t r, const int8_t *pm1);
 ea_status ea_get_bonds(ea_sim *sim, int8_t *pm1);
 ea_status ea_set_bonds(ea_sim *sim, const int8_t *pm1);
 
+/* ------------------------------------------------------------------------
+ * Batched form: many independent runs of different L, p, T and schedule in
+ * one persistent launch.  Each replica of each job is owned by one
+ * workgroup that keeps the replica's spins and the job's couplings in LDS and
+ * takes the scheduled snapshots and measurements itself, so L is limited by
+ * the LDS of one compute unit (multiple of 8 in 8..64).  A job's results are
+ * bit-identical to a plain run (ea_create) with the same parameters: the
+ * random words depend only on (seed, sample, replica, sweep, site).
+ */
+typedef struct ea_batch ea_batch;
+
+typedef struct {
+    int32_t L;               /* multiple of 8 in 8..64 */
+    double p;                /* P(J = -1) in [0, 1] */
+    double T;                /* temperature >= 0, finite */
+    uint64_t seed;
+    uint32_t sample;
+    uint64_t n_sweeps;       /* below 2^32 */
+    const uint64_t *meas_t;  /* [n_meas] measurement times, strictly increasing, <= n_sweeps */
+    int32_t n_meas;
+    const uint64_t *tw;      /* [n_tw] snapshot times S(t_w), strictly increasing, <= n_sweeps */
+    int32_t n_tw;            /* 0..64 */
+} ea_job;
+
+typedef struct {
+    void *stream;            /* hipStream_t to enqueue on, or NULL for a library stream */
+} ea_batch_opts;
+
+/* Copy the job list (the caller's schedule arrays may be freed afterwards),
+ * allocate device memory for every job and generate the initial states.
+ * EA_ERR_ARG names the first invalid job. */
+ea_status ea_batch_create(const ea_job *jobs, int32_t n_jobs, const ea_batch_opts *opts, ea_batch **out);
+void ea_batch_destroy(ea_batch *b);
+
+/* Regenerate every job's couplings and initial spins, t = 0, clear results. */
+ea_status ea_batch_reset(ea_batch *b);
+
+/* Advance every job to min(t_stop, its n_sweeps), taking the snapshots and
+ * measurements scheduled on the way; returns when the launch has finished. */
+ea_status ea_batch_run(ea_batch *b, uint64_t t_stop);
+
+/* Sweeps done by job j. */
+ea_status ea_batch_time(ea_batch *b, int32_t job, uint64_t *t);
+
+/* Observables of job j's k-th scheduled measurement (ea_obs as for a plain
+ * run; n_tw = the job's snapshot count, slots whose t_w lies after the
+ * measurement report autocorr 0).  EA_ERR_STATE if it was not reached. */
+ea_status ea_batch_result(ea_batch *b, int32_t job, int32_t k, ea_obs *out);
+
+/* Current spins of replica r of job j, int8 +-1 in canonical order [L^3]. */
+ea_status ea_batch_get_spins(ea_batch *b, int32_t job, int32_t r, int8_t *pm1);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,7 +15,7 @@ import numpy as np
 from . import abi
 from .abi import EAError
 
-__all__ = ["Sim", "EAError", "thresholds", "footprint", "version"]
+__all__ = ["Sim", "Batch", "EAError", "thresholds", "footprint", "version"]
 
 
 def version() -> str:
@@ -175,3 +175,93 @@ class Sim:
         if J.size != 3 * self.N:
             raise ValueError("wrong coupling count")
         abi.check(abi.lib().ea_set_bonds(self._h, abi.ptr(J, ctypes.c_int8)))
+
+
+def _job_struct(job, keep):
+    """Fill an ea_job from a workloads.Job-like object; `keep` holds the
+    schedule arrays alive for the duration of the call."""
+    j = abi.Job()
+    j.L, j.p, j.T = int(job.L), float(job.p), float(job.T)
+    j.seed, j.sample, j.n_sweeps = int(job.seed), int(job.sample), int(job.n_sweeps)
+    meas = np.ascontiguousarray(job.meas_t, dtype=np.uint64)
+    tw = np.ascontiguousarray(job.tw, dtype=np.uint64)
+    keep += [meas, tw]
+    j.meas_t = abi.ptr(meas, ctypes.c_uint64) if meas.size else None
+    j.n_meas = int(meas.size)
+    j.tw = abi.ptr(tw, ctypes.c_uint64) if tw.size else None
+    j.n_tw = int(tw.size)
+    return j
+
+
+class Batch:
+    """Many independent runs (L <= 64) in one persistent launch per span."""
+
+    def __init__(self, jobs, use_torch: bool = True):
+        self.jobs = list(jobs)
+        keep = []
+        arr = (abi.Job * len(self.jobs))(*[_job_struct(j, keep) for j in self.jobs])
+        opts = abi.BatchOpts()
+        self._stream = None
+        if use_torch:
+            try:
+                import torch
+                if torch.cuda.is_available():
+                    self._stream = torch.cuda.Stream()
+                    opts.stream = ctypes.c_void_p(self._stream.cuda_stream)
+            except ImportError:
+                pass
+        h = ctypes.c_void_p()
+        abi.check(abi.lib().ea_batch_create(arr, len(self.jobs), ctypes.byref(opts), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            abi.lib().ea_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def stream(self):
+        return self._stream
+
+    def reset(self):
+        abi.check(abi.lib().ea_batch_reset(self._h))
+
+    def run(self, t_stop: int | None = None):
+        """Advance every job to min(t_stop, its n_sweeps) (default: the end)."""
+        if t_stop is None:
+            t_stop = max(j.n_sweeps for j in self.jobs)
+        abi.check(abi.lib().ea_batch_run(self._h, int(t_stop)))
+
+    def time(self, job: int) -> int:
+        t = ctypes.c_uint64(0)
+        abi.check(abi.lib().ea_batch_time(self._h, int(job), ctypes.byref(t)))
+        return int(t.value)
+
+    def result(self, job: int, k: int, c4: bool = True) -> Obs:
+        J = self.jobs[job]
+        n_tw = len(J.tw)
+        o = abi.Obs()
+        tw = np.zeros(max(n_tw, 1), dtype=np.uint64)
+        ac = np.zeros((2, max(n_tw, 1)), dtype=np.int64)
+        c4a = np.zeros((3, J.L // 2 + 1), dtype=np.int64)
+        if n_tw:
+            o.n_tw = n_tw
+            o.tw = abi.ptr(tw, ctypes.c_uint64)
+            o.autocorr = abi.ptr(ac, ctypes.c_int64)
+        if c4:
+            o.rmax = J.L // 2
+            o.c4 = abi.ptr(c4a, ctypes.c_int64)
+        abi.check(abi.lib().ea_batch_result(self._h, int(job), int(k), ctypes.byref(o)))
+        return Obs(int(o.t), np.array(o.unsat[:], dtype=np.int64), np.array(o.mag[:], dtype=np.int64),
+                   int(o.overlap), tw[:n_tw].copy(), ac[:, :n_tw].copy(), c4a if c4 else None)
+
+    def spins(self, job: int, r: int) -> np.ndarray:
+        out = np.zeros(self.jobs[job].L ** 3, dtype=np.int8)
+        abi.check(abi.lib().ea_batch_get_spins(self._h, int(job), int(r), abi.ptr(out, ctypes.c_int8)))
+        return out

@@ -52,6 +52,25 @@ class Obs(ctypes.Structure):
     ]
 
 
+class Job(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_int32),
+        ("p", ctypes.c_double),
+        ("T", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("sample", ctypes.c_uint32),
+        ("n_sweeps", ctypes.c_uint64),
+        ("meas_t", ctypes.POINTER(ctypes.c_uint64)),
+        ("n_meas", ctypes.c_int32),
+        ("tw", ctypes.POINTER(ctypes.c_uint64)),
+        ("n_tw", ctypes.c_int32),
+    ]
+
+
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("stream", ctypes.c_void_p)]
+
+
 # name -> (restype, argtypes)
 _SIGS = {
     "ea_last_error": (ctypes.c_char_p, []),
@@ -73,6 +92,15 @@ _SIGS = {
     "ea_set_spins": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int8)]),
     "ea_get_bonds": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int8)]),
     "ea_set_bonds": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int8)]),
+    "ea_batch_create": (ctypes.c_int, [ctypes.POINTER(Job), ctypes.c_int32, ctypes.POINTER(BatchOpts),
+                                       ctypes.POINTER(ctypes.c_void_p)]),
+    "ea_batch_destroy": (None, [ctypes.c_void_p]),
+    "ea_batch_reset": (ctypes.c_int, [ctypes.c_void_p]),
+    "ea_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "ea_batch_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]),
+    "ea_batch_result": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Obs)]),
+    "ea_batch_get_spins": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_int8)]),
 }
 
 _lib = None

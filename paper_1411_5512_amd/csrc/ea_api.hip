@@ -2,7 +2,7 @@
 // checks, device memory, layout conversion and kernel dispatch for the plain
 // form (one launch per checkerboard half-step).
 #include "ea.h"
-#include "ea_kernels.h"
+#include "ea_batch_kernels.h"
 
 #include <cmath>
 #include <cstdarg>
@@ -41,12 +41,7 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 // Words per row: the fewest words of at most 32 bits such that every word
 // holds a whole number of 4-site random-word blocks.
-int words_per_row(int R)
-{
-    int rw = (R + 31) / 32;
-    while ((R / 4) % rw != 0) ++rw;
-    return rw;
-}
+int words_per_row(int R) { return ea::words_per_row_c(R); }
 
 struct Layout {
     int L, R, RW, W, rows, plane;
@@ -137,14 +132,19 @@ unsigned blocks_for(size_t n, unsigned bs = 256) { return (unsigned)((n + bs - 1
     default: return fail(EA_ERR_STATE, "unsupported word width %d", W);  \
     }
 
-ea_status launch_init(ea_sim *s)
+ea_status launch_init_lattice(const ea::Lattice &lat, const ea::Geom &g, int W, uint64_t seed, uint32_t sample,
+                              uint64_t pcut, hipStream_t stream)
 {
-    ea::Geom g = s->geom();
     dim3 grid(blocks_for(g.plane), 5, 2);
-    EA_DISPATCH_W(s->lay.W, hipLaunchKernelGGL((ea::init_kernel<WW>), grid, dim3(256), 0, s->stream,
-                                                s->lat, g, key_lo(s), key_hi(s), s->sample, s->pcut));
+    EA_DISPATCH_W(W, hipLaunchKernelGGL((ea::init_kernel<WW>), grid, dim3(256), 0, stream, lat, g,
+                                        (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), sample, pcut));
     EA_HIP(hipGetLastError());
     return EA_OK;
+}
+
+ea_status launch_init(ea_sim *s)
+{
+    return launch_init_lattice(s->lat, s->geom(), s->lay.W, s->seed, s->sample, s->pcut, s->stream);
 }
 
 ea_status launch_half_step(ea_sim *s, int half, uint32_t t_off)
@@ -539,3 +539,5 @@ ea_status ea_set_bonds(ea_sim *s, const int8_t *pm1)
 }
 
 }  // extern "C"
+
+#include "ea_batch_api.h"

@@ -1,0 +1,382 @@
+// ea_batch_api.h -- host side of the batched form (ea_batch_* in ea.h).
+// Included once, at the end of ea_api.hip, so that the whole library is one
+// translation unit and shares its helpers.
+#pragma once
+
+#include <numeric>
+
+namespace {
+
+struct BatchJobHost {
+    ea_job job{};             // parameters (schedule pointers not kept)
+    std::vector<uint32_t> meas_t, tw;
+    int R = 0, RW = 0, W = 0, POS = 0, obs_stride = 0;
+    uint32_t thr[3] = {0, 0, 0};
+    uint64_t pcut = 0;
+    size_t off_spins = 0, off_bonds = 0, off_snaps = 0, off_mspins = 0, off_obs = 0, off_arrive = 0,
+           off_tnow = 0, off_meas_t = 0, off_tw = 0;
+    uint64_t t_host = 0;      // sweeps done (host mirror)
+    bool started = false;     // a span has run (events at t = 0 are taken)
+};
+
+bool batch_L_ok(int L) { return L >= 8 && L <= ea::kBatchMaxL && L % 8 == 0; }
+
+int batch_lds_words(int L)
+{
+    switch (L) {
+    case 8: return ea::Shape<8>::LDS_WORDS;
+    case 16: return ea::Shape<16>::LDS_WORDS;
+    case 24: return ea::Shape<24>::LDS_WORDS;
+    case 32: return ea::Shape<32>::LDS_WORDS;
+    case 40: return ea::Shape<40>::LDS_WORDS;
+    case 48: return ea::Shape<48>::LDS_WORDS;
+    case 56: return ea::Shape<56>::LDS_WORDS;
+    case 64: return ea::Shape<64>::LDS_WORDS;
+    default: return -1;
+    }
+}
+
+ea_status copy_schedule(const uint64_t *src, int32_t n, uint64_t n_sweeps, const char *what,
+                        std::vector<uint32_t> &dst)
+{
+    dst.clear();
+    if (n < 0) return fail(EA_ERR_ARG, "%s count %d is negative", what, n);
+    if (n > 0 && !src) return fail(EA_ERR_ARG, "%s is NULL", what);
+    for (int32_t i = 0; i < n; ++i) {
+        if (src[i] > n_sweeps) return fail(EA_ERR_ARG, "%s[%d]=%llu beyond %llu sweeps", what, i,
+                                            (unsigned long long)src[i], (unsigned long long)n_sweeps);
+        if (i > 0 && src[i] <= src[i - 1]) return fail(EA_ERR_ARG, "%s is not strictly increasing", what);
+        dst.push_back((uint32_t)src[i]);
+    }
+    return EA_OK;
+}
+
+}  // namespace
+
+struct ea_batch {
+    std::vector<BatchJobHost> jobs;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    char *buf = nullptr;
+    size_t bytes = 0;
+    ea::BatchJobDev *d_jobs = nullptr;
+    ea::BatchUnit *d_units = nullptr;
+    std::vector<ea::BatchUnit> units;
+    size_t lds_bytes = 0;
+    std::vector<unsigned long long> h_obs;  // staging for ea_batch_result
+};
+
+namespace {
+
+ea_status batch_reset_device(ea_batch *b)
+{
+    for (auto &h : b->jobs) {
+        ea::Lattice lat;
+        lat.spins = (uint32_t *)(b->buf + h.off_spins);
+        lat.bonds = (uint32_t *)(b->buf + h.off_bonds);
+        ea::Geom g;
+        g.L = h.job.L;
+        g.R = h.R;
+        g.RW = h.RW;
+        g.rows = h.job.L * h.job.L;
+        g.plane = h.POS;
+        ea_status st = launch_init_lattice(lat, g, h.W, h.job.seed, h.job.sample, h.pcut, b->stream);
+        if (st != EA_OK) return st;
+        const size_t n_obs = (size_t)h.job.n_meas * (size_t)h.obs_stride;
+        if (n_obs)
+            hipLaunchKernelGGL(ea::zero_u64_kernel, dim3(blocks_for(n_obs)), dim3(256), 0, b->stream,
+                               (unsigned long long *)(b->buf + h.off_obs), n_obs);
+        // arrive[n_meas] and t_now[2] are contiguous 32-bit words
+        const size_t n_ctl32 = (size_t)h.job.n_meas + 2;
+        hipLaunchKernelGGL(ea::zero_u32_kernel, dim3(blocks_for(n_ctl32)), dim3(256), 0, b->stream,
+                           (uint32_t *)(b->buf + h.off_arrive), n_ctl32);
+        h.t_host = 0;
+        h.started = false;
+    }
+    EA_HIP(hipGetLastError());
+    return EA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ea_status ea_batch_create(const ea_job *jobs, int32_t n_jobs, const ea_batch_opts *opts, ea_batch **out)
+{
+    if (!out) return fail(EA_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!jobs || n_jobs <= 0) return fail(EA_ERR_ARG, "need at least one job");
+    ea_batch *b = new (std::nothrow) ea_batch();
+    if (!b) return fail(EA_ERR_NOMEM, "host allocation failed");
+    b->jobs.resize((size_t)n_jobs);
+    size_t off = 0;
+    int max_lds = 0;
+    for (int32_t j = 0; j < n_jobs; ++j) {
+        const ea_job &in = jobs[j];
+        BatchJobHost &h = b->jobs[(size_t)j];
+        ea_status st = EA_OK;
+        if (!batch_L_ok(in.L))
+            st = fail(EA_ERR_ARG, "job %d: L=%d must be a multiple of 8 in [8, %d] for the batched form", j,
+                      in.L, ea::kBatchMaxL);
+        else if (!(in.p >= 0.0 && in.p <= 1.0))
+            st = fail(EA_ERR_ARG, "job %d: p=%g outside [0, 1]", j, in.p);
+        else if (!(in.T >= 0.0) || !std::isfinite(in.T))
+            st = fail(EA_ERR_ARG, "job %d: T=%g must be finite and >= 0", j, in.T);
+        else if (in.n_sweeps >= (1ull << 32))
+            st = fail(EA_ERR_ARG, "job %d: n_sweeps must be below 2^32", j);
+        else if (in.n_tw > kMaxSlots)
+            st = fail(EA_ERR_ARG, "job %d: n_tw=%d above %d", j, in.n_tw, kMaxSlots);
+        if (st == EA_OK) st = copy_schedule(in.meas_t, in.n_meas, in.n_sweeps, "meas_t", h.meas_t);
+        if (st == EA_OK) st = copy_schedule(in.tw, in.n_tw, in.n_sweeps, "tw", h.tw);
+        if (st != EA_OK) {
+            delete b;
+            return st;
+        }
+        h.job = in;
+        h.job.meas_t = nullptr;
+        h.job.tw = nullptr;
+        h.R = in.L / 2;
+        h.RW = words_per_row(h.R);
+        h.W = h.R / h.RW;
+        h.POS = in.L * in.L * h.RW;
+        h.obs_stride = ea::M_AUTO + 2 * in.n_tw + 3 * (h.R + 1);
+        host_thresholds(in.T, h.thr);
+        h.pcut = (uint64_t)std::floor(std::ldexp(in.p, 32));
+        const size_t spin4 = 4 * (size_t)h.POS;  // words of [replica][colour]
+        h.off_spins = off = align256(off);
+        off += 4 * spin4;
+        h.off_bonds = off = align256(off);
+        off += 4 * 6 * (size_t)h.POS;
+        h.off_snaps = off = align256(off);
+        off += 4 * spin4 * (size_t)in.n_tw;
+        h.off_mspins = off = align256(off);
+        off += 4 * spin4 * (size_t)in.n_meas;
+        h.off_obs = off = align256(off);
+        off += 8 * (size_t)in.n_meas * (size_t)h.obs_stride;
+        h.off_arrive = off = align256(off);
+        off += 4 * (size_t)in.n_meas;
+        h.off_tnow = off;
+        off += 8;
+        h.off_meas_t = off = align256(off);
+        off += 4 * (size_t)in.n_meas;
+        h.off_tw = off = align256(off);
+        off += 4 * (size_t)in.n_tw;
+        max_lds = std::max(max_lds, batch_lds_words(in.L));
+    }
+    const size_t off_jobs = align256(off);
+    off = off_jobs + sizeof(ea::BatchJobDev) * (size_t)n_jobs;
+    const size_t off_units = align256(off);
+    off = off_units + sizeof(ea::BatchUnit) * 2 * (size_t)n_jobs;
+    b->bytes = align256(off);
+    b->lds_bytes = ((size_t)max_lds + 16) * 4;
+
+    int dev = 0, lds_limit = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) {
+        delete b;
+        return fail(EA_ERR_DEVICE, "device query: %s", hipGetErrorString(e));
+    }
+    if (b->lds_bytes > (size_t)lds_limit) {
+        const size_t need = b->lds_bytes;
+        delete b;
+        return fail(EA_ERR_ARG, "the largest job needs %zu bytes of LDS, the device offers %d", need, lds_limit);
+    }
+
+    if (opts && opts->stream) {
+        b->stream = (hipStream_t)opts->stream;
+    } else {
+        e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete b;
+            return fail(EA_ERR_DEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+        }
+        b->own_stream = true;
+    }
+    e = hipMalloc((void **)&b->buf, b->bytes);
+    if (e != hipSuccess) {
+        ea_batch_destroy(b);
+        return fail(EA_ERR_NOMEM, "hipMalloc(%zu): %s", b->bytes, hipGetErrorString(e));
+    }
+    e = hipFuncSetAttribute((const void *)ea::batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)b->lds_bytes);
+    if (e != hipSuccess) {
+        ea_batch_destroy(b);
+        return fail(EA_ERR_DEVICE, "hipFuncSetAttribute: %s", hipGetErrorString(e));
+    }
+
+    // Job table and schedules.
+    std::vector<ea::BatchJobDev> dj((size_t)n_jobs);
+    for (int32_t j = 0; j < n_jobs; ++j) {
+        const BatchJobHost &h = b->jobs[(size_t)j];
+        ea::BatchJobDev &d = dj[(size_t)j];
+        d.L = h.job.L;
+        d.k0 = (uint32_t)(h.job.seed & 0xffffffffu);
+        d.k1 = (uint32_t)(h.job.seed >> 32);
+        d.sample = h.job.sample;
+        d.thr1 = h.thr[0];
+        d.thr2 = h.thr[1];
+        d.thr3 = h.thr[2];
+        d.n_meas = h.job.n_meas;
+        d.n_tw = h.job.n_tw;
+        d.obs_stride = h.obs_stride;
+        d.spins = (uint32_t *)(b->buf + h.off_spins);
+        d.bonds = (const uint32_t *)(b->buf + h.off_bonds);
+        d.snaps = (uint32_t *)(b->buf + h.off_snaps);
+        d.mspins = (uint32_t *)(b->buf + h.off_mspins);
+        d.meas_t = (const uint32_t *)(b->buf + h.off_meas_t);
+        d.tw_t = (const uint32_t *)(b->buf + h.off_tw);
+        d.obs = (unsigned long long *)(b->buf + h.off_obs);
+        d.arrive = (uint32_t *)(b->buf + h.off_arrive);
+        d.t_now = (uint32_t *)(b->buf + h.off_tnow);
+        if (!h.meas_t.empty())
+            e = hipMemcpyAsync(b->buf + h.off_meas_t, h.meas_t.data(), 4 * h.meas_t.size(),
+                               hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess && !h.tw.empty())
+            e = hipMemcpyAsync(b->buf + h.off_tw, h.tw.data(), 4 * h.tw.size(), hipMemcpyHostToDevice,
+                               b->stream);
+        if (e != hipSuccess) break;
+    }
+    b->d_jobs = (ea::BatchJobDev *)(b->buf + off_jobs);
+    b->d_units = (ea::BatchUnit *)(b->buf + off_units);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_jobs, dj.data(), sizeof(ea::BatchJobDev) * dj.size(), hipMemcpyHostToDevice,
+                           b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        ea_batch_destroy(b);
+        return fail(EA_ERR_DEVICE, "job table upload: %s", hipGetErrorString(e));
+    }
+
+    // Units, largest lattices first so that the longest work starts first;
+    // the two replicas of a job are adjacent so they reach each measurement
+    // at about the same time.
+    std::vector<int32_t> order((size_t)n_jobs);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) {
+        const BatchJobHost &x = b->jobs[(size_t)a], &y = b->jobs[(size_t)c];
+        const double wx = (double)x.job.L * x.job.L * x.job.L * (double)x.job.n_sweeps;
+        const double wy = (double)y.job.L * y.job.L * y.job.L * (double)y.job.n_sweeps;
+        return wx > wy;
+    });
+    for (int32_t j : order)
+        for (int32_t r = 0; r < 2; ++r) b->units.push_back(ea::BatchUnit{j, r, 0u, 1});
+
+    ea_status st = batch_reset_device(b);
+    if (st != EA_OK) {
+        ea_batch_destroy(b);
+        return st;
+    }
+    *out = b;
+    return EA_OK;
+}
+
+void ea_batch_destroy(ea_batch *b)
+{
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->buf) (void)hipFree(b->buf);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+ea_status ea_batch_reset(ea_batch *b)
+{
+    if (!b) return fail(EA_ERR_ARG, "batch is NULL");
+    return batch_reset_device(b);
+}
+
+ea_status ea_batch_run(ea_batch *b, uint64_t t_stop)
+{
+    if (!b) return fail(EA_ERR_ARG, "batch is NULL");
+    bool any = false;
+    for (auto &u : b->units) {
+        const BatchJobHost &h = b->jobs[(size_t)u.job];
+        const uint64_t stop = std::min<uint64_t>(t_stop, h.job.n_sweeps);
+        u.t_stop = (uint32_t)std::max<uint64_t>(stop, h.t_host);
+        u.first = h.started ? 0 : 1;
+        any = any || u.t_stop > h.t_host || u.first;
+    }
+    if (!any) return EA_OK;
+    EA_HIP(hipMemcpyAsync(b->d_units, b->units.data(), sizeof(ea::BatchUnit) * b->units.size(),
+                          hipMemcpyHostToDevice, b->stream));
+    hipLaunchKernelGGL(ea::batch_kernel, dim3((unsigned)b->units.size()), dim3(ea::kBatchThreads), b->lds_bytes,
+                       b->stream, b->d_jobs, b->d_units);
+    EA_HIP(hipGetLastError());
+    for (auto &h : b->jobs) {
+        h.t_host = std::max<uint64_t>(h.t_host, std::min<uint64_t>(t_stop, h.job.n_sweeps));
+        h.started = true;
+    }
+    // the unit table is read by the kernel: keep the host copy stable until it ran
+    EA_HIP(hipStreamSynchronize(b->stream));
+    return EA_OK;
+}
+
+ea_status ea_batch_time(ea_batch *b, int32_t job, uint64_t *t)
+{
+    if (!b || !t) return fail(EA_ERR_ARG, "NULL argument");
+    if (job < 0 || job >= (int32_t)b->jobs.size()) return fail(EA_ERR_ARG, "job %d out of range", job);
+    *t = b->jobs[(size_t)job].t_host;
+    return EA_OK;
+}
+
+ea_status ea_batch_result(ea_batch *b, int32_t job, int32_t k, ea_obs *out)
+{
+    if (!b || !out) return fail(EA_ERR_ARG, "NULL argument");
+    if (job < 0 || job >= (int32_t)b->jobs.size()) return fail(EA_ERR_ARG, "job %d out of range", job);
+    const BatchJobHost &h = b->jobs[(size_t)job];
+    if (k < 0 || k >= h.job.n_meas) return fail(EA_ERR_ARG, "measurement %d out of range", k);
+    if (h.meas_t[(size_t)k] > h.t_host) return fail(EA_ERR_STATE, "measurement %d (t=%u) not reached", k,
+                                                     h.meas_t[(size_t)k]);
+    if (out->autocorr && out->n_tw != h.job.n_tw)
+        return fail(EA_ERR_ARG, "n_tw=%d but the job has %d snapshot times", out->n_tw, h.job.n_tw);
+    if (out->c4 && out->rmax != h.R) return fail(EA_ERR_ARG, "rmax=%d but L/2=%d", out->rmax, h.R);
+    b->h_obs.resize((size_t)h.obs_stride);
+    EA_HIP(hipMemcpyAsync(b->h_obs.data(), b->buf + h.off_obs + 8 * (size_t)k * (size_t)h.obs_stride,
+                          8 * (size_t)h.obs_stride, hipMemcpyDeviceToHost, b->stream));
+    EA_HIP(hipStreamSynchronize(b->stream));
+    const unsigned long long *m = b->h_obs.data();
+    const int64_t N = (int64_t)h.job.L * h.job.L * h.job.L;
+    const uint32_t t = h.meas_t[(size_t)k];
+    out->t = t;
+    for (int r = 0; r < 2; ++r) {
+        out->unsat[r] = (int64_t)m[ea::M_UNSAT + r];
+        out->mag[r] = N - 2 * (int64_t)m[ea::M_DOWN + r];
+    }
+    out->overlap = N - 2 * (int64_t)m[ea::M_QDIFF];
+    if (out->autocorr) {
+        for (int r = 0; r < 2; ++r)
+            for (int s = 0; s < h.job.n_tw; ++s)
+                out->autocorr[r * h.job.n_tw + s] =
+                    h.tw[(size_t)s] <= t ? N - 2 * (int64_t)m[ea::M_AUTO + 2 * s + r] : 0;
+        if (out->tw)
+            for (int s = 0; s < h.job.n_tw; ++s) out->tw[s] = h.tw[(size_t)s] <= t ? h.tw[(size_t)s] : 0;
+    }
+    if (out->c4) {
+        const int base = ea::M_AUTO + 2 * h.job.n_tw;
+        for (int i = 0; i < 3 * (h.R + 1); ++i) out->c4[i] = N - 2 * (int64_t)m[base + i];
+    }
+    return EA_OK;
+}
+
+ea_status ea_batch_get_spins(ea_batch *b, int32_t job, int32_t r, int8_t *pm1)
+{
+    if (!b || !pm1) return fail(EA_ERR_ARG, "NULL argument");
+    if (job < 0 || job >= (int32_t)b->jobs.size()) return fail(EA_ERR_ARG, "job %d out of range", job);
+    if (r < 0 || r > 1) return fail(EA_ERR_ARG, "replica %d not 0 or 1", r);
+    const BatchJobHost &h = b->jobs[(size_t)job];
+    std::vector<uint32_t> words(2 * (size_t)h.POS);
+    EA_HIP(hipMemcpyAsync(words.data(), b->buf + h.off_spins + 4 * (size_t)r * 2 * h.POS, 4 * words.size(),
+                          hipMemcpyDeviceToHost, b->stream));
+    EA_HIP(hipStreamSynchronize(b->stream));
+    Layout y = make_layout(h.job.L, 0);
+    const int64_t N = (int64_t)h.job.L * h.job.L * h.job.L;
+    for (int64_t i = 0; i < N; ++i) {
+        SiteAddr a = address_of(y, i);
+        const uint32_t bit = (words[(size_t)a.c * h.POS + a.word] >> a.bit) & 1u;
+        pm1[i] = bit ? (int8_t)-1 : (int8_t)1;
+    }
+    return EA_OK;
+}
+
+}  // extern "C"

@@ -256,6 +256,12 @@ __global__ __launch_bounds__(256) void zero_u64_kernel(unsigned long long *dst, 
     if (i < n) dst[i] = 0ull;
 }
 
+__global__ __launch_bounds__(256) void zero_u32_kernel(uint32_t *dst, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = 0u;
+}
+
 // Device-side sweep counter: set it, or advance it after a block of sweeps.
 __global__ void set_u32_kernel(uint32_t *dst, uint32_t v)
 {
