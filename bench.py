@@ -120,6 +120,9 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=60, help="oracle sweeps for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a device-to-device copy of this many MiB (a known-size kernel "
+                         "for calibrating hardware byte counters) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -134,6 +137,16 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n, "read": n, "written": n}), flush=True)
+        return
 
     jobs = wl.batch_jobs(n_jobs=args.jobs, n_sweeps=args.sweeps)
     flips_per_step = sum(j.flips for j in jobs)
