@@ -8,7 +8,8 @@ replicas each, L drawn from {24, 32, 48, 64}, p from {0.5, 0.3, 0.2}, T from
 log-spaced measurements of energy, magnetisation, overlap, C(t, t_w), C4(r)
 and snapshots at t_w in {10^2, 10^3, 10^4}.  A step regenerates every job's
 couplings and initial spins on the device and runs all jobs to the end in
-one persistent launch.  ps/flip = step time / sum_jobs(sweeps x L^3 x 2).
+one persistent launch; the two are captured as one hipGraph and replayed.
+ps/flip = step time / sum_jobs(sweeps x L^3 x 2).
 
 Plain workload (reported beside it): one L = 64 sample, p = 0.5, T = 0.7,
 the same schedule shape, one kernel launch per half-step.
@@ -108,6 +109,44 @@ def bench_plain(ea, torch, job, steps: int, burst: int):
     }
 
 
+def bench_serving(ea, wl, n_jobs: int, load: float, ps_per_flip_capacity: float):
+    """Poisson stream of jobs (L in {16..64}, p ~ U[0.1,0.5], T ~ U[0.5,1.2],
+    sweeps log-uniform in [1e3, 1e5], log-spaced schedules) offered at
+    `load` times the batched form's measured capacity; continuous batching
+    with admission by an HBM budget."""
+    stream = wl.serve_jobs(n_jobs=n_jobs, sweep_range=(1_000, 100_000), sizes=(16, 24, 32, 48, 64))
+    mean_flips = sum(j.flips for _, j in stream) / len(stream)
+    gap_s = mean_flips * ps_per_flip_capacity * 1e-12 / load
+    budget = 256 << 20
+    srv = ea.Server(hbm_budget=budget, max_resident=512)
+    srv.start()
+    t0 = time.perf_counter()
+    for arrival, job in stream:
+        delay = t0 + arrival * gap_s - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        srv.submit(job)
+    srv.drain(1200)
+    wall = time.perf_counter() - t0
+    srv.stop()
+    st = srv.stats()
+    total = sum(j.flips for _, j in stream)
+    srv.close()
+    return {
+        "workload": f"{n_jobs} Poisson arrivals at load {load} of the batched capacity (mean gap "
+                    f"{gap_s * 1e3:.2f} ms), L in {{16,24,32,48,64}}, p~U[0.1,0.5], T~U[0.5,1.2], "
+                    f"sweeps log-uniform in [1e3,1e5], 20 log-spaced measurements; HBM budget {budget >> 20} MiB",
+        "p50_latency_s": round(st["p50_latency_s"], 4),
+        "p99_latency_s": round(st["p99_latency_s"], 4),
+        "mean_latency_s": round(st["mean_latency_s"], 4),
+        "ps_per_flip_busy": round(st["ps_per_flip"], 4),
+        "ps_per_flip_wall": round(wall / total * 1e12, 4),
+        "epochs": int(st["epochs"]),
+        "hbm_peak_mib": round(st["hbm_peak"] / 2 ** 20, 1),
+        "wall_s": round(wall, 3),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,6 +159,8 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=60, help="oracle sweeps for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--serve-jobs", type=int, default=300, help="jobs in the serving leg (0 = skip)")
+    ap.add_argument("--serve-load", type=float, default=0.8, help="offered load of the serving leg")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (a known-size kernel "
                          "for calibrating hardware byte counters) and exit")
@@ -152,10 +193,10 @@ def main():
     flips_per_step = sum(j.flips for j in jobs)
     batch = ea.Batch(jobs)
     stream = batch.stream
+    batch.capture()  # reset + full run as one hipGraph
 
     for i in range(args.warmup):
-        batch.reset()
-        batch.run()
+        batch.replay()
         log(f"warmup {i + 1}/{args.warmup} done")
 
     torch.cuda.synchronize()
@@ -164,13 +205,12 @@ def main():
     run_ms = []
     w0 = time.perf_counter()
     for i in range(args.steps):
-        batch.reset()
         ev0.record(stream)
-        batch.run()
+        batch.replay()
         ev1.record(stream)
         torch.cuda.synchronize()
         run_ms.append(ev0.elapsed_time(ev1))
-        log(f"step {i + 1}/{args.steps} done ({run_ms[-1]:.1f} ms in the batch launch)")
+        log(f"step {i + 1}/{args.steps} done ({run_ms[-1]:.1f} ms for the graph: reset + batch launch)")
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     ms_per_step = wall * 1e3 / args.steps
@@ -205,7 +245,8 @@ def main():
         "config": {
             "workload": f"batched form: {len(jobs)} samples x 2 replicas, L in {Ls}, p in {{0.5,0.3,0.2}}, "
                         f"T in {{0.6,0.8,1.0}}, seeds 0..{len(jobs) - 1}, {args.sweeps} sweeps each, "
-                        f"20 log-spaced measurements + tw {{1e2,1e3,1e4}}, one persistent launch",
+                        f"20 log-spaced measurements + tw {{1e2,1e3,1e4}}, one persistent launch (graph: "
+                        f"device-side regeneration of every job + the launch)",
             "form": "batched",
             "jobs": len(jobs),
             "sweeps": args.sweeps,
@@ -227,6 +268,9 @@ def main():
     }
     batch.close()
 
+    if args.serve_jobs:
+        log("serving form ...")
+        out["serving"] = bench_serving(ea, wl, args.serve_jobs, args.serve_load, ps_per_flip)
     if not args.no_plain:
         log("plain form ...")
         plain = bench_plain(ea, torch, wl.mid_job(args.sweeps), args.plain_steps, args.burst)

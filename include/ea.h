@@ -191,6 +191,11 @@ ea_status ea_batch_reset(ea_batch *b);
  * measurements scheduled on the way; returns when the launch has finished. */
 ea_status ea_batch_run(ea_batch *b, uint64_t t_stop);
 
+/* Capture "reset every job, then run every job to its end" as a hipGraph;
+ * ea_batch_replay launches it and waits.  Replays give identical results. */
+ea_status ea_batch_capture(ea_batch *b);
+ea_status ea_batch_replay(ea_batch *b);
+
 /* Sweeps done by job j. */
 ea_status ea_batch_time(ea_batch *b, int32_t job, uint64_t *t);
 
@@ -201,6 +206,78 @@ ea_status ea_batch_result(ea_batch *b, int32_t job, int32_t k, ea_obs *out);
 
 /* Current spins of replica r of job j, int8 +-1 in canonical order [L^3]. */
 ea_status ea_batch_get_spins(ea_batch *b, int32_t job, int32_t r, int8_t *pm1);
+
+/* ------------------------------------------------------------------------
+ * Serving form: continuous batching of a stream of jobs (L <= 64, as for
+ * the batched form).  Jobs are admitted first-come first-served while their
+ * device footprint fits hbm_budget and fewer than max_resident are resident;
+ * each epoch is one persistent launch that advances every resident job by
+ * about epoch_site_sweeps site updates per replica (at least one sweep),
+ * taking its scheduled snapshots and measurements.  Finished jobs hand their
+ * results to the host and free their memory; waiting jobs join at the next
+ * epoch.  A job's results are identical to a run alone (ea_create or
+ * ea_batch_create) with the same parameters.  The calls are thread-safe:
+ * jobs can be submitted while a worker thread (ea_server_start) runs the
+ * epochs.
+ */
+typedef struct ea_server ea_server;
+
+typedef struct {
+    size_t hbm_budget;           /* bytes of device memory for resident jobs */
+    int32_t max_resident;        /* resident jobs at most (1..4096) */
+    int32_t max_pending;         /* waiting jobs at most; submit returns EA_ERR_BUSY beyond */
+    uint64_t epoch_site_sweeps;  /* site updates per replica per epoch; 0 = 64^4 */
+    void *stream;                /* hipStream_t, or NULL for a library stream */
+} ea_server_opts;
+
+typedef struct {
+    uint64_t submitted, admitted, completed, epochs;
+    int32_t resident, pending;
+    double p50_latency_s, p99_latency_s, mean_latency_s, max_latency_s; /* submit -> results on host */
+    double flips;         /* attempted flips done (both replicas) */
+    double busy_s;        /* time inside epoch launches */
+    double wall_s;        /* since the first submit */
+    double ps_per_flip;   /* busy_s / flips */
+    size_t hbm_in_use, hbm_peak;
+} ea_server_report;
+
+enum { EA_JOB_PENDING = 0, EA_JOB_RUNNING = 1, EA_JOB_DONE = 2 };
+
+ea_status ea_server_create(const ea_server_opts *opts, ea_server **out);
+void ea_server_destroy(ea_server *s);
+
+/* Device bytes a job occupies while resident. */
+ea_status ea_server_footprint(const ea_job *job, size_t *bytes);
+
+/* Queue a job (its schedule is copied); *id names it from now on.
+ * EA_ERR_BUSY if max_pending jobs already wait; EA_ERR_ARG for an invalid job
+ * or one larger than the whole budget. */
+ea_status ea_server_submit(ea_server *s, const ea_job *job, uint64_t *id);
+
+/* Run one epoch on the calling thread (*progressed = 0 if there was nothing
+ * to run).  EA_ERR_STATE while a worker thread runs. */
+ea_status ea_server_step(ea_server *s, int32_t *progressed);
+
+/* Run epochs on a worker thread until ea_server_stop. */
+ea_status ea_server_start(ea_server *s);
+ea_status ea_server_stop(ea_server *s);
+
+/* Wait until every submitted job is done (runs epochs itself when no worker
+ * runs).  EA_ERR_BUSY on timeout. */
+ea_status ea_server_drain(ea_server *s, double timeout_s);
+
+/* EA_JOB_PENDING, EA_JOB_RUNNING or EA_JOB_DONE. */
+ea_status ea_server_poll(ea_server *s, uint64_t id, int32_t *state);
+
+/* Measurement k of a finished job (ea_obs as for ea_batch_result), and the
+ * time from its submission to its results reaching the host. */
+ea_status ea_server_result(ea_server *s, uint64_t id, int32_t k, ea_obs *out);
+ea_status ea_server_latency(ea_server *s, uint64_t id, double *seconds);
+
+/* Forget a finished job's results. */
+ea_status ea_server_release(ea_server *s, uint64_t id);
+
+ea_status ea_server_stats(ea_server *s, ea_server_report *out);
 
 #ifdef __cplusplus
 }

@@ -15,7 +15,7 @@ import numpy as np
 from . import abi
 from .abi import EAError
 
-__all__ = ["Sim", "Batch", "EAError", "thresholds", "footprint", "version"]
+__all__ = ["Sim", "Batch", "Server", "EAError", "thresholds", "footprint", "version"]
 
 
 def version() -> str:
@@ -193,6 +193,25 @@ def _job_struct(job, keep):
     return j
 
 
+def _obs_buffers(L, n_tw, c4, o):
+    tw = np.zeros(max(n_tw, 1), dtype=np.uint64)
+    ac = np.zeros((2, max(n_tw, 1)), dtype=np.int64)
+    c4a = np.zeros((3, L // 2 + 1), dtype=np.int64)
+    if n_tw:
+        o.n_tw = n_tw
+        o.tw = abi.ptr(tw, ctypes.c_uint64)
+        o.autocorr = abi.ptr(ac, ctypes.c_int64)
+    if c4:
+        o.rmax = L // 2
+        o.c4 = abi.ptr(c4a, ctypes.c_int64)
+    return tw, ac, c4a
+
+
+def _obs_from(o, n_tw, tw, ac, c4a, c4):
+    return Obs(int(o.t), np.array(o.unsat[:], dtype=np.int64), np.array(o.mag[:], dtype=np.int64),
+               int(o.overlap), tw[:n_tw].copy(), ac[:, :n_tw].copy(), c4a if c4 else None)
+
+
 class Batch:
     """Many independent runs (L <= 64) in one persistent launch per span."""
 
@@ -238,6 +257,14 @@ class Batch:
             t_stop = max(j.n_sweeps for j in self.jobs)
         abi.check(abi.lib().ea_batch_run(self._h, int(t_stop)))
 
+    def capture(self):
+        """Capture reset + full run as a hipGraph (see replay)."""
+        abi.check(abi.lib().ea_batch_capture(self._h))
+
+    def replay(self):
+        """Reset every job and run it to the end by replaying the graph."""
+        abi.check(abi.lib().ea_batch_replay(self._h))
+
     def time(self, job: int) -> int:
         t = ctypes.c_uint64(0)
         abi.check(abi.lib().ea_batch_time(self._h, int(job), ctypes.byref(t)))
@@ -245,23 +272,111 @@ class Batch:
 
     def result(self, job: int, k: int, c4: bool = True) -> Obs:
         J = self.jobs[job]
-        n_tw = len(J.tw)
         o = abi.Obs()
-        tw = np.zeros(max(n_tw, 1), dtype=np.uint64)
-        ac = np.zeros((2, max(n_tw, 1)), dtype=np.int64)
-        c4a = np.zeros((3, J.L // 2 + 1), dtype=np.int64)
-        if n_tw:
-            o.n_tw = n_tw
-            o.tw = abi.ptr(tw, ctypes.c_uint64)
-            o.autocorr = abi.ptr(ac, ctypes.c_int64)
-        if c4:
-            o.rmax = J.L // 2
-            o.c4 = abi.ptr(c4a, ctypes.c_int64)
+        bufs = _obs_buffers(J.L, len(J.tw), c4, o)
         abi.check(abi.lib().ea_batch_result(self._h, int(job), int(k), ctypes.byref(o)))
-        return Obs(int(o.t), np.array(o.unsat[:], dtype=np.int64), np.array(o.mag[:], dtype=np.int64),
-                   int(o.overlap), tw[:n_tw].copy(), ac[:, :n_tw].copy(), c4a if c4 else None)
+        return _obs_from(o, len(J.tw), *bufs, c4)
 
     def spins(self, job: int, r: int) -> np.ndarray:
         out = np.zeros(self.jobs[job].L ** 3, dtype=np.int8)
         abi.check(abi.lib().ea_batch_get_spins(self._h, int(job), int(r), abi.ptr(out, ctypes.c_int8)))
         return out
+
+
+JOB_PENDING, JOB_RUNNING, JOB_DONE = 0, 1, 2
+
+
+class Server:
+    """Continuous batching of a job stream (see ea_server_* in ea.h)."""
+
+    def __init__(self, hbm_budget: int, max_resident: int = 512, max_pending: int = 100000,
+                 epoch_site_sweeps: int = 0, use_torch: bool = True):
+        opts = abi.ServerOpts()
+        opts.hbm_budget = int(hbm_budget)
+        opts.max_resident = int(max_resident)
+        opts.max_pending = int(max_pending)
+        opts.epoch_site_sweeps = int(epoch_site_sweeps)
+        self._stream = None
+        if use_torch:
+            try:
+                import torch
+                if torch.cuda.is_available():
+                    self._stream = torch.cuda.Stream()
+                    opts.stream = ctypes.c_void_p(self._stream.cuda_stream)
+            except ImportError:
+                pass
+        h = ctypes.c_void_p()
+        abi.check(abi.lib().ea_server_create(ctypes.byref(opts), ctypes.byref(h)))
+        self._h = h
+        self.jobs = {}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            abi.lib().ea_server_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def stream(self):
+        return self._stream
+
+    @staticmethod
+    def footprint(job) -> int:
+        keep = []
+        j = _job_struct(job, keep)
+        out = ctypes.c_size_t(0)
+        abi.check(abi.lib().ea_server_footprint(ctypes.byref(j), ctypes.byref(out)))
+        return int(out.value)
+
+    def submit(self, job) -> int:
+        keep = []
+        j = _job_struct(job, keep)
+        jid = ctypes.c_uint64(0)
+        abi.check(abi.lib().ea_server_submit(self._h, ctypes.byref(j), ctypes.byref(jid)))
+        self.jobs[int(jid.value)] = job
+        return int(jid.value)
+
+    def step(self) -> bool:
+        p = ctypes.c_int32(0)
+        abi.check(abi.lib().ea_server_step(self._h, ctypes.byref(p)))
+        return bool(p.value)
+
+    def start(self):
+        abi.check(abi.lib().ea_server_start(self._h))
+
+    def stop(self):
+        abi.check(abi.lib().ea_server_stop(self._h))
+
+    def drain(self, timeout_s: float = 600.0):
+        abi.check(abi.lib().ea_server_drain(self._h, float(timeout_s)))
+
+    def poll(self, jid: int) -> int:
+        st = ctypes.c_int32(0)
+        abi.check(abi.lib().ea_server_poll(self._h, int(jid), ctypes.byref(st)))
+        return int(st.value)
+
+    def result(self, jid: int, k: int, c4: bool = True) -> Obs:
+        J = self.jobs[jid]
+        o = abi.Obs()
+        bufs = _obs_buffers(J.L, len(J.tw), c4, o)
+        abi.check(abi.lib().ea_server_result(self._h, int(jid), int(k), ctypes.byref(o)))
+        return _obs_from(o, len(J.tw), *bufs, c4)
+
+    def latency(self, jid: int) -> float:
+        v = ctypes.c_double(0)
+        abi.check(abi.lib().ea_server_latency(self._h, int(jid), ctypes.byref(v)))
+        return float(v.value)
+
+    def release(self, jid: int):
+        abi.check(abi.lib().ea_server_release(self._h, int(jid)))
+        self.jobs.pop(jid, None)
+
+    def stats(self) -> dict:
+        r = abi.ServerReport()
+        abi.check(abi.lib().ea_server_stats(self._h, ctypes.byref(r)))
+        return {name: getattr(r, name) for name, _ in abi.ServerReport._fields_}

@@ -71,6 +71,37 @@ class BatchOpts(ctypes.Structure):
     _fields_ = [("stream", ctypes.c_void_p)]
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [
+        ("hbm_budget", ctypes.c_size_t),
+        ("max_resident", ctypes.c_int32),
+        ("max_pending", ctypes.c_int32),
+        ("epoch_site_sweeps", ctypes.c_uint64),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class ServerReport(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_uint64),
+        ("admitted", ctypes.c_uint64),
+        ("completed", ctypes.c_uint64),
+        ("epochs", ctypes.c_uint64),
+        ("resident", ctypes.c_int32),
+        ("pending", ctypes.c_int32),
+        ("p50_latency_s", ctypes.c_double),
+        ("p99_latency_s", ctypes.c_double),
+        ("mean_latency_s", ctypes.c_double),
+        ("max_latency_s", ctypes.c_double),
+        ("flips", ctypes.c_double),
+        ("busy_s", ctypes.c_double),
+        ("wall_s", ctypes.c_double),
+        ("ps_per_flip", ctypes.c_double),
+        ("hbm_in_use", ctypes.c_size_t),
+        ("hbm_peak", ctypes.c_size_t),
+    ]
+
+
 # name -> (restype, argtypes)
 _SIGS = {
     "ea_last_error": (ctypes.c_char_p, []),
@@ -97,10 +128,25 @@ _SIGS = {
     "ea_batch_destroy": (None, [ctypes.c_void_p]),
     "ea_batch_reset": (ctypes.c_int, [ctypes.c_void_p]),
     "ea_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "ea_batch_capture": (ctypes.c_int, [ctypes.c_void_p]),
+    "ea_batch_replay": (ctypes.c_int, [ctypes.c_void_p]),
     "ea_batch_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]),
     "ea_batch_result": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Obs)]),
     "ea_batch_get_spins": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                           ctypes.POINTER(ctypes.c_int8)]),
+    "ea_server_create": (ctypes.c_int, [ctypes.POINTER(ServerOpts), ctypes.POINTER(ctypes.c_void_p)]),
+    "ea_server_destroy": (None, [ctypes.c_void_p]),
+    "ea_server_footprint": (ctypes.c_int, [ctypes.POINTER(Job), ctypes.POINTER(ctypes.c_size_t)]),
+    "ea_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Job), ctypes.POINTER(ctypes.c_uint64)]),
+    "ea_server_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    "ea_server_start": (ctypes.c_int, [ctypes.c_void_p]),
+    "ea_server_stop": (ctypes.c_int, [ctypes.c_void_p]),
+    "ea_server_drain": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
+    "ea_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32)]),
+    "ea_server_result": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.POINTER(Obs)]),
+    "ea_server_latency": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]),
+    "ea_server_release": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "ea_server_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerReport)]),
 }
 
 _lib = None

@@ -541,3 +541,4 @@ ea_status ea_set_bonds(ea_sim *s, const int8_t *pm1)
 }  // extern "C"
 
 #include "ea_batch_api.h"
+#include "ea_server_api.h"

@@ -1,12 +1,14 @@
-// ea_batch_api.h -- host side of the batched form (ea_batch_* in ea.h).
-// Included once, at the end of ea_api.hip, so that the whole library is one
-// translation unit and shares its helpers.
+// ea_batch_api.h -- host side of the batched form (ea_batch_* in ea.h) and
+// the per-job helpers the serving loop shares with it.  Included once, at the
+// end of ea_api.hip, so that the whole library is one translation unit.
 #pragma once
 
 #include <numeric>
 
 namespace {
 
+// Host record of one job of the batched kernel: parameters, schedule,
+// geometry and the layout of its device region (offsets from `base`).
 struct BatchJobHost {
     ea_job job{};             // parameters (schedule pointers not kept)
     std::vector<uint32_t> meas_t, tw;
@@ -14,7 +16,8 @@ struct BatchJobHost {
     uint32_t thr[3] = {0, 0, 0};
     uint64_t pcut = 0;
     size_t off_spins = 0, off_bonds = 0, off_snaps = 0, off_mspins = 0, off_obs = 0, off_arrive = 0,
-           off_tnow = 0, off_meas_t = 0, off_tw = 0;
+           off_tnow = 0, off_meas_t = 0, off_tw = 0, bytes = 0;
+    char *base = nullptr;     // device region of this job
     uint64_t t_host = 0;      // sweeps done (host mirror)
     bool started = false;     // a span has run (events at t = 0 are taken)
 };
@@ -51,6 +54,197 @@ ea_status copy_schedule(const uint64_t *src, int32_t n, uint64_t n_sweeps, const
     return EA_OK;
 }
 
+// Validate a job and lay out its device region (offsets from 0).
+ea_status plan_job(const ea_job &in, int index, BatchJobHost &h)
+{
+    if (!batch_L_ok(in.L))
+        return fail(EA_ERR_ARG, "job %d: L=%d must be a multiple of 8 in [8, %d] for the batched form", index,
+                    in.L, ea::kBatchMaxL);
+    if (!(in.p >= 0.0 && in.p <= 1.0)) return fail(EA_ERR_ARG, "job %d: p=%g outside [0, 1]", index, in.p);
+    if (!(in.T >= 0.0) || !std::isfinite(in.T))
+        return fail(EA_ERR_ARG, "job %d: T=%g must be finite and >= 0", index, in.T);
+    if (in.n_sweeps >= (1ull << 32)) return fail(EA_ERR_ARG, "job %d: n_sweeps must be below 2^32", index);
+    if (in.n_tw > kMaxSlots) return fail(EA_ERR_ARG, "job %d: n_tw=%d above %d", index, in.n_tw, kMaxSlots);
+    ea_status st = copy_schedule(in.meas_t, in.n_meas, in.n_sweeps, "meas_t", h.meas_t);
+    if (st == EA_OK) st = copy_schedule(in.tw, in.n_tw, in.n_sweeps, "tw", h.tw);
+    if (st != EA_OK) return st;
+    h.job = in;
+    h.job.meas_t = nullptr;
+    h.job.tw = nullptr;
+    h.R = in.L / 2;
+    h.RW = words_per_row(h.R);
+    h.W = h.R / h.RW;
+    h.POS = in.L * in.L * h.RW;
+    h.obs_stride = ea::M_AUTO + 2 * in.n_tw + 3 * (h.R + 1);
+    host_thresholds(in.T, h.thr);
+    h.pcut = (uint64_t)std::floor(std::ldexp(in.p, 32));
+    const size_t spin4 = 4 * (size_t)h.POS;  // words of [replica][colour]
+    size_t off = 0;
+    h.off_spins = off;
+    off += 4 * spin4;
+    h.off_bonds = off = align256(off);
+    off += 4 * 6 * (size_t)h.POS;
+    h.off_snaps = off = align256(off);
+    off += 4 * spin4 * (size_t)in.n_tw;
+    h.off_mspins = off = align256(off);
+    off += 4 * spin4 * (size_t)in.n_meas;
+    h.off_obs = off = align256(off);
+    off += 8 * (size_t)in.n_meas * (size_t)h.obs_stride;
+    h.off_arrive = off = align256(off);
+    off += 4 * (size_t)in.n_meas;
+    h.off_tnow = off;
+    off += 8;
+    h.off_meas_t = off = align256(off);
+    off += 4 * (size_t)in.n_meas;
+    h.off_tw = off = align256(off);
+    off += 4 * (size_t)in.n_tw;
+    h.bytes = align256(off);
+    return EA_OK;
+}
+
+ea::BatchJobDev make_job_dev(const BatchJobHost &h)
+{
+    ea::BatchJobDev d{};
+    d.L = h.job.L;
+    d.k0 = (uint32_t)(h.job.seed & 0xffffffffu);
+    d.k1 = (uint32_t)(h.job.seed >> 32);
+    d.sample = h.job.sample;
+    d.thr1 = h.thr[0];
+    d.thr2 = h.thr[1];
+    d.thr3 = h.thr[2];
+    d.n_meas = h.job.n_meas;
+    d.n_tw = h.job.n_tw;
+    d.obs_stride = h.obs_stride;
+    d.spins = (uint32_t *)(h.base + h.off_spins);
+    d.bonds = (const uint32_t *)(h.base + h.off_bonds);
+    d.snaps = (uint32_t *)(h.base + h.off_snaps);
+    d.mspins = (uint32_t *)(h.base + h.off_mspins);
+    d.meas_t = (const uint32_t *)(h.base + h.off_meas_t);
+    d.tw_t = (const uint32_t *)(h.base + h.off_tw);
+    d.obs = (unsigned long long *)(h.base + h.off_obs);
+    d.arrive = (uint32_t *)(h.base + h.off_arrive);
+    d.t_now = (uint32_t *)(h.base + h.off_tnow);
+    return d;
+}
+
+// Copy the schedule to the job's region (the host vectors stay alive with h).
+ea_status upload_schedule(const BatchJobHost &h, hipStream_t stream)
+{
+    if (!h.meas_t.empty())
+        EA_HIP(hipMemcpyAsync(h.base + h.off_meas_t, h.meas_t.data(), 4 * h.meas_t.size(), hipMemcpyHostToDevice,
+                              stream));
+    if (!h.tw.empty())
+        EA_HIP(hipMemcpyAsync(h.base + h.off_tw, h.tw.data(), 4 * h.tw.size(), hipMemcpyHostToDevice, stream));
+    return EA_OK;
+}
+
+// Generate the job's couplings and initial spins and clear its counters.
+ea_status init_job_device(BatchJobHost &h, hipStream_t stream)
+{
+    ea::Lattice lat;
+    lat.spins = (uint32_t *)(h.base + h.off_spins);
+    lat.bonds = (uint32_t *)(h.base + h.off_bonds);
+    ea::Geom g;
+    g.L = h.job.L;
+    g.R = h.R;
+    g.RW = h.RW;
+    g.rows = h.job.L * h.job.L;
+    g.plane = h.POS;
+    ea_status st = launch_init_lattice(lat, g, h.W, h.job.seed, h.job.sample, h.pcut, stream);
+    if (st != EA_OK) return st;
+    const size_t n_obs = (size_t)h.job.n_meas * (size_t)h.obs_stride;
+    if (n_obs)
+        hipLaunchKernelGGL(ea::zero_u64_kernel, dim3(blocks_for(n_obs)), dim3(256), 0, stream,
+                           (unsigned long long *)(h.base + h.off_obs), n_obs);
+    // arrive[n_meas] and t_now[2] are contiguous 32-bit words
+    const size_t n_ctl32 = (size_t)h.job.n_meas + 2;
+    hipLaunchKernelGGL(ea::zero_u32_kernel, dim3(blocks_for(n_ctl32)), dim3(256), 0, stream,
+                       (uint32_t *)(h.base + h.off_arrive), n_ctl32);
+    EA_HIP(hipGetLastError());
+    h.t_host = 0;
+    h.started = false;
+    return EA_OK;
+}
+
+// Turn measurement k's popcount counters m[obs_stride] into an ea_obs.
+ea_status fill_obs(const BatchJobHost &h, const unsigned long long *m, int32_t k, ea_obs *out)
+{
+    if (out->autocorr && out->n_tw != h.job.n_tw)
+        return fail(EA_ERR_ARG, "n_tw=%d but the job has %d snapshot times", out->n_tw, h.job.n_tw);
+    if (out->c4 && out->rmax != h.R) return fail(EA_ERR_ARG, "rmax=%d but L/2=%d", out->rmax, h.R);
+    const int64_t N = (int64_t)h.job.L * h.job.L * h.job.L;
+    const uint32_t t = h.meas_t[(size_t)k];
+    out->t = t;
+    for (int r = 0; r < 2; ++r) {
+        out->unsat[r] = (int64_t)m[ea::M_UNSAT + r];
+        out->mag[r] = N - 2 * (int64_t)m[ea::M_DOWN + r];
+    }
+    out->overlap = N - 2 * (int64_t)m[ea::M_QDIFF];
+    if (out->autocorr) {
+        for (int r = 0; r < 2; ++r)
+            for (int s = 0; s < h.job.n_tw; ++s)
+                out->autocorr[r * h.job.n_tw + s] =
+                    h.tw[(size_t)s] <= t ? N - 2 * (int64_t)m[ea::M_AUTO + 2 * s + r] : 0;
+        if (out->tw)
+            for (int s = 0; s < h.job.n_tw; ++s) out->tw[s] = h.tw[(size_t)s] <= t ? h.tw[(size_t)s] : 0;
+    }
+    if (out->c4) {
+        const int base = ea::M_AUTO + 2 * h.job.n_tw;
+        for (int i = 0; i < 3 * (h.R + 1); ++i) out->c4[i] = N - 2 * (int64_t)m[base + i];
+    }
+    return EA_OK;
+}
+
+// Unpack replica r's spins from a device region into int8 +-1.
+ea_status read_job_spins(const BatchJobHost &h, int32_t r, int8_t *pm1, hipStream_t stream)
+{
+    std::vector<uint32_t> words(2 * (size_t)h.POS);
+    EA_HIP(hipMemcpyAsync(words.data(), h.base + h.off_spins + 4 * (size_t)r * 2 * h.POS, 4 * words.size(),
+                          hipMemcpyDeviceToHost, stream));
+    EA_HIP(hipStreamSynchronize(stream));
+    Layout y = make_layout(h.job.L, 0);
+    const int64_t N = (int64_t)h.job.L * h.job.L * h.job.L;
+    for (int64_t i = 0; i < N; ++i) {
+        SiteAddr a = address_of(y, i);
+        const uint32_t bit = (words[(size_t)a.c * h.POS + a.word] >> a.bit) & 1u;
+        pm1[i] = bit ? (int8_t)-1 : (int8_t)1;
+    }
+    return EA_OK;
+}
+
+// Check that a launch with this much dynamic LDS fits one workgroup, and
+// allow it (the kernel's default cap is lower).
+ea_status prepare_batch_lds(size_t dyn_bytes)
+{
+    int dev = 0, lds_limit = 0;
+    EA_HIP(hipGetDevice(&dev));
+    EA_HIP(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    if (dyn_bytes + 4 * (size_t)ea::kSelectTableWords > (size_t)lds_limit)
+        return fail(EA_ERR_ARG, "the largest job needs %zu bytes of LDS, the device offers %d", dyn_bytes,
+                    lds_limit);
+    EA_HIP(hipFuncSetAttribute((const void *)ea::batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)dyn_bytes));
+    return EA_OK;
+}
+
+// Units of a set of jobs, largest remaining work first (the longest units
+// start first); the two replicas of a job are adjacent so that they reach
+// each measurement at about the same time.
+void order_units(const std::vector<BatchJobHost *> &jobs, const std::vector<uint64_t> &span,
+                 std::vector<ea::BatchUnit> &units)
+{
+    std::vector<int32_t> order(jobs.size());
+    std::iota(order.begin(), order.end(), 0);
+    auto work = [&](int32_t a) {
+        const double L = (double)jobs[(size_t)a]->job.L;
+        return L * L * L * (double)span[(size_t)a];
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) { return work(a) > work(c); });
+    units.clear();
+    for (int32_t j : order)
+        for (int32_t r = 0; r < 2; ++r) units.push_back(ea::BatchUnit{j, r, 0u, 1});
+}
+
 }  // namespace
 
 struct ea_batch {
@@ -61,43 +255,13 @@ struct ea_batch {
     size_t bytes = 0;
     ea::BatchJobDev *d_jobs = nullptr;
     ea::BatchUnit *d_units = nullptr;
+    ea::BatchUnit *d_units_graph = nullptr;  // whole-run units read by the captured graph
     std::vector<ea::BatchUnit> units;
     size_t lds_bytes = 0;
     std::vector<unsigned long long> h_obs;  // staging for ea_batch_result
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
 };
-
-namespace {
-
-ea_status batch_reset_device(ea_batch *b)
-{
-    for (auto &h : b->jobs) {
-        ea::Lattice lat;
-        lat.spins = (uint32_t *)(b->buf + h.off_spins);
-        lat.bonds = (uint32_t *)(b->buf + h.off_bonds);
-        ea::Geom g;
-        g.L = h.job.L;
-        g.R = h.R;
-        g.RW = h.RW;
-        g.rows = h.job.L * h.job.L;
-        g.plane = h.POS;
-        ea_status st = launch_init_lattice(lat, g, h.W, h.job.seed, h.job.sample, h.pcut, b->stream);
-        if (st != EA_OK) return st;
-        const size_t n_obs = (size_t)h.job.n_meas * (size_t)h.obs_stride;
-        if (n_obs)
-            hipLaunchKernelGGL(ea::zero_u64_kernel, dim3(blocks_for(n_obs)), dim3(256), 0, b->stream,
-                               (unsigned long long *)(b->buf + h.off_obs), n_obs);
-        // arrive[n_meas] and t_now[2] are contiguous 32-bit words
-        const size_t n_ctl32 = (size_t)h.job.n_meas + 2;
-        hipLaunchKernelGGL(ea::zero_u32_kernel, dim3(blocks_for(n_ctl32)), dim3(256), 0, b->stream,
-                           (uint32_t *)(b->buf + h.off_arrive), n_ctl32);
-        h.t_host = 0;
-        h.started = false;
-    }
-    EA_HIP(hipGetLastError());
-    return EA_OK;
-}
-
-}  // namespace
 
 extern "C" {
 
@@ -111,78 +275,32 @@ ea_status ea_batch_create(const ea_job *jobs, int32_t n_jobs, const ea_batch_opt
     b->jobs.resize((size_t)n_jobs);
     size_t off = 0;
     int max_lds = 0;
+    std::vector<size_t> region((size_t)n_jobs);
     for (int32_t j = 0; j < n_jobs; ++j) {
-        const ea_job &in = jobs[j];
-        BatchJobHost &h = b->jobs[(size_t)j];
-        ea_status st = EA_OK;
-        if (!batch_L_ok(in.L))
-            st = fail(EA_ERR_ARG, "job %d: L=%d must be a multiple of 8 in [8, %d] for the batched form", j,
-                      in.L, ea::kBatchMaxL);
-        else if (!(in.p >= 0.0 && in.p <= 1.0))
-            st = fail(EA_ERR_ARG, "job %d: p=%g outside [0, 1]", j, in.p);
-        else if (!(in.T >= 0.0) || !std::isfinite(in.T))
-            st = fail(EA_ERR_ARG, "job %d: T=%g must be finite and >= 0", j, in.T);
-        else if (in.n_sweeps >= (1ull << 32))
-            st = fail(EA_ERR_ARG, "job %d: n_sweeps must be below 2^32", j);
-        else if (in.n_tw > kMaxSlots)
-            st = fail(EA_ERR_ARG, "job %d: n_tw=%d above %d", j, in.n_tw, kMaxSlots);
-        if (st == EA_OK) st = copy_schedule(in.meas_t, in.n_meas, in.n_sweeps, "meas_t", h.meas_t);
-        if (st == EA_OK) st = copy_schedule(in.tw, in.n_tw, in.n_sweeps, "tw", h.tw);
+        ea_status st = plan_job(jobs[j], j, b->jobs[(size_t)j]);
         if (st != EA_OK) {
             delete b;
             return st;
         }
-        h.job = in;
-        h.job.meas_t = nullptr;
-        h.job.tw = nullptr;
-        h.R = in.L / 2;
-        h.RW = words_per_row(h.R);
-        h.W = h.R / h.RW;
-        h.POS = in.L * in.L * h.RW;
-        h.obs_stride = ea::M_AUTO + 2 * in.n_tw + 3 * (h.R + 1);
-        host_thresholds(in.T, h.thr);
-        h.pcut = (uint64_t)std::floor(std::ldexp(in.p, 32));
-        const size_t spin4 = 4 * (size_t)h.POS;  // words of [replica][colour]
-        h.off_spins = off = align256(off);
-        off += 4 * spin4;
-        h.off_bonds = off = align256(off);
-        off += 4 * 6 * (size_t)h.POS;
-        h.off_snaps = off = align256(off);
-        off += 4 * spin4 * (size_t)in.n_tw;
-        h.off_mspins = off = align256(off);
-        off += 4 * spin4 * (size_t)in.n_meas;
-        h.off_obs = off = align256(off);
-        off += 8 * (size_t)in.n_meas * (size_t)h.obs_stride;
-        h.off_arrive = off = align256(off);
-        off += 4 * (size_t)in.n_meas;
-        h.off_tnow = off;
-        off += 8;
-        h.off_meas_t = off = align256(off);
-        off += 4 * (size_t)in.n_meas;
-        h.off_tw = off = align256(off);
-        off += 4 * (size_t)in.n_tw;
-        max_lds = std::max(max_lds, batch_lds_words(in.L));
+        region[(size_t)j] = off = align256(off);
+        off += b->jobs[(size_t)j].bytes;
+        max_lds = std::max(max_lds, batch_lds_words(jobs[j].L));
     }
     const size_t off_jobs = align256(off);
     off = off_jobs + sizeof(ea::BatchJobDev) * (size_t)n_jobs;
     const size_t off_units = align256(off);
     off = off_units + sizeof(ea::BatchUnit) * 2 * (size_t)n_jobs;
+    const size_t off_units_graph = align256(off);
+    off = off_units_graph + sizeof(ea::BatchUnit) * 2 * (size_t)n_jobs;
     b->bytes = align256(off);
-    b->lds_bytes = ((size_t)max_lds + 16) * 4;
+    b->lds_bytes = (size_t)max_lds * 4;  // dynamic part; the select tables are static
 
-    int dev = 0, lds_limit = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-    if (e != hipSuccess) {
+    ea_status st = prepare_batch_lds(b->lds_bytes);
+    if (st != EA_OK) {
         delete b;
-        return fail(EA_ERR_DEVICE, "device query: %s", hipGetErrorString(e));
+        return st;
     }
-    if (b->lds_bytes > (size_t)lds_limit) {
-        const size_t need = b->lds_bytes;
-        delete b;
-        return fail(EA_ERR_ARG, "the largest job needs %zu bytes of LDS, the device offers %d", need, lds_limit);
-    }
-
+    hipError_t e;
     if (opts && opts->stream) {
         b->stream = (hipStream_t)opts->stream;
     } else {
@@ -198,71 +316,33 @@ ea_status ea_batch_create(const ea_job *jobs, int32_t n_jobs, const ea_batch_opt
         ea_batch_destroy(b);
         return fail(EA_ERR_NOMEM, "hipMalloc(%zu): %s", b->bytes, hipGetErrorString(e));
     }
-    e = hipFuncSetAttribute((const void *)ea::batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)b->lds_bytes);
-    if (e != hipSuccess) {
-        ea_batch_destroy(b);
-        return fail(EA_ERR_DEVICE, "hipFuncSetAttribute: %s", hipGetErrorString(e));
-    }
-
-    // Job table and schedules.
     std::vector<ea::BatchJobDev> dj((size_t)n_jobs);
+    std::vector<BatchJobHost *> ptrs;
+    std::vector<uint64_t> span;
     for (int32_t j = 0; j < n_jobs; ++j) {
-        const BatchJobHost &h = b->jobs[(size_t)j];
-        ea::BatchJobDev &d = dj[(size_t)j];
-        d.L = h.job.L;
-        d.k0 = (uint32_t)(h.job.seed & 0xffffffffu);
-        d.k1 = (uint32_t)(h.job.seed >> 32);
-        d.sample = h.job.sample;
-        d.thr1 = h.thr[0];
-        d.thr2 = h.thr[1];
-        d.thr3 = h.thr[2];
-        d.n_meas = h.job.n_meas;
-        d.n_tw = h.job.n_tw;
-        d.obs_stride = h.obs_stride;
-        d.spins = (uint32_t *)(b->buf + h.off_spins);
-        d.bonds = (const uint32_t *)(b->buf + h.off_bonds);
-        d.snaps = (uint32_t *)(b->buf + h.off_snaps);
-        d.mspins = (uint32_t *)(b->buf + h.off_mspins);
-        d.meas_t = (const uint32_t *)(b->buf + h.off_meas_t);
-        d.tw_t = (const uint32_t *)(b->buf + h.off_tw);
-        d.obs = (unsigned long long *)(b->buf + h.off_obs);
-        d.arrive = (uint32_t *)(b->buf + h.off_arrive);
-        d.t_now = (uint32_t *)(b->buf + h.off_tnow);
-        if (!h.meas_t.empty())
-            e = hipMemcpyAsync(b->buf + h.off_meas_t, h.meas_t.data(), 4 * h.meas_t.size(),
-                               hipMemcpyHostToDevice, b->stream);
-        if (e == hipSuccess && !h.tw.empty())
-            e = hipMemcpyAsync(b->buf + h.off_tw, h.tw.data(), 4 * h.tw.size(), hipMemcpyHostToDevice,
-                               b->stream);
-        if (e != hipSuccess) break;
+        BatchJobHost &h = b->jobs[(size_t)j];
+        h.base = b->buf + region[(size_t)j];
+        dj[(size_t)j] = make_job_dev(h);
+        st = upload_schedule(h, b->stream);
+        if (st != EA_OK) {
+            ea_batch_destroy(b);
+            return st;
+        }
+        ptrs.push_back(&h);
+        span.push_back(h.job.n_sweeps);
     }
     b->d_jobs = (ea::BatchJobDev *)(b->buf + off_jobs);
     b->d_units = (ea::BatchUnit *)(b->buf + off_units);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(b->d_jobs, dj.data(), sizeof(ea::BatchJobDev) * dj.size(), hipMemcpyHostToDevice,
-                           b->stream);
+    b->d_units_graph = (ea::BatchUnit *)(b->buf + off_units_graph);
+    e = hipMemcpyAsync(b->d_jobs, dj.data(), sizeof(ea::BatchJobDev) * dj.size(), hipMemcpyHostToDevice,
+                       b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) {
         ea_batch_destroy(b);
         return fail(EA_ERR_DEVICE, "job table upload: %s", hipGetErrorString(e));
     }
-
-    // Units, largest lattices first so that the longest work starts first;
-    // the two replicas of a job are adjacent so they reach each measurement
-    // at about the same time.
-    std::vector<int32_t> order((size_t)n_jobs);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) {
-        const BatchJobHost &x = b->jobs[(size_t)a], &y = b->jobs[(size_t)c];
-        const double wx = (double)x.job.L * x.job.L * x.job.L * (double)x.job.n_sweeps;
-        const double wy = (double)y.job.L * y.job.L * y.job.L * (double)y.job.n_sweeps;
-        return wx > wy;
-    });
-    for (int32_t j : order)
-        for (int32_t r = 0; r < 2; ++r) b->units.push_back(ea::BatchUnit{j, r, 0u, 1});
-
-    ea_status st = batch_reset_device(b);
+    order_units(ptrs, span, b->units);
+    st = ea_batch_reset(b);
     if (st != EA_OK) {
         ea_batch_destroy(b);
         return st;
@@ -275,6 +355,8 @@ void ea_batch_destroy(ea_batch *b)
 {
     if (!b) return;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->buf) (void)hipFree(b->buf);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
@@ -283,7 +365,11 @@ void ea_batch_destroy(ea_batch *b)
 ea_status ea_batch_reset(ea_batch *b)
 {
     if (!b) return fail(EA_ERR_ARG, "batch is NULL");
-    return batch_reset_device(b);
+    for (auto &h : b->jobs) {
+        ea_status st = init_job_device(h, b->stream);
+        if (st != EA_OK) return st;
+    }
+    return EA_OK;
 }
 
 ea_status ea_batch_run(ea_batch *b, uint64_t t_stop)
@@ -312,6 +398,57 @@ ea_status ea_batch_run(ea_batch *b, uint64_t t_stop)
     return EA_OK;
 }
 
+ea_status ea_batch_capture(ea_batch *b)
+{
+    if (!b) return fail(EA_ERR_ARG, "batch is NULL");
+    if (b->graph_exec) return EA_OK;
+    // the whole-run unit table goes to the device once, outside the graph
+    std::vector<ea::BatchUnit> full = b->units;
+    for (auto &u : full) {
+        u.t_stop = (uint32_t)b->jobs[(size_t)u.job].job.n_sweeps;
+        u.first = 1;
+    }
+    EA_HIP(hipMemcpyAsync(b->d_units_graph, full.data(), sizeof(ea::BatchUnit) * full.size(),
+                          hipMemcpyHostToDevice, b->stream));
+    EA_HIP(hipStreamSynchronize(b->stream));
+    EA_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    ea_status st = EA_OK;
+    for (auto &h : b->jobs) {
+        st = init_job_device(h, b->stream);
+        if (st != EA_OK) break;
+    }
+    if (st == EA_OK)
+        hipLaunchKernelGGL(ea::batch_kernel, dim3((unsigned)full.size()), dim3(ea::kBatchThreads), b->lds_bytes,
+                           b->stream, b->d_jobs, b->d_units_graph);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(b->stream, &graph);
+    if (st != EA_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return fail(EA_ERR_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&b->graph_exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return fail(EA_ERR_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    b->graph = graph;
+    return EA_OK;
+}
+
+ea_status ea_batch_replay(ea_batch *b)
+{
+    if (!b) return fail(EA_ERR_ARG, "batch is NULL");
+    if (!b->graph_exec) return fail(EA_ERR_STATE, "ea_batch_capture first");
+    EA_HIP(hipGraphLaunch(b->graph_exec, b->stream));
+    EA_HIP(hipStreamSynchronize(b->stream));
+    for (auto &h : b->jobs) {
+        h.t_host = h.job.n_sweeps;
+        h.started = true;
+    }
+    return EA_OK;
+}
+
 ea_status ea_batch_time(ea_batch *b, int32_t job, uint64_t *t)
 {
     if (!b || !t) return fail(EA_ERR_ARG, "NULL argument");
@@ -326,37 +463,13 @@ ea_status ea_batch_result(ea_batch *b, int32_t job, int32_t k, ea_obs *out)
     if (job < 0 || job >= (int32_t)b->jobs.size()) return fail(EA_ERR_ARG, "job %d out of range", job);
     const BatchJobHost &h = b->jobs[(size_t)job];
     if (k < 0 || k >= h.job.n_meas) return fail(EA_ERR_ARG, "measurement %d out of range", k);
-    if (h.meas_t[(size_t)k] > h.t_host) return fail(EA_ERR_STATE, "measurement %d (t=%u) not reached", k,
-                                                     h.meas_t[(size_t)k]);
-    if (out->autocorr && out->n_tw != h.job.n_tw)
-        return fail(EA_ERR_ARG, "n_tw=%d but the job has %d snapshot times", out->n_tw, h.job.n_tw);
-    if (out->c4 && out->rmax != h.R) return fail(EA_ERR_ARG, "rmax=%d but L/2=%d", out->rmax, h.R);
+    if (h.meas_t[(size_t)k] > h.t_host || !h.started)
+        return fail(EA_ERR_STATE, "measurement %d (t=%u) not reached", k, h.meas_t[(size_t)k]);
     b->h_obs.resize((size_t)h.obs_stride);
-    EA_HIP(hipMemcpyAsync(b->h_obs.data(), b->buf + h.off_obs + 8 * (size_t)k * (size_t)h.obs_stride,
+    EA_HIP(hipMemcpyAsync(b->h_obs.data(), h.base + h.off_obs + 8 * (size_t)k * (size_t)h.obs_stride,
                           8 * (size_t)h.obs_stride, hipMemcpyDeviceToHost, b->stream));
     EA_HIP(hipStreamSynchronize(b->stream));
-    const unsigned long long *m = b->h_obs.data();
-    const int64_t N = (int64_t)h.job.L * h.job.L * h.job.L;
-    const uint32_t t = h.meas_t[(size_t)k];
-    out->t = t;
-    for (int r = 0; r < 2; ++r) {
-        out->unsat[r] = (int64_t)m[ea::M_UNSAT + r];
-        out->mag[r] = N - 2 * (int64_t)m[ea::M_DOWN + r];
-    }
-    out->overlap = N - 2 * (int64_t)m[ea::M_QDIFF];
-    if (out->autocorr) {
-        for (int r = 0; r < 2; ++r)
-            for (int s = 0; s < h.job.n_tw; ++s)
-                out->autocorr[r * h.job.n_tw + s] =
-                    h.tw[(size_t)s] <= t ? N - 2 * (int64_t)m[ea::M_AUTO + 2 * s + r] : 0;
-        if (out->tw)
-            for (int s = 0; s < h.job.n_tw; ++s) out->tw[s] = h.tw[(size_t)s] <= t ? h.tw[(size_t)s] : 0;
-    }
-    if (out->c4) {
-        const int base = ea::M_AUTO + 2 * h.job.n_tw;
-        for (int i = 0; i < 3 * (h.R + 1); ++i) out->c4[i] = N - 2 * (int64_t)m[base + i];
-    }
-    return EA_OK;
+    return fill_obs(h, b->h_obs.data(), k, out);
 }
 
 ea_status ea_batch_get_spins(ea_batch *b, int32_t job, int32_t r, int8_t *pm1)
@@ -364,19 +477,7 @@ ea_status ea_batch_get_spins(ea_batch *b, int32_t job, int32_t r, int8_t *pm1)
     if (!b || !pm1) return fail(EA_ERR_ARG, "NULL argument");
     if (job < 0 || job >= (int32_t)b->jobs.size()) return fail(EA_ERR_ARG, "job %d out of range", job);
     if (r < 0 || r > 1) return fail(EA_ERR_ARG, "replica %d not 0 or 1", r);
-    const BatchJobHost &h = b->jobs[(size_t)job];
-    std::vector<uint32_t> words(2 * (size_t)h.POS);
-    EA_HIP(hipMemcpyAsync(words.data(), b->buf + h.off_spins + 4 * (size_t)r * 2 * h.POS, 4 * words.size(),
-                          hipMemcpyDeviceToHost, b->stream));
-    EA_HIP(hipStreamSynchronize(b->stream));
-    Layout y = make_layout(h.job.L, 0);
-    const int64_t N = (int64_t)h.job.L * h.job.L * h.job.L;
-    for (int64_t i = 0; i < N; ++i) {
-        SiteAddr a = address_of(y, i);
-        const uint32_t bit = (words[(size_t)a.c * h.POS + a.word] >> a.bit) & 1u;
-        pm1[i] = bit ? (int8_t)-1 : (int8_t)1;
-    }
-    return EA_OK;
+    return read_job_spins(b->jobs[(size_t)job], r, pm1, b->stream);
 }
 
 }  // extern "C"

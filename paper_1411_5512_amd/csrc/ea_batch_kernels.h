@@ -37,7 +37,8 @@ struct Shape {
     static constexpr int POS = L * L * RW;  // packed words per colour
     static constexpr int NT = POS >= kBatchThreads ? kBatchThreads : ((POS + 63) / 64) * 64;
     static constexpr int P = (POS + NT - 1) / NT;  // words per thread per half-step
-    static constexpr int LDS_WORDS = 8 * POS;      // 2 spin planes + 6 coupling planes
+    static constexpr int LATTICE_WORDS = 8 * POS;  // 2 spin planes + 6 coupling planes
+    static constexpr int LDS_WORDS = LATTICE_WORDS + 16;  // dynamic LDS: lattice + flag
 };
 
 // Device-side description of one sample in a batch.
@@ -71,10 +72,15 @@ struct BatchUnit {
 // [5 + 2k + r] S_r(t) != S_r(tw_k), then [5 + 2 n_tw + d (R+1) + rho] for C4.
 __device__ __forceinline__ int batch_c4_base(int n_tw) { return M_AUTO + 2 * n_tw; }
 
-// The workgroup's dynamic LDS: [colour][POS] spins of its replica, then
-// [direction][colour][POS] couplings, then one word for a broadcast flag.
+// The workgroup's LDS: the threshold-select tables are a static array (its
+// address is a compile-time constant, so table reads need no address add),
+// followed by the dynamic part: [colour][POS] spins of the replica,
+// [direction][colour][POS] couplings and one word for a broadcast flag.
 // Declared at file scope so that every access is a plain ds_read/ds_write.
 extern __shared__ uint32_t batch_lds[];
+__shared__ uint32_t batch_select_tables[kSelectTableWords];
+
+__device__ __forceinline__ uint32_t *batch_tables() { return batch_select_tables; }
 
 template <int L>
 __device__ __forceinline__ uint32_t *lds_spin(int c)
@@ -135,7 +141,7 @@ __device__ __forceinline__ void batch_half_step(const BatchJobDev &J, int r, int
         const uint32_t a6 = xor3(S0, oth[zm * RW + w], bz_oth[zm * RW + w]);
         const Decision d = classify(a1, a2, a3, a4, a5, a6);
         const uint32_t quad0 = (uint32_t)((row * S::R + w * W) >> 2);
-        own[p] = S0 ^ flip_mask<W>(d, t, quad0, c2, J.sample, J.k0, J.k1, J.thr1, J.thr2, J.thr3);
+        own[p] = S0 ^ flip_mask_lds<W>(d, t, quad0, c2, J.sample, J.k0, J.k1, batch_tables());
     }
 }
 
@@ -191,7 +197,7 @@ __device__ void batch_measure(const BatchJobDev &J, int r, int m, int n_taken)
     batch_store_spins<L>(J.mspins + ((size_t)m * 2 + (size_t)r) * 2 * POS);
     __threadfence();
     __syncthreads();
-    uint32_t *flag = batch_lds + S::LDS_WORDS;
+    uint32_t *flag = batch_lds + S::LATTICE_WORDS;
     if (threadIdx.x == 0) *flag = atomicAdd(J.arrive + m, 1u);
     __syncthreads();
     const bool second = *flag == 1u;
@@ -257,6 +263,7 @@ __device__ void batch_run_unit(const BatchJobDev &J, int r, uint32_t t_stop, boo
     const uint32_t *src = J.spins + (size_t)r * 2 * S::POS;
     for (int i = (int)threadIdx.x; i < 2 * S::POS; i += S::NT) batch_lds[i] = src[i];
     for (int i = (int)threadIdx.x; i < 6 * S::POS; i += S::NT) batch_lds[2 * S::POS + i] = J.bonds[i];
+    fill_select_tables(batch_tables(), J.thr1, J.thr2, J.thr3, (int)threadIdx.x, S::NT);
     __syncthreads();
 
     int im = 0, iw = 0;

@@ -157,8 +157,8 @@ __device__ __forceinline__ uint32_t accept_site(uint32_t accept, uint32_t u, con
     const uint32_t t = __builtin_amdgcn_bitop3_b32(m_any, thr1,
                                                    __builtin_amdgcn_bitop3_b32(m_odd, thr2, thr3, kBitopSelect),
                                                    kBitopSelect);
-    const uint32_t below = __builtin_amdgcn_bitop3_b32(u, t, u - t, kBitopBelow);
-    return __builtin_amdgcn_alignbit(accept, below, 31);
+    // accept = 2 accept + (u < t): a compare into the carry and one add-with-carry
+    return accept + accept + (uint32_t)(u < t);
 }
 
 // Blocks J = W/4-1 down to 0: block J covers sites 4J..4J+3 and has counter
@@ -187,6 +187,73 @@ __device__ __forceinline__ uint32_t flip_mask(const Decision &d, uint32_t c0, ui
                                               uint32_t thr1, uint32_t thr2, uint32_t thr3)
 {
     return d.always | accept_blocks<W / 4 - 1>(0u, d, c0, quad0, c2, c3, k0, k1, thr1, thr2, thr3);
+}
+
+// ---------------------------------------------------------------------------
+// Threshold select through an LDS table.  Per word, the two class masks are
+// turned into one nibble per site, 8 (any) + 4 (odd) = the byte offset of the
+// site's threshold in a 4-entry table {thr3, thr2, thr1, 0}; two 256-entry
+// tables spread a byte of each mask into nibbles.  Per site this costs one
+// bit-field extract and one LDS read instead of two extracts and two selects.
+
+constexpr int kSelectTableWords = 4 + 2 * 256;
+
+// Fill the tables (any thread count; caller synchronises before use).
+__device__ __forceinline__ void fill_select_tables(uint32_t *tab, uint32_t thr1, uint32_t thr2, uint32_t thr3,
+                                                   int tid, int nthreads)
+{
+    for (int i = tid; i < kSelectTableWords; i += nthreads) {
+        uint32_t v;
+        if (i < 4) {
+            v = i == 0 ? thr3 : (i == 1 ? thr2 : (i == 2 ? thr1 : 0u));
+        } else {
+            const int x = (i - 4) & 255;
+            const int shift = i < 4 + 256 ? 3 : 2;
+            v = 0;
+            for (int k = 0; k < 8; ++k) v |= (uint32_t)((x >> k) & 1) << (4 * k + shift);
+        }
+        tab[i] = v;
+    }
+}
+
+template <int J, int W>
+__device__ __forceinline__ uint32_t accept_blocks_lds(uint32_t accept, const uint32_t (&thr)[W], uint32_t c0,
+                                                      uint32_t quad0, uint32_t c2, uint32_t c3, uint32_t k0,
+                                                      uint32_t k1)
+{
+    const Words4 u = philox10(c0, quad0 + (uint32_t)J, c2, c3, k0, k1);
+#pragma unroll
+    for (int q = 3; q >= 0; --q) {
+        const int i = 4 * J + q;
+        accept = __builtin_amdgcn_alignbit(accept, __builtin_amdgcn_bitop3_b32(u.v[q], thr[i], u.v[q] - thr[i],
+                                                                               kBitopBelow), 31);
+    }
+    if constexpr (J > 0)
+        return accept_blocks_lds<J - 1, W>(accept, thr, c0, quad0, c2, c3, k0, k1);
+    else
+        return accept;
+}
+
+// Flip mask of one packed word of W sites, thresholds from the LDS tables
+// (tab = kSelectTableWords words filled by fill_select_tables).  All W
+// thresholds are read before the random words are computed, so the LDS
+// latency overlaps the Philox rounds.
+template <int W>
+__device__ __forceinline__ uint32_t flip_mask_lds(const Decision &d, uint32_t c0, uint32_t quad0, uint32_t c2,
+                                                  uint32_t c3, uint32_t k0, uint32_t k1, const uint32_t *tab)
+{
+    const uint32_t *spread_any = tab + 4;
+    const uint32_t *spread_odd = tab + 4 + 256;
+    uint32_t code[(W + 7) / 8];
+#pragma unroll
+    for (int j = 0; j < (W + 7) / 8; ++j)
+        code[j] = spread_any[__builtin_amdgcn_ubfe(d.any, 8 * j, 8)] |
+                  spread_odd[__builtin_amdgcn_ubfe(d.odd, 8 * j, 8)];
+    uint32_t thr[W];
+#pragma unroll
+    for (int i = 0; i < W; ++i)
+        thr[i] = *(const uint32_t *)((const char *)tab + __builtin_amdgcn_ubfe(code[i >> 3], 4 * (i & 7), 4));
+    return d.always | accept_blocks_lds<W / 4 - 1, W>(0u, thr, c0, quad0, c2, c3, k0, k1);
 }
 
 }  // namespace ea

@@ -116,6 +116,8 @@ __global__ __launch_bounds__(256) void half_step_kernel(Lattice lat, Geom g, int
 
     const Decision d = classify(a1, a2, a3, a4, a5, a6);
     const uint32_t quad0 = (uint32_t)((row * g.R + w * W) >> 2);
+    // the register select: this launch is latency-bound, an LDS table would
+    // add a fill and a barrier to every block
     const uint32_t flips = flip_mask<W>(d, t, quad0, counter_word2(TAG_METRO, (uint32_t)c, (uint32_t)r),
                                         sample, k0, k1, thr1, thr2, thr3);
     own[base + w] = S ^ flips;

@@ -1,0 +1,499 @@
+// ea_server_api.h -- the serving form (ea_server_* in ea.h): continuous
+// batching of a stream of simulation jobs on the batched kernel.
+//
+// Jobs are admitted first-come first-served while their device footprint
+// fits a fixed HBM budget (a first-fit pool carved from one allocation) and
+// a slot is free.  Admitted jobs keep their lattices resident in HBM; every
+// epoch is one persistent launch that advances each resident job by a span of
+// sweeps sized so that all units take about the same time (a fixed number of
+// site-sweeps per replica), taking the job's scheduled snapshots and
+// measurements on the way.  Between epochs finished jobs hand their results
+// to the host and free their memory, and waiting jobs are admitted.  Epochs
+// run on the calling thread (ea_server_step) or on a worker thread
+// (ea_server_start), so that requests that arrive while a launch is on the
+// GPU join at the next epoch.  Results are the same integers as a run alone:
+// the dynamics never depend on how the sweeps are split or what else runs.
+#pragma once
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
+namespace {
+
+using steady = std::chrono::steady_clock;
+
+// First-fit allocator over one device buffer (offsets, 256-byte granules).
+struct DevicePool {
+    size_t size = 0;
+    std::map<size_t, size_t> free_;  // offset -> length
+    size_t in_use = 0, peak = 0;
+
+    void reset(size_t n)
+    {
+        size = n;
+        free_.clear();
+        if (n) free_[0] = n;
+        in_use = peak = 0;
+    }
+    bool alloc(size_t n, size_t *off)
+    {
+        n = align256(n);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                *off = it->first;
+                const size_t rest = it->second - n, at = it->first + n;
+                free_.erase(it);
+                if (rest) free_[at] = rest;
+                in_use += n;
+                peak = std::max(peak, in_use);
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t n)
+    {
+        n = align256(n);
+        in_use -= n;
+        auto it = free_.emplace(off, n).first;
+        auto next = std::next(it);
+        if (next != free_.end() && it->first + it->second == next->first) {
+            it->second += next->second;
+            free_.erase(next);
+        }
+        if (it != free_.begin()) {
+            auto prev = std::prev(it);
+            if (prev->first + prev->second == it->first) {
+                prev->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+enum { SJ_PENDING = 0, SJ_RUNNING = 1, SJ_DONE = 2 };
+
+struct ServerJob {
+    uint64_t id = 0;
+    BatchJobHost h;
+    size_t pool_off = 0;
+    steady::time_point t_submit, t_done;
+    std::vector<unsigned long long> results;  // [n_meas][obs_stride] after completion
+};
+
+}  // namespace
+
+struct ea_server {
+    ea_server_opts opts{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    char *pool_buf = nullptr;
+    DevicePool pool;
+    ea::BatchJobDev *d_jobs = nullptr;
+    ea::BatchUnit *d_units = nullptr;
+    size_t lds_bytes = 0;
+
+    std::mutex mu;  // guards everything below
+    std::condition_variable cv;
+    std::deque<std::unique_ptr<ServerJob>> pending;
+    std::vector<std::unique_ptr<ServerJob>> resident;
+    std::unordered_map<uint64_t, std::unique_ptr<ServerJob>> done;
+    std::unordered_map<uint64_t, int> state_of;
+    uint64_t next_id = 1, submitted = 0, admitted = 0, completed = 0, epochs = 0;
+    std::vector<double> latencies;
+    double flips = 0.0, busy_s = 0.0;
+    bool have_first = false;
+    steady::time_point first_submit;
+
+    std::thread worker;
+    bool worker_on = false, stop = false;
+    std::mutex epoch_mu;  // one epoch at a time
+    std::string worker_error;
+};
+
+namespace {
+
+// One epoch: retire, admit, launch, wait.  Returns EA_OK with *progressed = 0
+// when nothing was resident or admissible.
+ea_status server_epoch(ea_server *s, int32_t *progressed)
+{
+    std::lock_guard<std::mutex> epoch_lock(s->epoch_mu);
+    *progressed = 0;
+    std::vector<ServerJob *> run;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        // admit in arrival order while memory and slots allow
+        while (!s->pending.empty() && (int32_t)s->resident.size() < s->opts.max_resident) {
+            ServerJob *j = s->pending.front().get();
+            size_t off = 0;
+            if (!s->pool.alloc(j->h.bytes, &off)) break;
+            j->pool_off = off;
+            j->h.base = s->pool_buf + off;
+            s->resident.push_back(std::move(s->pending.front()));
+            s->pending.pop_front();
+            s->state_of[j->id] = SJ_RUNNING;
+            ++s->admitted;
+            ea_status st = upload_schedule(j->h, s->stream);
+            if (st == EA_OK) st = init_job_device(j->h, s->stream);
+            if (st != EA_OK) return st;
+        }
+        for (auto &p : s->resident) run.push_back(p.get());
+    }
+    if (run.empty()) return EA_OK;
+
+    // spans: about opts.epoch_site_sweeps site-updates per replica, at least one sweep
+    std::vector<BatchJobHost *> hs;
+    std::vector<uint64_t> span;
+    std::vector<ea::BatchJobDev> dj;
+    for (ServerJob *j : run) {
+        const uint64_t N = (uint64_t)j->h.job.L * j->h.job.L * j->h.job.L;
+        const uint64_t want = std::max<uint64_t>(1, s->opts.epoch_site_sweeps / N);
+        span.push_back(std::min<uint64_t>(want, j->h.job.n_sweeps - j->h.t_host));
+        hs.push_back(&j->h);
+        dj.push_back(make_job_dev(j->h));
+    }
+    std::vector<ea::BatchUnit> units;
+    order_units(hs, span, units);
+    for (auto &u : units) {
+        const BatchJobHost &h = *hs[(size_t)u.job];
+        u.t_stop = (uint32_t)(h.t_host + span[(size_t)u.job]);
+        u.first = h.started ? 0 : 1;
+    }
+    const auto t0 = steady::now();
+    EA_HIP(hipMemcpyAsync(s->d_jobs, dj.data(), sizeof(ea::BatchJobDev) * dj.size(), hipMemcpyHostToDevice,
+                          s->stream));
+    EA_HIP(hipMemcpyAsync(s->d_units, units.data(), sizeof(ea::BatchUnit) * units.size(), hipMemcpyHostToDevice,
+                          s->stream));
+    hipLaunchKernelGGL(ea::batch_kernel, dim3((unsigned)units.size()), dim3(ea::kBatchThreads), s->lds_bytes,
+                       s->stream, s->d_jobs, s->d_units);
+    EA_HIP(hipGetLastError());
+    EA_HIP(hipStreamSynchronize(s->stream));
+    const auto t1 = steady::now();
+
+    // bookkeeping; finished jobs hand their results over and free their memory
+    double epoch_flips = 0.0;
+    std::vector<ServerJob *> finished;
+    for (size_t i = 0; i < run.size(); ++i) {
+        BatchJobHost &h = run[i]->h;
+        h.t_host += span[i];
+        h.started = true;
+        epoch_flips += 2.0 * h.job.L * h.job.L * h.job.L * (double)span[i];
+        if (h.t_host >= h.job.n_sweeps) finished.push_back(run[i]);
+    }
+    for (ServerJob *j : finished) {
+        j->results.resize((size_t)j->h.job.n_meas * (size_t)j->h.obs_stride);
+        if (!j->results.empty())
+            EA_HIP(hipMemcpy(j->results.data(), j->h.base + j->h.off_obs, 8 * j->results.size(),
+                             hipMemcpyDeviceToHost));
+    }
+    const auto t2 = steady::now();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        ++s->epochs;
+        s->flips += epoch_flips;
+        s->busy_s += std::chrono::duration<double>(t1 - t0).count();
+        for (ServerJob *j : finished) {
+            j->t_done = t2;
+            s->latencies.push_back(std::chrono::duration<double>(j->t_done - j->t_submit).count());
+            s->pool.release(j->pool_off, j->h.bytes);
+            j->h.base = nullptr;
+            auto it = std::find_if(s->resident.begin(), s->resident.end(),
+                                   [&](const std::unique_ptr<ServerJob> &p) { return p.get() == j; });
+            s->state_of[j->id] = SJ_DONE;
+            ++s->completed;
+            s->done[j->id] = std::move(*it);
+            s->resident.erase(it);
+        }
+    }
+    s->cv.notify_all();
+    *progressed = 1;
+    return EA_OK;
+}
+
+void server_worker(ea_server *s)
+{
+    (void)hipSetDevice(s->device);
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv.wait(lk, [&] { return s->stop || !s->pending.empty() || !s->resident.empty(); });
+            if (s->stop) return;
+        }
+        int32_t progressed = 0;
+        ea_status st = server_epoch(s, &progressed);
+        if (st != EA_OK) {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->worker_error = ea_last_error();
+            s->stop = true;
+            s->cv.notify_all();
+            return;
+        }
+        if (!progressed) {
+            // nothing admissible right now (memory full with nothing resident cannot happen)
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv.wait_for(lk, std::chrono::milliseconds(1));
+        }
+    }
+}
+
+double percentile(std::vector<double> v, double q)
+{
+    if (v.empty()) return 0.0;
+    std::sort(v.begin(), v.end());
+    const double pos = q * (double)(v.size() - 1);
+    const size_t i = (size_t)pos;
+    const double f = pos - (double)i;
+    return i + 1 < v.size() ? v[i] * (1.0 - f) + v[i + 1] * f : v[i];
+}
+
+}  // namespace
+
+extern "C" {
+
+ea_status ea_server_create(const ea_server_opts *opts, ea_server **out)
+{
+    if (!opts || !out) return fail(EA_ERR_ARG, "NULL argument");
+    *out = nullptr;
+    if (opts->hbm_budget < 4096) return fail(EA_ERR_ARG, "hbm_budget %zu is too small", opts->hbm_budget);
+    if (opts->max_resident < 1 || opts->max_resident > 4096)
+        return fail(EA_ERR_ARG, "max_resident %d outside [1, 4096]", opts->max_resident);
+    if (opts->max_pending < 1) return fail(EA_ERR_ARG, "max_pending must be positive");
+    ea_server *s = new (std::nothrow) ea_server();
+    if (!s) return fail(EA_ERR_NOMEM, "host allocation failed");
+    s->opts = *opts;
+    if (!s->opts.epoch_site_sweeps) s->opts.epoch_site_sweeps = 64ull * 64 * 64 * 64;
+    s->lds_bytes = (size_t)batch_lds_words(ea::kBatchMaxL) * 4;
+    ea_status st = prepare_batch_lds(s->lds_bytes);
+    hipError_t e = hipGetDevice(&s->device);
+    if (st == EA_OK && e != hipSuccess) st = fail(EA_ERR_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    if (st != EA_OK) {
+        delete s;
+        return st;
+    }
+    if (opts->stream) {
+        s->stream = (hipStream_t)opts->stream;
+    } else {
+        e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete s;
+            return fail(EA_ERR_DEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+        }
+        s->own_stream = true;
+    }
+    const size_t table_bytes = align256(sizeof(ea::BatchJobDev) * (size_t)opts->max_resident) +
+                               align256(sizeof(ea::BatchUnit) * 2 * (size_t)opts->max_resident);
+    e = hipMalloc((void **)&s->pool_buf, align256(opts->hbm_budget) + table_bytes);
+    if (e != hipSuccess) {
+        ea_server_destroy(s);
+        return fail(EA_ERR_NOMEM, "hipMalloc(%zu): %s", opts->hbm_budget, hipGetErrorString(e));
+    }
+    s->pool.reset(align256(opts->hbm_budget));
+    s->d_jobs = (ea::BatchJobDev *)(s->pool_buf + align256(opts->hbm_budget));
+    s->d_units = (ea::BatchUnit *)((char *)s->d_jobs +
+                                   align256(sizeof(ea::BatchJobDev) * (size_t)opts->max_resident));
+    *out = s;
+    return EA_OK;
+}
+
+void ea_server_destroy(ea_server *s)
+{
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    if (s->pool_buf) (void)hipFree(s->pool_buf);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+ea_status ea_server_footprint(const ea_job *job, size_t *bytes)
+{
+    if (!job || !bytes) return fail(EA_ERR_ARG, "NULL argument");
+    BatchJobHost h;
+    ea_status st = plan_job(*job, 0, h);
+    if (st != EA_OK) return st;
+    *bytes = h.bytes;
+    return EA_OK;
+}
+
+ea_status ea_server_submit(ea_server *s, const ea_job *job, uint64_t *id)
+{
+    if (!s || !job || !id) return fail(EA_ERR_ARG, "NULL argument");
+    auto j = std::make_unique<ServerJob>();
+    ea_status st = plan_job(*job, 0, j->h);
+    if (st != EA_OK) return st;
+    if (align256(j->h.bytes) > s->pool.size)
+        return fail(EA_ERR_ARG, "job needs %zu bytes, more than the whole budget %zu", j->h.bytes, s->pool.size);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (!s->worker_error.empty()) return fail(EA_ERR_STATE, "worker stopped: %s", s->worker_error.c_str());
+        if ((int32_t)s->pending.size() >= s->opts.max_pending)
+            return fail(EA_ERR_BUSY, "%zu jobs already wait", s->pending.size());
+        j->id = s->next_id++;
+        j->t_submit = steady::now();
+        if (!s->have_first) {
+            s->have_first = true;
+            s->first_submit = j->t_submit;
+        }
+        *id = j->id;
+        s->state_of[j->id] = SJ_PENDING;
+        ++s->submitted;
+        s->pending.push_back(std::move(j));
+    }
+    s->cv.notify_all();
+    return EA_OK;
+}
+
+ea_status ea_server_step(ea_server *s, int32_t *progressed)
+{
+    if (!s || !progressed) return fail(EA_ERR_ARG, "NULL argument");
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->worker_on) return fail(EA_ERR_STATE, "a worker thread runs the epochs");
+    }
+    return server_epoch(s, progressed);
+}
+
+ea_status ea_server_start(ea_server *s)
+{
+    if (!s) return fail(EA_ERR_ARG, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->worker_on) return EA_OK;
+    s->stop = false;
+    s->worker_on = true;
+    s->worker = std::thread(server_worker, s);
+    return EA_OK;
+}
+
+ea_status ea_server_stop(ea_server *s)
+{
+    if (!s) return fail(EA_ERR_ARG, "server is NULL");
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (!s->worker_on) return EA_OK;
+        s->stop = true;
+    }
+    s->cv.notify_all();
+    s->worker.join();
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->worker_on = false;
+    s->stop = false;
+    if (!s->worker_error.empty()) return fail(EA_ERR_DEVICE, "worker failed: %s", s->worker_error.c_str());
+    return EA_OK;
+}
+
+ea_status ea_server_drain(ea_server *s, double timeout_s)
+{
+    if (!s) return fail(EA_ERR_ARG, "server is NULL");
+    bool threaded;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        threaded = s->worker_on;
+    }
+    const auto deadline = steady::now() + std::chrono::duration_cast<steady::duration>(
+                                              std::chrono::duration<double>(timeout_s));
+    if (!threaded) {
+        for (;;) {
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                if (s->pending.empty() && s->resident.empty()) return EA_OK;
+            }
+            if (steady::now() > deadline) return fail(EA_ERR_BUSY, "drain timed out");
+            int32_t progressed = 0;
+            ea_status st = server_epoch(s, &progressed);
+            if (st != EA_OK) return st;
+        }
+    }
+    std::unique_lock<std::mutex> lk(s->mu);
+    const bool ok = s->cv.wait_until(lk, deadline, [&] {
+        return (s->pending.empty() && s->resident.empty()) || !s->worker_error.empty();
+    });
+    if (!s->worker_error.empty()) return fail(EA_ERR_DEVICE, "worker failed: %s", s->worker_error.c_str());
+    return ok ? EA_OK : fail(EA_ERR_BUSY, "drain timed out");
+}
+
+ea_status ea_server_poll(ea_server *s, uint64_t id, int32_t *state)
+{
+    if (!s || !state) return fail(EA_ERR_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->state_of.find(id);
+    if (it == s->state_of.end()) return fail(EA_ERR_ARG, "unknown job id %llu", (unsigned long long)id);
+    *state = it->second;
+    return EA_OK;
+}
+
+ea_status ea_server_result(ea_server *s, uint64_t id, int32_t k, ea_obs *out)
+{
+    if (!s || !out) return fail(EA_ERR_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->done.find(id);
+    if (it == s->done.end()) {
+        if (s->state_of.count(id)) return fail(EA_ERR_STATE, "job %llu has not finished", (unsigned long long)id);
+        return fail(EA_ERR_ARG, "unknown job id %llu", (unsigned long long)id);
+    }
+    const ServerJob &j = *it->second;
+    if (k < 0 || k >= j.h.job.n_meas) return fail(EA_ERR_ARG, "measurement %d out of range", k);
+    return fill_obs(j.h, j.results.data() + (size_t)k * (size_t)j.h.obs_stride, k, out);
+}
+
+ea_status ea_server_latency(ea_server *s, uint64_t id, double *seconds)
+{
+    if (!s || !seconds) return fail(EA_ERR_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->done.find(id);
+    if (it == s->done.end()) return fail(EA_ERR_STATE, "job %llu has not finished", (unsigned long long)id);
+    *seconds = std::chrono::duration<double>(it->second->t_done - it->second->t_submit).count();
+    return EA_OK;
+}
+
+ea_status ea_server_release(ea_server *s, uint64_t id)
+{
+    if (!s) return fail(EA_ERR_ARG, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->done.find(id);
+    if (it == s->done.end()) return fail(EA_ERR_STATE, "job %llu has not finished", (unsigned long long)id);
+    s->done.erase(it);
+    s->state_of.erase(id);
+    return EA_OK;
+}
+
+ea_status ea_server_stats(ea_server *s, ea_server_report *out)
+{
+    if (!s || !out) return fail(EA_ERR_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    ea_server_report r{};
+    r.submitted = s->submitted;
+    r.admitted = s->admitted;
+    r.completed = s->completed;
+    r.resident = (int32_t)s->resident.size();
+    r.pending = (int32_t)s->pending.size();
+    r.epochs = s->epochs;
+    r.p50_latency_s = percentile(s->latencies, 0.50);
+    r.p99_latency_s = percentile(s->latencies, 0.99);
+    r.max_latency_s = s->latencies.empty() ? 0.0 : *std::max_element(s->latencies.begin(), s->latencies.end());
+    double sum = 0.0;
+    for (double v : s->latencies) sum += v;
+    r.mean_latency_s = s->latencies.empty() ? 0.0 : sum / (double)s->latencies.size();
+    r.flips = s->flips;
+    r.busy_s = s->busy_s;
+    r.wall_s = s->have_first ? std::chrono::duration<double>(steady::now() - s->first_submit).count() : 0.0;
+    r.ps_per_flip = s->flips > 0 ? s->busy_s / s->flips * 1e12 : 0.0;
+    r.hbm_in_use = s->pool.in_use;
+    r.hbm_peak = s->pool.peak;
+    *out = r;
+    return EA_OK;
+}
+
+}  // extern "C"

@@ -150,3 +150,24 @@ def test_batch_errors(ea_gpu):
         b.result(0, 1)
     b.run()
     b.result(0, 1)
+
+
+def test_batch_graph_replays(ea_gpu):
+    """The captured reset + run graph gives the eager results on every
+    replay, with other eager work on the device in between."""
+    jobs = _mixed_jobs()
+    eager = ea_gpu.Batch(jobs)
+    eager.run()
+    g = ea_gpu.Batch(jobs)
+    g.capture()
+    other = ea_gpu.Sim(16, 0.5, 0.8, seed=3)
+    for rep in range(3):
+        g.replay()
+        for j, job in enumerate(jobs):
+            assert g.time(j) == job.n_sweeps
+            for k in range(len(job.meas_t)):
+                _same_obs(g.result(j, k), eager.result(j, k), f"replay {rep} job {j} meas {k}")
+            for r in (0, 1):
+                assert np.array_equal(g.spins(j, r), eager.spins(j, r)), (rep, j, r)
+        other.sweep(10)
+        other.measure()

@@ -1,0 +1,116 @@
+"""The serving form: jobs submitted while others run are admitted by memory
+and slots, interleave on the device, and each one's results equal the same
+job run alone (tolerance 0: every observable is an integer)."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _same_obs(a, b, ctx):
+    assert a.t == b.t, ctx
+    assert list(a.unsat) == list(b.unsat), ctx
+    assert list(a.mag) == list(b.mag), ctx
+    assert a.overlap == b.overlap, ctx
+    assert np.array_equal(a.autocorr, b.autocorr), ctx
+    assert np.array_equal(a.c4, b.c4), ctx
+
+
+def _stream_jobs(n, seed, sweep_range=(20, 400)):
+    """A small Poisson-like mix of L in {8..64}, p in [0.1, 0.5],
+    T in [0.5, 1.2], log-uniform sweeps, log-spaced schedules."""
+    from paper_1411_5512_amd.workloads import Job, log_schedule
+    rng = np.random.default_rng(seed)
+    jobs = []
+    for j in range(n):
+        L = int(rng.choice([8, 16, 24, 32, 40, 48, 56, 64]))
+        nsw = int(round(np.exp(rng.uniform(np.log(sweep_range[0]), np.log(sweep_range[1])))))
+        tw = [t for t in (5, 50) if t <= nsw]
+        meas = sorted(set(log_schedule(nsw, 6)) | set(tw))
+        jobs.append(Job(L, float(rng.uniform(0.1, 0.5)), float(rng.uniform(0.5, 1.2)),
+                        seed=7000 + j, sample=j % 3, n_sweeps=nsw, meas_t=meas, tw=tw))
+    return jobs
+
+
+def test_server_mix_equals_alone(ea_gpu):
+    jobs = _stream_jobs(40, seed=1)
+    # a budget that holds only a few jobs at once, so admission binds
+    budget = 3 * max(ea_gpu.Server.footprint(j) for j in jobs)
+    srv = ea_gpu.Server(hbm_budget=budget, max_resident=6, epoch_site_sweeps=64 ** 3 * 8)
+    srv.start()
+    ids = []
+    for j in jobs:
+        ids.append(srv.submit(j))
+        time.sleep(0.002)  # arrivals interleave with running epochs
+    srv.drain(300)
+    srv.stop()
+    st = srv.stats()
+    _say(f"server stats {st}")
+    assert st["completed"] == len(jobs) and st["pending"] == 0 and st["resident"] == 0
+    assert 0 < st["hbm_peak"] <= budget
+    assert st["epochs"] > 1 and st["p99_latency_s"] >= st["p50_latency_s"] > 0
+    alone = ea_gpu.Batch(jobs)
+    alone.run()
+    for i, (jid, job) in enumerate(zip(ids, jobs)):
+        assert srv.poll(jid) == ea_gpu.JOB_DONE
+        for k in range(len(job.meas_t)):
+            _same_obs(srv.result(jid, k), alone.result(i, k), f"job {i} meas {k}")
+        assert srv.latency(jid) > 0
+
+
+def test_server_step_mode_matches_oracle(ea_gpu, oracle_mod):
+    """Driven epoch by epoch on the calling thread, with a tiny epoch so that
+    every job is split over many launches."""
+    jobs = _stream_jobs(6, seed=2, sweep_range=(10, 60))
+    srv = ea_gpu.Server(hbm_budget=1 << 26, max_resident=3, epoch_site_sweeps=16 ** 3 * 3)
+    ids = [srv.submit(j) for j in jobs]
+    n = 0
+    while srv.step():
+        n += 1
+        assert n < 10000
+    for jid, job in zip(ids, jobs):
+        o = oracle_mod.Sim(job.L, job.p, job.T, seed=job.seed, sample=job.sample, n_slots=len(job.tw))
+        t, k = 0, 0
+        for te, slots, meas in job.events():
+            o.sweep(te - t)
+            t = te
+            for s in slots:
+                o.snapshot(s)
+            if meas:
+                _same_obs(srv.result(jid, k), o.measure(), f"job {jid} meas {k}")
+                k += 1
+        srv.release(jid)
+        with pytest.raises(ea_gpu.EAError):
+            srv.poll(jid)
+
+
+def test_server_admission_limits(ea_gpu):
+    from paper_1411_5512_amd.workloads import Job
+    big = Job(64, 0.5, 0.7, seed=1, n_sweeps=5, meas_t=[5])
+    fp = ea_gpu.Server.footprint(big)
+    srv = ea_gpu.Server(hbm_budget=fp, max_resident=4, max_pending=2)
+    with pytest.raises(ea_gpu.EAError):  # larger than the whole budget
+        srv.submit(Job(64, 0.5, 0.7, seed=1, n_sweeps=5, meas_t=[1, 2, 3, 4, 5], tw=[1, 2]))
+    with pytest.raises(ea_gpu.EAError):  # the batched kernel holds L <= 64
+        srv.submit(Job(96, 0.5, 0.7, seed=1, n_sweeps=5, meas_t=[5]))
+    a = srv.submit(big)
+    b = srv.submit(big)
+    with pytest.raises(ea_gpu.EAError):  # max_pending
+        srv.submit(big)
+    assert srv.step()
+    # only one fits the budget: the first ran, the second waited
+    assert srv.poll(a) == ea_gpu.JOB_DONE and srv.poll(b) == ea_gpu.JOB_PENDING
+    with pytest.raises(ea_gpu.EAError):
+        srv.result(b, 0)
+    assert srv.step()
+    assert srv.poll(b) == ea_gpu.JOB_DONE
+    assert not srv.step()
+    _same_obs(srv.result(a, 0), srv.result(b, 0), "identical jobs")
