@@ -159,6 +159,7 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=60, help="oracle sweeps for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="run every size with its default configuration")
     ap.add_argument("--serve-jobs", type=int, default=300, help="jobs in the serving leg (0 = skip)")
     ap.add_argument("--serve-load", type=float, default=0.8, help="offered load of the serving leg")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -191,7 +192,13 @@ def main():
 
     jobs = wl.batch_jobs(n_jobs=args.jobs, n_sweeps=args.sweeps)
     flips_per_step = sum(j.flips for j in jobs)
-    batch = ea.Batch(jobs)
+    Ls = sorted({j.L for j in jobs})
+    tuned = {}
+    if not args.no_autotune:
+        for L in Ls:  # untimed: probes every candidate, keeps the bit-exact fastest
+            tuned[L] = ea.tune(L)["chosen"]
+            log(f"autotune L={L}: {tuned[L]}")
+    batch = ea.Batch(jobs, autotune=not args.no_autotune)
     stream = batch.stream
     batch.capture()  # reset + full run as one hipGraph
 
@@ -228,7 +235,6 @@ def main():
                 assert list(o.autocorr[:, slot]) == [job.L ** 3] * 2, (j, k)
     n_results = sum(len(j.meas_t) for j in jobs)
 
-    Ls = sorted({j.L for j in jobs})
     out = {
         "metric": METRIC,
         "value": round(ps_per_flip, 4),
@@ -252,6 +258,8 @@ def main():
             "sweeps": args.sweeps,
             "flips_per_step": flips_per_step,
             "measurements_per_step": n_results,
+            "launch_config": {str(L): (f"{c['words_per_row']} words/row, {c['threads']} threads, "
+                                       f"{c['select']} select") for L, c in tuned.items()} or "default",
         },
         "roofline": {
             "bound": "alu",

@@ -176,7 +176,28 @@ typedef struct {
 
 typedef struct {
     void *stream;            /* hipStream_t to enqueue on, or NULL for a library stream */
+    int32_t autotune;        /* 1: run each lattice size with its autotuned configuration */
 } ea_batch_opts;
+
+/* Launch configuration of the batched kernel for one lattice size. */
+typedef struct {
+    int32_t words_per_row;   /* packed words per row of L/2 same-colour sites */
+    int32_t threads;         /* working threads per workgroup */
+    int32_t select;          /* threshold select: 0 = LDS table, 1 = register bit-field selects */
+    double ms;               /* time of the probe run with this configuration */
+    int32_t parity_ok;       /* 1 if its results equal the default configuration's bit for bit */
+} ea_tune_choice;
+
+/* Autotune the batched kernel for lattice size L: time every valid
+ * configuration (row packing, threads, select variant) on a probe batch of 64
+ * samples, reject any whose results differ from the default configuration's,
+ * keep the fastest.  The choice is cached for the process and, if the
+ * environment variable EA_TUNE_CACHE names a file, appended to it and read
+ * back by later processes.  force = 1 re-tunes.  tried[0..max_tried) receives
+ * the candidates (the first is the default); *n_tried their number (0 when
+ * the choice came from the cache). */
+ea_status ea_tune(int32_t L, int32_t force, ea_tune_choice *chosen, ea_tune_choice *tried, int32_t max_tried,
+                  int32_t *n_tried);
 
 /* Copy the job list (the caller's schedule arrays may be freed afterwards),
  * allocate device memory for every job and generate the initial states.

@@ -15,7 +15,7 @@ import numpy as np
 from . import abi
 from .abi import EAError
 
-__all__ = ["Sim", "Batch", "Server", "EAError", "thresholds", "footprint", "version"]
+__all__ = ["Sim", "Batch", "Server", "EAError", "thresholds", "footprint", "version", "tune"]
 
 
 def version() -> str:
@@ -32,6 +32,19 @@ def footprint(L: int, n_tw: int = 0) -> int:
     out = ctypes.c_size_t(0)
     abi.check(abi.lib().ea_footprint(int(L), int(n_tw), ctypes.byref(out)))
     return int(out.value)
+
+
+def tune(L: int, force: bool = False) -> dict:
+    """Autotune the batched kernel for lattice size L (see ea_tune)."""
+    chosen = abi.TuneChoice()
+    tried = (abi.TuneChoice * 64)()
+    n = ctypes.c_int32(0)
+    abi.check(abi.lib().ea_tune(int(L), int(force), ctypes.byref(chosen), tried, 64, ctypes.byref(n)))
+
+    def d(c):
+        return {"words_per_row": c.words_per_row, "threads": c.threads,
+                "select": "lds" if c.select == 0 else "reg", "ms": c.ms, "parity_ok": bool(c.parity_ok)}
+    return {"chosen": d(chosen), "tried": [d(tried[i]) for i in range(n.value)]}
 
 
 def _torch_stream_and_buffer(nbytes: int, use_torch: bool):
@@ -215,11 +228,12 @@ def _obs_from(o, n_tw, tw, ac, c4a, c4):
 class Batch:
     """Many independent runs (L <= 64) in one persistent launch per span."""
 
-    def __init__(self, jobs, use_torch: bool = True):
+    def __init__(self, jobs, use_torch: bool = True, autotune: bool = False):
         self.jobs = list(jobs)
         keep = []
         arr = (abi.Job * len(self.jobs))(*[_job_struct(j, keep) for j in self.jobs])
         opts = abi.BatchOpts()
+        opts.autotune = 1 if autotune else 0
         self._stream = None
         if use_torch:
             try:

@@ -68,7 +68,17 @@ class Job(ctypes.Structure):
 
 
 class BatchOpts(ctypes.Structure):
-    _fields_ = [("stream", ctypes.c_void_p)]
+    _fields_ = [("stream", ctypes.c_void_p), ("autotune", ctypes.c_int32)]
+
+
+class TuneChoice(ctypes.Structure):
+    _fields_ = [
+        ("words_per_row", ctypes.c_int32),
+        ("threads", ctypes.c_int32),
+        ("select", ctypes.c_int32),
+        ("ms", ctypes.c_double),
+        ("parity_ok", ctypes.c_int32),
+    ]
 
 
 class ServerOpts(ctypes.Structure):
@@ -128,6 +138,8 @@ _SIGS = {
     "ea_batch_destroy": (None, [ctypes.c_void_p]),
     "ea_batch_reset": (ctypes.c_int, [ctypes.c_void_p]),
     "ea_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "ea_tune": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(TuneChoice),
+                               ctypes.POINTER(TuneChoice), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "ea_batch_capture": (ctypes.c_int, [ctypes.c_void_p]),
     "ea_batch_replay": (ctypes.c_int, [ctypes.c_void_p]),
     "ea_batch_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]),

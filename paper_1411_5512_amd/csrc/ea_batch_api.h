@@ -3,14 +3,43 @@
 // end of ea_api.hip, so that the whole library is one translation unit.
 #pragma once
 
+#include <cstdlib>
+#include <map>
+#include <mutex>
 #include <numeric>
 
 namespace {
 
 // Host record of one job of the batched kernel: parameters, schedule,
 // geometry and the layout of its device region (offsets from `base`).
+// Launch configuration of one lattice size: row packing, working threads
+// per workgroup and threshold-select variant (chosen by the autotuner).
+struct TuneCfg {
+    int rw = 0, nt = 0, sel = 0;
+};
+
+int round_up64(int v) { return (v + 63) / 64 * 64; }
+
+TuneCfg default_cfg(int L)
+{
+    TuneCfg c;
+    c.rw = ea::words_per_row_c(L / 2);
+    c.nt = std::min(ea::kBatchThreads, round_up64(L * L * c.rw));
+    c.sel = ea::SEL_LDS;
+    return c;
+}
+
+bool cfg_valid(int L, const TuneCfg &c)
+{
+    const int R = L / 2, rw0 = ea::words_per_row_c(R), rw1 = ea::finer_words_per_row_c(R, rw0);
+    if (c.rw != rw0 && (rw1 == 0 || c.rw != rw1)) return false;
+    if (c.nt < 64 || c.nt > ea::kBatchThreads || c.nt % 64) return false;
+    return c.sel == ea::SEL_LDS || c.sel == ea::SEL_REG;
+}
+
 struct BatchJobHost {
     ea_job job{};             // parameters (schedule pointers not kept)
+    TuneCfg cfg;
     std::vector<uint32_t> meas_t, tw;
     int R = 0, RW = 0, W = 0, POS = 0, obs_stride = 0;
     uint32_t thr[3] = {0, 0, 0};
@@ -24,20 +53,7 @@ struct BatchJobHost {
 
 bool batch_L_ok(int L) { return L >= 8 && L <= ea::kBatchMaxL && L % 8 == 0; }
 
-int batch_lds_words(int L)
-{
-    switch (L) {
-    case 8: return ea::Shape<8>::LDS_WORDS;
-    case 16: return ea::Shape<16>::LDS_WORDS;
-    case 24: return ea::Shape<24>::LDS_WORDS;
-    case 32: return ea::Shape<32>::LDS_WORDS;
-    case 40: return ea::Shape<40>::LDS_WORDS;
-    case 48: return ea::Shape<48>::LDS_WORDS;
-    case 56: return ea::Shape<56>::LDS_WORDS;
-    case 64: return ea::Shape<64>::LDS_WORDS;
-    default: return -1;
-    }
-}
+int batch_lds_words(int L, int rw) { return 8 * L * L * rw + 16; }
 
 ea_status copy_schedule(const uint64_t *src, int32_t n, uint64_t n_sweeps, const char *what,
                         std::vector<uint32_t> &dst)
@@ -55,7 +71,7 @@ ea_status copy_schedule(const uint64_t *src, int32_t n, uint64_t n_sweeps, const
 }
 
 // Validate a job and lay out its device region (offsets from 0).
-ea_status plan_job(const ea_job &in, int index, BatchJobHost &h)
+ea_status plan_job(const ea_job &in, int index, BatchJobHost &h, const TuneCfg *cfg = nullptr)
 {
     if (!batch_L_ok(in.L))
         return fail(EA_ERR_ARG, "job %d: L=%d must be a multiple of 8 in [8, %d] for the batched form", index,
@@ -71,8 +87,12 @@ ea_status plan_job(const ea_job &in, int index, BatchJobHost &h)
     h.job = in;
     h.job.meas_t = nullptr;
     h.job.tw = nullptr;
+    h.cfg = cfg ? *cfg : default_cfg(in.L);
+    if (!cfg_valid(in.L, h.cfg))
+        return fail(EA_ERR_ARG, "job %d: invalid launch configuration rw=%d nt=%d sel=%d", index, h.cfg.rw,
+                    h.cfg.nt, h.cfg.sel);
     h.R = in.L / 2;
-    h.RW = words_per_row(h.R);
+    h.RW = h.cfg.rw;
     h.W = h.R / h.RW;
     h.POS = in.L * in.L * h.RW;
     h.obs_stride = ea::M_AUTO + 2 * in.n_tw + 3 * (h.R + 1);
@@ -106,6 +126,9 @@ ea::BatchJobDev make_job_dev(const BatchJobHost &h)
 {
     ea::BatchJobDev d{};
     d.L = h.job.L;
+    d.rw = h.cfg.rw;
+    d.nt = h.cfg.nt;
+    d.sel = h.cfg.sel;
     d.k0 = (uint32_t)(h.job.seed & 0xffffffffu);
     d.k1 = (uint32_t)(h.job.seed >> 32);
     d.sample = h.job.sample;
@@ -203,6 +226,8 @@ ea_status read_job_spins(const BatchJobHost &h, int32_t r, int8_t *pm1, hipStrea
                           hipMemcpyDeviceToHost, stream));
     EA_HIP(hipStreamSynchronize(stream));
     Layout y = make_layout(h.job.L, 0);
+    y.RW = h.RW;
+    y.W = h.W;
     const int64_t N = (int64_t)h.job.L * h.job.L * h.job.L;
     for (int64_t i = 0; i < N; ++i) {
         SiteAddr a = address_of(y, i);
@@ -263,9 +288,204 @@ struct ea_batch {
     hipGraphExec_t graph_exec = nullptr;
 };
 
-extern "C" {
 
-ea_status ea_batch_create(const ea_job *jobs, int32_t n_jobs, const ea_batch_opts *opts, ea_batch **out)
+namespace {
+
+ea_status batch_create_cfg(const ea_job *jobs, int32_t n_jobs, void *stream, const TuneCfg *cfgs, ea_batch **out);
+
+// ---------------------------------------------------------------------------
+// Autotuner.  For one lattice size it times every valid combination of row
+// packing (the default and the next finer one, if its lattice fits LDS),
+// working threads per workgroup (256, 512, 1024, capped by the word count)
+// and threshold-select variant on a probe batch of 64 samples, keeps only
+// candidates whose results equal the default configuration's bit for bit,
+// and picks the fastest.  Choices are cached per process and, if the
+// environment variable EA_TUNE_CACHE names a file, across processes.
+
+struct TuneRecord {
+    TuneCfg cfg;
+    double ms = 0.0;
+    bool parity_ok = false;
+};
+
+std::mutex g_tune_mu;
+std::map<int, TuneCfg> g_tuned;
+bool g_tune_file_read = false;
+
+std::string device_arch()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t colon = a.find(':');
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+void read_tune_file()
+{
+    if (g_tune_file_read) return;
+    g_tune_file_read = true;
+    const char *path = std::getenv("EA_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    const std::string arch = device_arch();
+    char a[64];
+    int L, rw, nt, sel;
+    while (std::fscanf(f, "%63s %d %d %d %d%*[^\n]", a, &L, &rw, &nt, &sel) == 5) {
+        TuneCfg c;
+        c.rw = rw;
+        c.nt = nt;
+        c.sel = sel;
+        if (arch == a && batch_L_ok(L) && cfg_valid(L, c)) g_tuned[L] = c;
+    }
+    std::fclose(f);
+}
+
+void append_tune_file(int L, const TuneCfg &c, double ms)
+{
+    const char *path = std::getenv("EA_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %d %d %d %.4f\n", device_arch().c_str(), L, c.rw, c.nt, c.sel, ms);
+    std::fclose(f);
+}
+
+std::vector<TuneCfg> tune_candidates(int L, size_t lds_limit)
+{
+    std::vector<TuneCfg> out;
+    const int R = L / 2, rw0 = ea::words_per_row_c(R), rw1 = ea::finer_words_per_row_c(R, rw0);
+    const TuneCfg def = default_cfg(L);
+    out.push_back(def);  // the reference comes first
+    for (int rw : {rw0, rw1}) {
+        if (rw == 0) continue;
+        if (4 * (size_t)batch_lds_words(L, rw) + 4 * (size_t)ea::kSelectTableWords > lds_limit) continue;
+        const int words = L * L * rw;
+        for (int nt : {256, 512, 1024}) {
+            if (nt > round_up64(words) && nt != 256) continue;
+            for (int sel : {(int)ea::SEL_LDS, (int)ea::SEL_REG}) {
+                TuneCfg c;
+                c.rw = rw;
+                c.nt = std::min(nt, round_up64(words));
+                c.sel = sel;
+                bool dup = false;
+                for (const TuneCfg &o : out) dup = dup || (o.rw == c.rw && o.nt == c.nt && o.sel == c.sel);
+                if (!dup) out.push_back(c);
+            }
+        }
+    }
+    return out;
+}
+
+// Run the probe batch with one configuration; returns its results (all
+// measurement counters and the final spins, canonical order) and time.
+ea_status tune_probe(int L, const TuneCfg &cfg, std::vector<long long> &results, double &ms)
+{
+    const int n = 64;
+    const uint64_t N = (uint64_t)L * L * L;
+    const uint64_t sweeps = std::max<uint64_t>(8, (1ull << 22) / N);
+    std::vector<uint64_t> meas = {sweeps / 2, sweeps}, tw = {sweeps / 4};
+    std::vector<ea_job> jobs((size_t)n);
+    for (int i = 0; i < n; ++i) {
+        ea_job &j = jobs[(size_t)i];
+        j.L = L;
+        j.p = (i % 3 == 0) ? 0.2 : 0.5;
+        j.T = (i % 2 == 0) ? 0.6 : 1.0;
+        j.seed = 1000 + (uint64_t)i;
+        j.sample = 0;
+        j.n_sweeps = sweeps;
+        j.meas_t = meas.data();
+        j.n_meas = (int32_t)meas.size();
+        j.tw = tw.data();
+        j.n_tw = (int32_t)tw.size();
+    }
+    std::vector<TuneCfg> cfgs((size_t)n, cfg);
+    ea_batch *b = nullptr;
+    ea_status st = batch_create_cfg(jobs.data(), n, nullptr, cfgs.data(), &b);
+    if (st != EA_OK) return st;
+    st = ea_batch_run(b, sweeps);  // warm-up
+    if (st == EA_OK) st = ea_batch_reset(b);
+    if (st == EA_OK) {
+        const auto t0 = std::chrono::steady_clock::now();
+        st = ea_batch_run(b, sweeps);
+        ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    results.clear();
+    for (int i = 0; st == EA_OK && i < n; ++i) {
+        const BatchJobHost &h = b->jobs[(size_t)i];
+        std::vector<unsigned long long> obs((size_t)h.job.n_meas * (size_t)h.obs_stride);
+        hipError_t e = hipMemcpy(obs.data(), h.base + h.off_obs, 8 * obs.size(), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) st = fail(EA_ERR_DEVICE, "hipMemcpy: %s", hipGetErrorString(e));
+        for (unsigned long long v : obs) results.push_back((long long)v);
+        if (i < 4) {
+            std::vector<int8_t> spins(N);
+            for (int r = 0; st == EA_OK && r < 2; ++r) {
+                st = read_job_spins(h, r, spins.data(), b->stream);
+                for (int8_t v : spins) results.push_back(v);
+            }
+        }
+    }
+    ea_batch_destroy(b);
+    return st;
+}
+
+ea_status tune_lattice(int L, std::vector<TuneRecord> &tried, TuneCfg *best)
+{
+    int dev = 0, lds_limit = 0;
+    EA_HIP(hipGetDevice(&dev));
+    EA_HIP(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const std::vector<TuneCfg> cands = tune_candidates(L, (size_t)lds_limit);
+    std::vector<long long> ref;
+    tried.clear();
+    double best_ms = 0.0;
+    *best = cands[0];
+    for (size_t i = 0; i < cands.size(); ++i) {
+        TuneRecord rec;
+        rec.cfg = cands[i];
+        std::vector<long long> res;
+        ea_status st = tune_probe(L, cands[i], res, rec.ms);
+        if (st != EA_OK) return st;
+        if (i == 0) ref = res;
+        rec.parity_ok = res == ref;
+        tried.push_back(rec);
+        if (rec.parity_ok && (i == 0 || rec.ms < best_ms)) {
+            best_ms = rec.ms;
+            *best = cands[i];
+        }
+    }
+    return EA_OK;
+}
+
+// The configuration a job of size L runs with when tuning is requested.
+ea_status tuned_cfg(int L, TuneCfg *out)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    read_tune_file();
+    auto it = g_tuned.find(L);
+    if (it != g_tuned.end()) {
+        *out = it->second;
+        return EA_OK;
+    }
+    std::vector<TuneRecord> tried;
+    TuneCfg best;
+    ea_status st = tune_lattice(L, tried, &best);
+    if (st != EA_OK) return st;
+    g_tuned[L] = best;
+    double ms = 0.0;
+    for (const TuneRecord &r : tried)
+        if (r.cfg.rw == best.rw && r.cfg.nt == best.nt && r.cfg.sel == best.sel) ms = r.ms;
+    append_tune_file(L, best, ms);
+    *out = best;
+    return EA_OK;
+}
+
+}  // namespace
+
+namespace {
+
+ea_status batch_create_cfg(const ea_job *jobs, int32_t n_jobs, void *stream, const TuneCfg *cfgs, ea_batch **out)
 {
     if (!out) return fail(EA_ERR_ARG, "out is NULL");
     *out = nullptr;
@@ -277,14 +497,14 @@ ea_status ea_batch_create(const ea_job *jobs, int32_t n_jobs, const ea_batch_opt
     int max_lds = 0;
     std::vector<size_t> region((size_t)n_jobs);
     for (int32_t j = 0; j < n_jobs; ++j) {
-        ea_status st = plan_job(jobs[j], j, b->jobs[(size_t)j]);
+        ea_status st = plan_job(jobs[j], j, b->jobs[(size_t)j], cfgs ? &cfgs[j] : nullptr);
         if (st != EA_OK) {
             delete b;
             return st;
         }
         region[(size_t)j] = off = align256(off);
         off += b->jobs[(size_t)j].bytes;
-        max_lds = std::max(max_lds, batch_lds_words(jobs[j].L));
+        max_lds = std::max(max_lds, batch_lds_words(jobs[j].L, b->jobs[(size_t)j].RW));
     }
     const size_t off_jobs = align256(off);
     off = off_jobs + sizeof(ea::BatchJobDev) * (size_t)n_jobs;
@@ -301,8 +521,8 @@ ea_status ea_batch_create(const ea_job *jobs, int32_t n_jobs, const ea_batch_opt
         return st;
     }
     hipError_t e;
-    if (opts && opts->stream) {
-        b->stream = (hipStream_t)opts->stream;
+    if (stream) {
+        b->stream = (hipStream_t)stream;
     } else {
         e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
         if (e != hipSuccess) {
@@ -348,6 +568,69 @@ ea_status ea_batch_create(const ea_job *jobs, int32_t n_jobs, const ea_batch_opt
         return st;
     }
     *out = b;
+    return EA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ea_status ea_batch_create(const ea_job *jobs, int32_t n_jobs, const ea_batch_opts *opts, ea_batch **out)
+{
+    if (!out) return fail(EA_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!jobs || n_jobs <= 0) return fail(EA_ERR_ARG, "need at least one job");
+    std::vector<TuneCfg> cfgs((size_t)n_jobs);
+    for (int32_t j = 0; j < n_jobs; ++j) {
+        if (!batch_L_ok(jobs[j].L))
+            return fail(EA_ERR_ARG, "job %d: L=%d must be a multiple of 8 in [8, %d] for the batched form", j,
+                        jobs[j].L, ea::kBatchMaxL);
+        cfgs[(size_t)j] = default_cfg(jobs[j].L);
+        if (opts && opts->autotune) {
+            ea_status st = tuned_cfg(jobs[j].L, &cfgs[(size_t)j]);
+            if (st != EA_OK) return st;
+        }
+    }
+    return batch_create_cfg(jobs, n_jobs, opts ? opts->stream : nullptr, cfgs.data(), out);
+}
+
+ea_status ea_tune(int32_t L, int32_t force, ea_tune_choice *chosen, ea_tune_choice *tried, int32_t max_tried,
+                  int32_t *n_tried)
+{
+    if (!chosen) return fail(EA_ERR_ARG, "chosen is NULL");
+    if (!batch_L_ok(L)) return fail(EA_ERR_ARG, "L=%d has no batched configuration", L);
+    std::vector<TuneRecord> recs;
+    TuneCfg best;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        read_tune_file();
+        auto it = g_tuned.find(L);
+        if (it != g_tuned.end() && !force) {
+            best = it->second;
+        } else {
+            ea_status st = tune_lattice(L, recs, &best);
+            if (st != EA_OK) return st;
+            g_tuned[L] = best;
+            double ms = 0.0;
+            for (const TuneRecord &r : recs)
+                if (r.cfg.rw == best.rw && r.cfg.nt == best.nt && r.cfg.sel == best.sel) ms = r.ms;
+            append_tune_file(L, best, ms);
+        }
+    }
+    auto put = [](ea_tune_choice *c, const TuneCfg &cfg, double ms, bool ok) {
+        c->words_per_row = cfg.rw;
+        c->threads = cfg.nt;
+        c->select = cfg.sel;
+        c->ms = ms;
+        c->parity_ok = ok ? 1 : 0;
+    };
+    double best_ms = 0.0;
+    for (const TuneRecord &r : recs)
+        if (r.cfg.rw == best.rw && r.cfg.nt == best.nt && r.cfg.sel == best.sel) best_ms = r.ms;
+    put(chosen, best, best_ms, true);
+    if (n_tried) *n_tried = (int32_t)recs.size();
+    for (size_t i = 0; tried && i < recs.size() && (int32_t)i < max_tried; ++i)
+        put(&tried[i], recs[i].cfg, recs[i].ms, recs[i].parity_ok);
     return EA_OK;
 }
 

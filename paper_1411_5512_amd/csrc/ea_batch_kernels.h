@@ -28,22 +28,36 @@ __host__ __device__ constexpr int words_per_row_c(int R)
     return rw;
 }
 
-// Compile-time geometry of one lattice size.
-template <int L>
+// The next finer valid packing of a row of R sites: the smallest word count
+// above rw that splits the row into whole 4-site blocks (0 if none).
+__host__ __device__ constexpr int finer_words_per_row_c(int R, int rw)
+{
+    for (int d = rw + 1; d <= R / 4; ++d)
+        if ((R / 4) % d == 0) return d;
+    return 0;
+}
+
+// Compile-time geometry of one lattice size and row packing.
+template <int L, int RW>
 struct Shape {
     static constexpr int R = L / 2;
-    static constexpr int RW = words_per_row_c(R);
     static constexpr int W = R / RW;
     static constexpr int POS = L * L * RW;  // packed words per colour
-    static constexpr int NT = POS >= kBatchThreads ? kBatchThreads : ((POS + 63) / 64) * 64;
-    static constexpr int P = (POS + NT - 1) / NT;  // words per thread per half-step
     static constexpr int LATTICE_WORDS = 8 * POS;  // 2 spin planes + 6 coupling planes
     static constexpr int LDS_WORDS = LATTICE_WORDS + 16;  // dynamic LDS: lattice + flag
+    static_assert(R % RW == 0 && W % 4 == 0 && W <= 32, "invalid row packing");
 };
+
+// Threshold select of the update: through the LDS tables or with register
+// bit-field selects.
+enum : int { SEL_LDS = 0, SEL_REG = 1 };
 
 // Device-side description of one sample in a batch.
 struct BatchJobDev {
     int32_t L;
+    int32_t rw;   // words per row of the packed layout
+    int32_t nt;   // threads of the workgroup that work (multiple of 64, <= kBatchThreads)
+    int32_t sel;  // SEL_LDS or SEL_REG
     uint32_t k0, k1, sample;
     uint32_t thr1, thr2, thr3;
     int32_t n_meas, n_tw, obs_stride;
@@ -82,31 +96,30 @@ __shared__ uint32_t batch_select_tables[kSelectTableWords];
 
 __device__ __forceinline__ uint32_t *batch_tables() { return batch_select_tables; }
 
-template <int L>
+template <class S>
 __device__ __forceinline__ uint32_t *lds_spin(int c)
 {
-    return batch_lds + c * Shape<L>::POS;
+    return batch_lds + c * S::POS;
 }
 
-template <int L>
+template <class S>
 __device__ __forceinline__ uint32_t *lds_bond(int d, int c)
 {
-    return batch_lds + (2 + 2 * d + c) * Shape<L>::POS;
+    return batch_lds + (2 + 2 * d + c) * S::POS;
 }
 
 // Update the colour-c words of this workgroup's replica (eq. 9), reading the
 // other colour and the couplings from LDS.
-template <int L>
+template <int L, int RW, int SEL>
 __device__ __forceinline__ void batch_half_step(const BatchJobDev &J, int r, int c, uint32_t t)
 {
-    using S = Shape<L>;
-    constexpr int RW = S::RW, W = S::W;
-    uint32_t *own = lds_spin<L>(c);
-    const uint32_t *oth = lds_spin<L>(c ^ 1);
-    const uint32_t *bx_own = lds_bond<L>(0, c), *by_own = lds_bond<L>(1, c),
-                   *bz_own = lds_bond<L>(2, c);
-    const uint32_t *bx_oth = lds_bond<L>(0, c ^ 1), *by_oth = lds_bond<L>(1, c ^ 1),
-                   *bz_oth = lds_bond<L>(2, c ^ 1);
+    using S = Shape<L, RW>;
+    constexpr int W = S::W;
+    uint32_t *own = lds_spin<S>(c);
+    const uint32_t *oth = lds_spin<S>(c ^ 1);
+    const uint32_t *bx_own = lds_bond<S>(0, c), *by_own = lds_bond<S>(1, c), *bz_own = lds_bond<S>(2, c);
+    const uint32_t *bx_oth = lds_bond<S>(0, c ^ 1), *by_oth = lds_bond<S>(1, c ^ 1),
+                   *bz_oth = lds_bond<S>(2, c ^ 1);
     const uint32_t c2 = counter_word2(TAG_METRO, (uint32_t)c, (uint32_t)r);
     // Recompute the addresses every half-step: hoisting them out of the
     // sweep loop would keep some thirty address registers live and spill.
@@ -115,19 +128,17 @@ __device__ __forceinline__ void batch_half_step(const BatchJobDev &J, int r, int
     // one word at a time: a word already carries W/4 independent Philox
     // blocks of instruction-level parallelism, and unrolling further spills
 #pragma unroll 1
-    for (int k = 0; k < S::P; ++k) {
-        const int p = tid + k * S::NT;
-        if (S::POS % S::NT != 0 && p >= S::POS) break;
-        const int row = p / RW;
-        const int w = p - row * RW;
-        const int y = row % L;
-        const int z = row / L;
-        const int par = (y + z + c) & 1;
-        const int wm = w == 0 ? RW - 1 : w - 1;
-        const int wp = w == RW - 1 ? 0 : w + 1;
-        const int ym = (y == 0 ? L - 1 : y - 1) + L * z, yp = (y == L - 1 ? 0 : y + 1) + L * z;
-        const int zm = y + L * (z == 0 ? L - 1 : z - 1), zp = y + L * (z == L - 1 ? 0 : z + 1);
-        const int base = row * RW;
+    for (int p = tid; p < S::POS; p += J.nt) {
+        const unsigned row = (unsigned)p / RW;
+        const unsigned w = (unsigned)p - row * RW;
+        const unsigned y = row % L;
+        const unsigned z = row / L;
+        const int par = (int)((y + z + (unsigned)c) & 1u);
+        const unsigned wm = w == 0 ? RW - 1 : w - 1;
+        const unsigned wp = w == RW - 1 ? 0 : w + 1;
+        const unsigned ym = (y == 0 ? L - 1 : y - 1) + L * z, yp = (y == L - 1 ? 0 : y + 1) + L * z;
+        const unsigned zm = y + L * (z == 0 ? L - 1 : z - 1), zp = y + L * (z == L - 1 ? 0 : z + 1);
+        const unsigned base = row * RW;
         const uint32_t S0 = own[p];
         const uint32_t O = oth[base + w], Om = oth[base + wm], Op = oth[base + wp];
         const uint32_t Xo = bx_oth[base + w], Xom = bx_oth[base + wm];
@@ -141,30 +152,36 @@ __device__ __forceinline__ void batch_half_step(const BatchJobDev &J, int r, int
         const uint32_t a6 = xor3(S0, oth[zm * RW + w], bz_oth[zm * RW + w]);
         const Decision d = classify(a1, a2, a3, a4, a5, a6);
         const uint32_t quad0 = (uint32_t)((row * S::R + w * W) >> 2);
-        own[p] = S0 ^ flip_mask_lds<W>(d, t, quad0, c2, J.sample, J.k0, J.k1, batch_tables());
+        uint32_t flips;
+        if constexpr (SEL == SEL_LDS)
+            flips = flip_mask_lds<W>(d, t, quad0, c2, J.sample, J.k0, J.k1, batch_tables());
+        else
+            flips = flip_mask<W>(d, t, quad0, c2, J.sample, J.k0, J.k1, J.thr1, J.thr2, J.thr3);
+        own[p] = S0 ^ flips;
     }
 }
 
 // Copy this replica's two colour planes between LDS and a global array.
-template <int L>
-__device__ __forceinline__ void batch_store_spins(uint32_t *dst)
+template <class S>
+__device__ __forceinline__ void batch_store_spins(uint32_t *dst, int nt)
 {
-    for (int i = (int)threadIdx.x; i < 2 * Shape<L>::POS; i += Shape<L>::NT) dst[i] = batch_lds[i];
+    for (int i = (int)threadIdx.x; i < 2 * S::POS; i += nt) dst[i] = batch_lds[i];
 }
 
 // Measurement at time t (index m) of replica r.
-template <int L>
+template <int L, int RW>
 __device__ void batch_measure(const BatchJobDev &J, int r, int m, int n_taken)
 {
-    using S = Shape<L>;
-    constexpr int RW = S::RW, W = S::W, POS = S::POS;
+    using S = Shape<L, RW>;
+    constexpr int W = S::W, POS = S::POS;
+    const int nt = J.nt;
     unsigned long long *o = J.obs + (size_t)m * (size_t)J.obs_stride;
     uint32_t unsat = 0, down = 0;
 #pragma unroll 1
     for (int c = 0; c < 2; ++c) {
-        const uint32_t *own = lds_spin<L>(c);
-        const uint32_t *oth = lds_spin<L>(c ^ 1);
-        for (int p = (int)threadIdx.x; p < POS; p += S::NT) {
+        const uint32_t *own = lds_spin<S>(c);
+        const uint32_t *oth = lds_spin<S>(c ^ 1);
+        for (int p = (int)threadIdx.x; p < POS; p += nt) {
             const int row = p / RW;
             const int w = p - row * RW;
             const int y = row % L;
@@ -176,9 +193,9 @@ __device__ void batch_measure(const BatchJobDev &J, int r, int m, int n_taken)
             const uint32_t Sv = own[p];
             const uint32_t O = oth[row * RW + w];
             const uint32_t xp = par ? take_plus1<W>(O, oth[row * RW + wp]) : O;
-            unsat += __popc(Sv ^ xp ^ lds_bond<L>(0, c)[p]) +
-                     __popc(xor3(Sv, oth[yp * RW + w], lds_bond<L>(1, c)[p])) +
-                     __popc(xor3(Sv, oth[zp * RW + w], lds_bond<L>(2, c)[p]));
+            unsat += __popc(Sv ^ xp ^ lds_bond<S>(0, c)[p]) +
+                     __popc(xor3(Sv, oth[yp * RW + w], lds_bond<S>(1, c)[p])) +
+                     __popc(xor3(Sv, oth[zp * RW + w], lds_bond<S>(2, c)[p]));
             down += __popc(Sv);
         }
     }
@@ -188,13 +205,13 @@ __device__ void batch_measure(const BatchJobDev &J, int r, int m, int n_taken)
     for (int k = 0; k < n_taken; ++k) {
         const uint32_t *ref = J.snaps + ((size_t)k * 2 + (size_t)r) * 2 * POS;
         uint32_t diff = 0;
-        for (int i = (int)threadIdx.x; i < 2 * POS; i += S::NT) diff += __popc(batch_lds[i] ^ ref[i]);
+        for (int i = (int)threadIdx.x; i < 2 * POS; i += nt) diff += __popc(batch_lds[i] ^ ref[i]);
         wave_add(o + M_AUTO + 2 * k + r, diff);
     }
 
     // Publish this replica's configuration; the second replica to arrive
     // computes the overlap and C4 from both copies.
-    batch_store_spins<L>(J.mspins + ((size_t)m * 2 + (size_t)r) * 2 * POS);
+    batch_store_spins<S>(J.mspins + ((size_t)m * 2 + (size_t)r) * 2 * POS, nt);
     __threadfence();
     __syncthreads();
     uint32_t *flag = batch_lds + S::LATTICE_WORDS;
@@ -208,7 +225,7 @@ __device__ void batch_measure(const BatchJobDev &J, int r, int m, int n_taken)
     const uint32_t *q0 = J.mspins + (size_t)m * 4 * POS;
     const uint32_t *q1 = q0 + 2 * POS;
     uint32_t qdiff = 0;
-    for (int i = (int)threadIdx.x; i < 2 * POS; i += S::NT) qdiff += __popc(q0[i] ^ q1[i]);
+    for (int i = (int)threadIdx.x; i < 2 * POS; i += nt) qdiff += __popc(q0[i] ^ q1[i]);
     wave_add(o + M_QDIFF, qdiff);
 
     unsigned long long *c4 = o + batch_c4_base(J.n_tw);
@@ -221,7 +238,7 @@ __device__ void batch_measure(const BatchJobDev &J, int r, int m, int n_taken)
             for (int c = 0; c < 2; ++c) {
                 const int cp = c ^ (rho & 1);
 #pragma unroll 1
-                for (int p = (int)threadIdx.x; p < POS; p += S::NT) {
+                for (int p = (int)threadIdx.x; p < POS; p += nt) {
                     const int row = p / RW;
                     const int w = p - row * RW;
                     const int y = row % L;
@@ -253,17 +270,18 @@ __device__ void batch_measure(const BatchJobDev &J, int r, int m, int n_taken)
 // Run one unit: load the replica and the couplings into LDS, sweep up to
 // t_stop taking the events scheduled in (t0, t_stop] (and at t0 itself on the
 // job's first span), then write the replica back.
-template <int L>
+template <int L, int RW, int SEL>
 __device__ void batch_run_unit(const BatchJobDev &J, int r, uint32_t t_stop, bool first)
 {
-    using S = Shape<L>;
-    if ((int)threadIdx.x >= S::NT) return;  // whole surplus waves leave the barrier set
+    using S = Shape<L, RW>;
+    const int nt = J.nt;
+    if ((int)threadIdx.x >= nt) return;  // whole surplus waves leave the barrier set
     const uint32_t t0 = J.t_now[r];
     if (!first && t0 >= t_stop) return;
     const uint32_t *src = J.spins + (size_t)r * 2 * S::POS;
-    for (int i = (int)threadIdx.x; i < 2 * S::POS; i += S::NT) batch_lds[i] = src[i];
-    for (int i = (int)threadIdx.x; i < 6 * S::POS; i += S::NT) batch_lds[2 * S::POS + i] = J.bonds[i];
-    fill_select_tables(batch_tables(), J.thr1, J.thr2, J.thr3, (int)threadIdx.x, S::NT);
+    for (int i = (int)threadIdx.x; i < 2 * S::POS; i += nt) batch_lds[i] = src[i];
+    for (int i = (int)threadIdx.x; i < 6 * S::POS; i += nt) batch_lds[2 * S::POS + i] = J.bonds[i];
+    if constexpr (SEL == SEL_LDS) fill_select_tables(batch_tables(), J.thr1, J.thr2, J.thr3, (int)threadIdx.x, nt);
     __syncthreads();
 
     int im = 0, iw = 0;
@@ -273,25 +291,44 @@ __device__ void batch_run_unit(const BatchJobDev &J, int r, uint32_t t_stop, boo
     uint32_t t = t0;
     for (;;) {
         if (iw < J.n_tw && J.tw_t[iw] == t) {
-            batch_store_spins<L>(J.snaps + ((size_t)iw * 2 + (size_t)r) * 2 * S::POS);
+            batch_store_spins<S>(J.snaps + ((size_t)iw * 2 + (size_t)r) * 2 * S::POS, nt);
             ++iw;
             __threadfence();
             __syncthreads();
         }
         if (im < J.n_meas && J.meas_t[im] == t) {
-            batch_measure<L>(J, r, im, iw);
+            batch_measure<L, RW>(J, r, im, iw);
             ++im;
             __syncthreads();
         }
         if (t >= t_stop) break;
-        batch_half_step<L>(J, r, r, t);
+        batch_half_step<L, RW, SEL>(J, r, r, t);
         __syncthreads();
-        batch_half_step<L>(J, r, r ^ 1, t);
+        batch_half_step<L, RW, SEL>(J, r, r ^ 1, t);
         __syncthreads();
         ++t;
     }
-    batch_store_spins<L>(J.spins + (size_t)r * 2 * S::POS);
+    batch_store_spins<S>(J.spins + (size_t)r * 2 * S::POS, nt);
     if (threadIdx.x == 0) J.t_now[r] = t;
+}
+
+// Dispatch on the packing (finest valid alternative or the default) and the
+// select variant for one lattice size.
+template <int L>
+__device__ __forceinline__ void batch_dispatch_L(const BatchJobDev &J, int r, uint32_t t_stop, bool first)
+{
+    constexpr int R = L / 2;
+    constexpr int RW0 = words_per_row_c(R);
+    constexpr int RW1 = finer_words_per_row_c(R, RW0);
+    if (J.rw == RW0) {
+        if (J.sel == SEL_LDS) batch_run_unit<L, RW0, SEL_LDS>(J, r, t_stop, first);
+        else batch_run_unit<L, RW0, SEL_REG>(J, r, t_stop, first);
+    } else if constexpr (RW1 != 0) {
+        if (J.rw == RW1) {
+            if (J.sel == SEL_LDS) batch_run_unit<L, RW1, SEL_LDS>(J, r, t_stop, first);
+            else batch_run_unit<L, RW1, SEL_REG>(J, r, t_stop, first);
+        }
+    }
 }
 
 __global__ __launch_bounds__(kBatchThreads) void batch_kernel(const BatchJobDev *__restrict__ jobs,
@@ -299,15 +336,16 @@ __global__ __launch_bounds__(kBatchThreads) void batch_kernel(const BatchJobDev 
 {
     const BatchUnit u = units[blockIdx.x];
     const BatchJobDev J = jobs[u.job];
+    const bool first = u.first != 0;
     switch (J.L) {
-    case 8: batch_run_unit<8>(J, u.replica, u.t_stop, u.first != 0); break;
-    case 16: batch_run_unit<16>(J, u.replica, u.t_stop, u.first != 0); break;
-    case 24: batch_run_unit<24>(J, u.replica, u.t_stop, u.first != 0); break;
-    case 32: batch_run_unit<32>(J, u.replica, u.t_stop, u.first != 0); break;
-    case 40: batch_run_unit<40>(J, u.replica, u.t_stop, u.first != 0); break;
-    case 48: batch_run_unit<48>(J, u.replica, u.t_stop, u.first != 0); break;
-    case 56: batch_run_unit<56>(J, u.replica, u.t_stop, u.first != 0); break;
-    case 64: batch_run_unit<64>(J, u.replica, u.t_stop, u.first != 0); break;
+    case 8: batch_dispatch_L<8>(J, u.replica, u.t_stop, first); break;
+    case 16: batch_dispatch_L<16>(J, u.replica, u.t_stop, first); break;
+    case 24: batch_dispatch_L<24>(J, u.replica, u.t_stop, first); break;
+    case 32: batch_dispatch_L<32>(J, u.replica, u.t_stop, first); break;
+    case 40: batch_dispatch_L<40>(J, u.replica, u.t_stop, first); break;
+    case 48: batch_dispatch_L<48>(J, u.replica, u.t_stop, first); break;
+    case 56: batch_dispatch_L<56>(J, u.replica, u.t_stop, first); break;
+    case 64: batch_dispatch_L<64>(J, u.replica, u.t_stop, first); break;
     default: break;
     }
 }

@@ -160,6 +160,8 @@ ea_status server_epoch(ea_server *s, int32_t *progressed)
         hs.push_back(&j->h);
         dj.push_back(make_job_dev(j->h));
     }
+    size_t lds = 0;
+    for (BatchJobHost *h : hs) lds = std::max(lds, (size_t)batch_lds_words(h->job.L, h->RW) * 4);
     std::vector<ea::BatchUnit> units;
     order_units(hs, span, units);
     for (auto &u : units) {
@@ -172,8 +174,8 @@ ea_status server_epoch(ea_server *s, int32_t *progressed)
                           s->stream));
     EA_HIP(hipMemcpyAsync(s->d_units, units.data(), sizeof(ea::BatchUnit) * units.size(), hipMemcpyHostToDevice,
                           s->stream));
-    hipLaunchKernelGGL(ea::batch_kernel, dim3((unsigned)units.size()), dim3(ea::kBatchThreads), s->lds_bytes,
-                       s->stream, s->d_jobs, s->d_units);
+    hipLaunchKernelGGL(ea::batch_kernel, dim3((unsigned)units.size()), dim3(ea::kBatchThreads), lds, s->stream,
+                       s->d_jobs, s->d_units);
     EA_HIP(hipGetLastError());
     EA_HIP(hipStreamSynchronize(s->stream));
     const auto t1 = steady::now();
@@ -270,7 +272,7 @@ ea_status ea_server_create(const ea_server_opts *opts, ea_server **out)
     if (!s) return fail(EA_ERR_NOMEM, "host allocation failed");
     s->opts = *opts;
     if (!s->opts.epoch_site_sweeps) s->opts.epoch_site_sweeps = 64ull * 64 * 64 * 64;
-    s->lds_bytes = (size_t)batch_lds_words(ea::kBatchMaxL) * 4;
+    s->lds_bytes = (size_t)batch_lds_words(ea::kBatchMaxL, ea::words_per_row_c(ea::kBatchMaxL / 2)) * 4;
     ea_status st = prepare_batch_lds(s->lds_bytes);
     hipError_t e = hipGetDevice(&s->device);
     if (st == EA_OK && e != hipSuccess) st = fail(EA_ERR_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
