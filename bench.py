@@ -109,15 +109,39 @@ def bench_plain(ea, torch, job, steps: int, burst: int):
     }
 
 
-def bench_serving(ea, wl, n_jobs: int, load: float, ps_per_flip_capacity: float):
-    """Poisson stream of jobs (L in {16..64}, p ~ U[0.1,0.5], T ~ U[0.5,1.2],
-    sweeps log-uniform in [1e3, 1e5], log-spaced schedules) offered at
-    `load` times the batched form's measured capacity; continuous batching
-    with admission by an HBM budget."""
-    stream = wl.serve_jobs(n_jobs=n_jobs, sweep_range=(1_000, 100_000), sizes=(16, 24, 32, 48, 64))
-    mean_flips = sum(j.flips for _, j in stream) / len(stream)
-    gap_s = mean_flips * ps_per_flip_capacity * 1e-12 / load
-    budget = 256 << 20
+def plain_rate(ea, torch, L: int, sweeps: int = 256) -> float:
+    """ps per attempted flip of the plain form at size L (p = 0.5, T = 0.7),
+    a burst of captured sweeps timed with events on the run's stream."""
+    sim = ea.Sim(L, 0.5, 0.7, seed=1)
+    sim.sweep(64)  # builds the captured graph
+    b0 = torch.cuda.Event(enable_timing=True)
+    b1 = torch.cuda.Event(enable_timing=True)
+    b0.record(sim.stream)
+    sim.sweep(sweeps)
+    b1.record(sim.stream)
+    torch.cuda.synchronize()
+    ms = b0.elapsed_time(b1)
+    sim.close()
+    return ms * 1e-3 / (sweeps * 2 * L ** 3) * 1e12
+
+
+SERVE_SIZES = (16, 24, 32, 48, 64, 96, 128)
+
+
+def bench_serving(ea, torch, wl, n_jobs: int, load: float, sweep_hi: int, ps_batched: float):
+    """Poisson stream of jobs (L uniform over {16,...,128}, p ~ U[0.1,0.5],
+    T ~ U[0.5,1.2], sweeps log-uniform in [1e3, sweep_hi], log-spaced
+    schedules) offered at `load` times the capacity measured for each form
+    (batched rate for L <= 64, plain rate per size above); continuous
+    batching with admission by an HBM budget."""
+    stream = wl.serve_jobs(n_jobs=n_jobs, sweep_range=(1_000, sweep_hi), sizes=SERVE_SIZES)
+    rate = {L: ps_batched for L in SERVE_SIZES if L <= 64}
+    for L in SERVE_SIZES:
+        if L > 64:
+            rate[L] = plain_rate(ea, torch, L)
+    capacity_s = sum(j.flips * rate[j.L] for _, j in stream) * 1e-12
+    gap_s = capacity_s / len(stream) / load
+    budget = 1 << 30
     srv = ea.Server(hbm_budget=budget, max_resident=512)
     srv.start()
     t0 = time.perf_counter()
@@ -133,14 +157,17 @@ def bench_serving(ea, wl, n_jobs: int, load: float, ps_per_flip_capacity: float)
     total = sum(j.flips for _, j in stream)
     srv.close()
     return {
-        "workload": f"{n_jobs} Poisson arrivals at load {load} of the batched capacity (mean gap "
-                    f"{gap_s * 1e3:.2f} ms), L in {{16,24,32,48,64}}, p~U[0.1,0.5], T~U[0.5,1.2], "
-                    f"sweeps log-uniform in [1e3,1e5], 20 log-spaced measurements; HBM budget {budget >> 20} MiB",
+        "workload": f"{n_jobs} Poisson arrivals (mean gap {gap_s * 1e3:.2f} ms = load {load} of the capacity "
+                    f"measured per form), L uniform in {{16,24,32,48,64,96,128}} (L > 64 streamed from HBM "
+                    f"beside the batched launch), p~U[0.1,0.5], T~U[0.5,1.2], sweeps log-uniform in "
+                    f"[1e3,{sweep_hi:.0e}], 20 log-spaced measurements; HBM budget {budget >> 20} MiB",
         "p50_latency_s": round(st["p50_latency_s"], 4),
         "p99_latency_s": round(st["p99_latency_s"], 4),
         "mean_latency_s": round(st["mean_latency_s"], 4),
         "ps_per_flip_busy": round(st["ps_per_flip"], 4),
         "ps_per_flip_wall": round(wall / total * 1e12, 4),
+        "plain_ps_per_flip": {str(L): round(rate[L], 3) for L in SERVE_SIZES if L > 64},
+        "flips": total,
         "epochs": int(st["epochs"]),
         "hbm_peak_mib": round(st["hbm_peak"] / 2 ** 20, 1),
         "wall_s": round(wall, 3),
@@ -162,6 +189,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="run every size with its default configuration")
     ap.add_argument("--serve-jobs", type=int, default=300, help="jobs in the serving leg (0 = skip)")
     ap.add_argument("--serve-load", type=float, default=0.8, help="offered load of the serving leg")
+    ap.add_argument("--serve-sweeps", type=int, default=10_000, help="upper end of the serving sweep range")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (a known-size kernel "
                          "for calibrating hardware byte counters) and exit")
@@ -278,7 +306,8 @@ def main():
 
     if args.serve_jobs:
         log("serving form ...")
-        out["serving"] = bench_serving(ea, wl, args.serve_jobs, args.serve_load, ps_per_flip)
+        out["serving"] = bench_serving(ea, torch, wl, args.serve_jobs, args.serve_load, args.serve_sweeps,
+                                       ps_per_flip)
     if not args.no_plain:
         log("plain form ...")
         plain = bench_plain(ea, torch, wl.mid_job(args.sweeps), args.plain_steps, args.burst)

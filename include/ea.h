@@ -229,17 +229,24 @@ ea_status ea_batch_result(ea_batch *b, int32_t job, int32_t k, ea_obs *out);
 ea_status ea_batch_get_spins(ea_batch *b, int32_t job, int32_t r, int8_t *pm1);
 
 /* ------------------------------------------------------------------------
- * Serving form: continuous batching of a stream of jobs (L <= 64, as for
- * the batched form).  Jobs are admitted first-come first-served while their
- * device footprint fits hbm_budget and fewer than max_resident are resident;
- * each epoch is one persistent launch that advances every resident job by
- * about epoch_site_sweeps site updates per replica (at least one sweep),
- * taking its scheduled snapshots and measurements.  Finished jobs hand their
- * results to the host and free their memory; waiting jobs join at the next
- * epoch.  A job's results are identical to a run alone (ea_create or
- * ea_batch_create) with the same parameters.  The calls are thread-safe:
- * jobs can be submitted while a worker thread (ea_server_start) runs the
- * epochs.
+ * Serving form: continuous batching of a stream of jobs.  The dynamics
+ * (Sec. III, eq. 9) and measurements (eqs. 1-3, 7) are those of a run
+ * alone; only the scheduling is new.  Jobs are admitted first-come
+ * first-served while their device footprint fits hbm_budget and fewer than
+ * max_resident are resident.  Each epoch advances every resident job by a
+ * span of sweeps, taking its scheduled snapshots and measurements:
+ *   - L <= 64: one persistent launch of the batched kernel holds every such
+ *     job in LDS; its span is about epoch_site_sweeps site updates per
+ *     replica (at least one sweep);
+ *   - 64 < L <= 256 (multiple of 8): the job is a plain-form simulation in
+ *     its pool region, advanced through the HBM-streaming kernels on a second
+ *     library stream while the batched launch runs; its span is sized so
+ *     that the streamed work takes about as long as the last batched launch.
+ * Finished jobs hand their results to the host and free their memory;
+ * waiting jobs join at the next epoch.  A job's results are identical to a
+ * run alone (ea_create, or ea_batch_create for L <= 64) with the same
+ * parameters.  The calls are thread-safe: jobs can be submitted while a
+ * worker thread (ea_server_start) runs the epochs.
  */
 typedef struct ea_server ea_server;
 
@@ -248,7 +255,7 @@ typedef struct {
     int32_t max_resident;        /* resident jobs at most (1..4096) */
     int32_t max_pending;         /* waiting jobs at most; submit returns EA_ERR_BUSY beyond */
     uint64_t epoch_site_sweeps;  /* site updates per replica per epoch; 0 = 64^4 */
-    void *stream;                /* hipStream_t, or NULL for a library stream */
+    void *stream;                /* hipStream_t of the batched launches, or NULL for a library stream */
 } ea_server_opts;
 
 typedef struct {

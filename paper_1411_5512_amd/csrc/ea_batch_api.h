@@ -70,12 +70,10 @@ ea_status copy_schedule(const uint64_t *src, int32_t n, uint64_t n_sweeps, const
     return EA_OK;
 }
 
-// Validate a job and lay out its device region (offsets from 0).
-ea_status plan_job(const ea_job &in, int index, BatchJobHost &h, const TuneCfg *cfg = nullptr)
+// Checks and host data shared by both kinds of job: parameters, schedules,
+// thresholds, coupling cut and the size of one measurement's counters.
+ea_status plan_common(const ea_job &in, int index, BatchJobHost &h)
 {
-    if (!batch_L_ok(in.L))
-        return fail(EA_ERR_ARG, "job %d: L=%d must be a multiple of 8 in [8, %d] for the batched form", index,
-                    in.L, ea::kBatchMaxL);
     if (!(in.p >= 0.0 && in.p <= 1.0)) return fail(EA_ERR_ARG, "job %d: p=%g outside [0, 1]", index, in.p);
     if (!(in.T >= 0.0) || !std::isfinite(in.T))
         return fail(EA_ERR_ARG, "job %d: T=%g must be finite and >= 0", index, in.T);
@@ -87,17 +85,29 @@ ea_status plan_job(const ea_job &in, int index, BatchJobHost &h, const TuneCfg *
     h.job = in;
     h.job.meas_t = nullptr;
     h.job.tw = nullptr;
+    h.R = in.L / 2;
+    h.obs_stride = ea::M_AUTO + 2 * in.n_tw + 3 * (h.R + 1);
+    host_thresholds(in.T, h.thr);
+    h.pcut = (uint64_t)std::floor(std::ldexp(in.p, 32));
+    return EA_OK;
+}
+
+// Validate a job of the batched kernel and lay out its device region
+// (offsets from 0).
+ea_status plan_job(const ea_job &in, int index, BatchJobHost &h, const TuneCfg *cfg = nullptr)
+{
+    if (!batch_L_ok(in.L))
+        return fail(EA_ERR_ARG, "job %d: L=%d must be a multiple of 8 in [8, %d] for the batched form", index,
+                    in.L, ea::kBatchMaxL);
+    ea_status st = plan_common(in, index, h);
+    if (st != EA_OK) return st;
     h.cfg = cfg ? *cfg : default_cfg(in.L);
     if (!cfg_valid(in.L, h.cfg))
         return fail(EA_ERR_ARG, "job %d: invalid launch configuration rw=%d nt=%d sel=%d", index, h.cfg.rw,
                     h.cfg.nt, h.cfg.sel);
-    h.R = in.L / 2;
     h.RW = h.cfg.rw;
     h.W = h.R / h.RW;
     h.POS = in.L * in.L * h.RW;
-    h.obs_stride = ea::M_AUTO + 2 * in.n_tw + 3 * (h.R + 1);
-    host_thresholds(in.T, h.thr);
-    h.pcut = (uint64_t)std::floor(std::ldexp(in.p, 32));
     const size_t spin4 = 4 * (size_t)h.POS;  // words of [replica][colour]
     size_t off = 0;
     h.off_spins = off;
@@ -119,6 +129,24 @@ ea_status plan_job(const ea_job &in, int index, BatchJobHost &h, const TuneCfg *
     h.off_tw = off = align256(off);
     off += 4 * (size_t)in.n_tw;
     h.bytes = align256(off);
+    return EA_OK;
+}
+
+// A job whose lattice does not fit one workgroup's LDS: it runs through the
+// plain form's HBM-streaming kernels in the plain form's device layout, so
+// its region is what ea_footprint gives.
+ea_status plan_streamed_job(const ea_job &in, int index, BatchJobHost &h)
+{
+    if (!valid_L(in.L) || batch_L_ok(in.L))
+        return fail(EA_ERR_ARG, "job %d: L=%d is not a streamed size (multiple of 8 in (%d, %d])", index, in.L,
+                    ea::kBatchMaxL, kMaxL);
+    ea_status st = plan_common(in, index, h);
+    if (st != EA_OK) return st;
+    const Layout lay = make_layout(in.L, in.n_tw);
+    h.RW = lay.RW;
+    h.W = lay.W;
+    h.POS = in.L * in.L * h.RW;
+    h.bytes = align256(lay.total);
     return EA_OK;
 }
 

@@ -1,5 +1,5 @@
 // ea_server_api.h -- the serving form (ea_server_* in ea.h): continuous
-// batching of a stream of simulation jobs on the batched kernel.
+// batching of a stream of simulation jobs.
 //
 // Jobs are admitted first-come first-served while their device footprint
 // fits a fixed HBM budget (a first-fit pool carved from one allocation) and
@@ -13,6 +13,13 @@
 // (ea_server_start), so that requests that arrive while a launch is on the
 // GPU join at the next epoch.  Results are the same integers as a run alone:
 // the dynamics never depend on how the sweeps are split or what else runs.
+//
+// Lattices too large for one workgroup's LDS (L > 64) are "streamed" jobs:
+// each is a plain-form simulation placed in its pool region, advanced during
+// the epoch through the HBM-streaming kernels on a second stream, so that its
+// half-steps run on the device alongside the batched launch.  A streamed
+// job's span is sized by time, so that the streamed work of an epoch takes
+// about as long as the previous epoch's batched launch.
 #pragma once
 
 #include <algorithm>
@@ -86,7 +93,17 @@ struct ServerJob {
     size_t pool_off = 0;
     steady::time_point t_submit, t_done;
     std::vector<unsigned long long> results;  // [n_meas][obs_stride] after completion
+    bool streamed = false;                     // L > 64: plain-form kernels on the second stream
+    ea_sim *sim = nullptr;                     // its simulation, in the pool region
+    int next_meas = 0, next_tw = 0;            // schedule positions of a streamed job
 };
+
+ea_status plan_server_job(const ea_job &in, ServerJob &j)
+{
+    if (!valid_L(in.L)) return fail(EA_ERR_ARG, "L=%d must be a multiple of 8 in [8, %d]", in.L, kMaxL);
+    j.streamed = !batch_L_ok(in.L);
+    return j.streamed ? plan_streamed_job(in, 0, j.h) : plan_job(in, 0, j.h);
+}
 
 }  // namespace
 
@@ -95,6 +112,9 @@ struct ea_server {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    hipStream_t stream_big = nullptr;  // streamed jobs (always the server's own)
+    double last_batch_s = 0.0;         // wall time of the last epoch's batched launch
+    double streamed_site_s = 0.0;      // measured seconds per site-sweep of streamed work
     char *pool_buf = nullptr;
     DevicePool pool;
     ea::BatchJobDev *d_jobs = nullptr;
@@ -121,6 +141,59 @@ struct ea_server {
 
 namespace {
 
+// Advance a streamed job to t_stop on the second stream, taking the snapshots
+// and measurements scheduled up to t_stop that it has not taken yet (those at
+// t = 0 included); each measurement's integers become the job's result row in
+// the batched kernel's counter form, so results are read back the same way.
+ea_status server_advance_streamed(ServerJob &j, uint64_t t_stop)
+{
+    BatchJobHost &h = j.h;
+    const int n_meas = h.job.n_meas, n_tw = h.job.n_tw;
+    const int64_t N = (int64_t)h.job.L * h.job.L * h.job.L;
+    std::vector<uint64_t> tw((size_t)n_tw);
+    std::vector<int64_t> autocorr(2 * (size_t)n_tw), c4(3 * (size_t)(h.R + 1));
+    uint64_t t = h.t_host;
+    for (;;) {
+        uint64_t te = ~0ull;
+        if (j.next_tw < n_tw) te = std::min<uint64_t>(te, h.tw[(size_t)j.next_tw]);
+        if (j.next_meas < n_meas) te = std::min<uint64_t>(te, h.meas_t[(size_t)j.next_meas]);
+        if (te > t_stop) break;
+        if (te > t) {
+            ea_status st = ea_sweep(j.sim, te - t);
+            if (st != EA_OK) return st;
+            t = te;
+        }
+        if (j.next_tw < n_tw && h.tw[(size_t)j.next_tw] == te) {
+            ea_status st = ea_snapshot(j.sim, j.next_tw);
+            if (st != EA_OK) return st;
+            ++j.next_tw;
+        }
+        if (j.next_meas < n_meas && h.meas_t[(size_t)j.next_meas] == te) {
+            ea_obs o{};
+            o.n_tw = n_tw;
+            o.tw = tw.data();
+            o.autocorr = autocorr.data();
+            o.rmax = h.R;
+            o.c4 = c4.data();
+            ea_status st = ea_measure(j.sim, &o);
+            if (st != EA_OK) return st;
+            unsigned long long *m = j.results.data() + (size_t)j.next_meas * (size_t)h.obs_stride;
+            for (int r = 0; r < 2; ++r) {
+                m[ea::M_UNSAT + r] = (unsigned long long)o.unsat[r];
+                m[ea::M_DOWN + r] = (unsigned long long)((N - o.mag[r]) / 2);
+                for (int k = 0; k < n_tw; ++k)
+                    m[ea::M_AUTO + 2 * k + r] = (unsigned long long)((N - o.autocorr[r * n_tw + k]) / 2);
+            }
+            m[ea::M_QDIFF] = (unsigned long long)((N - o.overlap) / 2);
+            for (int i = 0; i < 3 * (h.R + 1); ++i)
+                m[ea::M_AUTO + 2 * n_tw + i] = (unsigned long long)((N - o.c4[i]) / 2);
+            ++j.next_meas;
+        }
+    }
+    if (t_stop > t) return ea_sweep(j.sim, t_stop - t);
+    return EA_OK;
+}
+
 // One epoch: retire, admit, launch, wait.  Returns EA_OK with *progressed = 0
 // when nothing was resident or admissible.
 ea_status server_epoch(ea_server *s, int32_t *progressed)
@@ -141,8 +214,24 @@ ea_status server_epoch(ea_server *s, int32_t *progressed)
             s->pending.pop_front();
             s->state_of[j->id] = SJ_RUNNING;
             ++s->admitted;
-            ea_status st = upload_schedule(j->h, s->stream);
-            if (st == EA_OK) st = init_job_device(j->h, s->stream);
+            ea_status st;
+            if (j->streamed) {
+                ea_config c{};
+                c.L = j->h.job.L;
+                c.p = j->h.job.p;
+                c.T = j->h.job.T;
+                c.seed = j->h.job.seed;
+                c.sample = j->h.job.sample;
+                c.n_tw_slots = j->h.job.n_tw;
+                c.stream = s->stream_big;
+                c.dev_buf = j->h.base;
+                c.dev_buf_bytes = j->h.bytes;
+                st = ea_create_ex(&c, &j->sim);
+                j->results.assign((size_t)j->h.job.n_meas * (size_t)j->h.obs_stride, 0ull);
+            } else {
+                st = upload_schedule(j->h, s->stream);
+                if (st == EA_OK) st = init_job_device(j->h, s->stream);
+            }
             if (st != EA_OK) return st;
         }
         for (auto &p : s->resident) run.push_back(p.get());
@@ -151,34 +240,68 @@ ea_status server_epoch(ea_server *s, int32_t *progressed)
 
     // spans: about opts.epoch_site_sweeps site-updates per replica, at least one sweep
     std::vector<BatchJobHost *> hs;
-    std::vector<uint64_t> span;
+    std::vector<ServerJob *> batched, streamed;
+    std::vector<uint64_t> span(run.size()), bspan;
     std::vector<ea::BatchJobDev> dj;
-    for (ServerJob *j : run) {
+    for (size_t i = 0; i < run.size(); ++i) {
+        ServerJob *j = run[i];
+        if (j->streamed) {
+            streamed.push_back(j);
+            continue;
+        }
         const uint64_t N = (uint64_t)j->h.job.L * j->h.job.L * j->h.job.L;
         const uint64_t want = std::max<uint64_t>(1, s->opts.epoch_site_sweeps / N);
-        span.push_back(std::min<uint64_t>(want, j->h.job.n_sweeps - j->h.t_host));
+        span[i] = std::min<uint64_t>(want, j->h.job.n_sweeps - j->h.t_host);
+        batched.push_back(j);
+        bspan.push_back(span[i]);
         hs.push_back(&j->h);
         dj.push_back(make_job_dev(j->h));
     }
-    size_t lds = 0;
-    for (BatchJobHost *h : hs) lds = std::max(lds, (size_t)batch_lds_words(h->job.L, h->RW) * 4);
-    std::vector<ea::BatchUnit> units;
-    order_units(hs, span, units);
-    for (auto &u : units) {
-        const BatchJobHost &h = *hs[(size_t)u.job];
-        u.t_stop = (uint32_t)(h.t_host + span[(size_t)u.job]);
-        u.first = h.started ? 0 : 1;
-    }
     const auto t0 = steady::now();
-    EA_HIP(hipMemcpyAsync(s->d_jobs, dj.data(), sizeof(ea::BatchJobDev) * dj.size(), hipMemcpyHostToDevice,
-                          s->stream));
-    EA_HIP(hipMemcpyAsync(s->d_units, units.data(), sizeof(ea::BatchUnit) * units.size(), hipMemcpyHostToDevice,
-                          s->stream));
-    hipLaunchKernelGGL(ea::batch_kernel, dim3((unsigned)units.size()), dim3(ea::kBatchThreads), lds, s->stream,
-                       s->d_jobs, s->d_units);
-    EA_HIP(hipGetLastError());
+    if (!batched.empty()) {
+        size_t lds = 0;
+        for (BatchJobHost *h : hs) lds = std::max(lds, (size_t)batch_lds_words(h->job.L, h->RW) * 4);
+        std::vector<ea::BatchUnit> units;
+        order_units(hs, bspan, units);
+        for (auto &u : units) {
+            const BatchJobHost &h = *hs[(size_t)u.job];
+            u.t_stop = (uint32_t)(h.t_host + bspan[(size_t)u.job]);
+            u.first = h.started ? 0 : 1;
+        }
+        EA_HIP(hipMemcpyAsync(s->d_jobs, dj.data(), sizeof(ea::BatchJobDev) * dj.size(), hipMemcpyHostToDevice,
+                              s->stream));
+        EA_HIP(hipMemcpyAsync(s->d_units, units.data(), sizeof(ea::BatchUnit) * units.size(),
+                              hipMemcpyHostToDevice, s->stream));
+        hipLaunchKernelGGL(ea::batch_kernel, dim3((unsigned)units.size()), dim3(ea::kBatchThreads), lds, s->stream,
+                           s->d_jobs, s->d_units);
+        EA_HIP(hipGetLastError());
+    }
+    // streamed jobs, on the second stream while the batched launch runs; each
+    // gets an equal share of the expected epoch time
+    double streamed_sites = 0.0;
+    if (!streamed.empty()) {
+        const double target = std::max(s->last_batch_s, 2e-3) / (double)streamed.size();
+        for (size_t i = 0; i < run.size(); ++i) {
+            ServerJob *j = run[i];
+            if (!j->streamed) continue;
+            const double N = (double)j->h.job.L * j->h.job.L * j->h.job.L;
+            const double per_sweep = s->streamed_site_s > 0.0 ? s->streamed_site_s * N : 2e-5;
+            const uint64_t want = (uint64_t)std::max(1.0, std::floor(target / per_sweep));
+            span[i] = std::min<uint64_t>(want, j->h.job.n_sweeps - j->h.t_host);
+            ea_status st = server_advance_streamed(*j, j->h.t_host + span[i]);
+            if (st != EA_OK) return st;
+            streamed_sites += N * (double)span[i];
+        }
+    }
+    if (!streamed.empty()) EA_HIP(hipStreamSynchronize(s->stream_big));
+    const auto t_streamed = steady::now();
     EA_HIP(hipStreamSynchronize(s->stream));
     const auto t1 = steady::now();
+    if (!batched.empty()) s->last_batch_s = std::chrono::duration<double>(t1 - t0).count();
+    if (streamed_sites > 0.0) {
+        const double per_site = std::chrono::duration<double>(t_streamed - t0).count() / streamed_sites;
+        s->streamed_site_s = s->streamed_site_s > 0.0 ? 0.5 * (s->streamed_site_s + per_site) : per_site;
+    }
 
     // bookkeeping; finished jobs hand their results over and free their memory
     double epoch_flips = 0.0;
@@ -191,6 +314,11 @@ ea_status server_epoch(ea_server *s, int32_t *progressed)
         if (h.t_host >= h.job.n_sweeps) finished.push_back(run[i]);
     }
     for (ServerJob *j : finished) {
+        if (j->streamed) {  // results were taken at each measurement
+            ea_destroy(j->sim);
+            j->sim = nullptr;
+            continue;
+        }
         j->results.resize((size_t)j->h.job.n_meas * (size_t)j->h.obs_stride);
         if (!j->results.empty())
             EA_HIP(hipMemcpy(j->results.data(), j->h.base + j->h.off_obs, 8 * j->results.size(),
@@ -290,6 +418,11 @@ ea_status ea_server_create(const ea_server_opts *opts, ea_server **out)
         }
         s->own_stream = true;
     }
+    e = hipStreamCreateWithFlags(&s->stream_big, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        ea_server_destroy(s);
+        return fail(EA_ERR_DEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+    }
     const size_t table_bytes = align256(sizeof(ea::BatchJobDev) * (size_t)opts->max_resident) +
                                align256(sizeof(ea::BatchUnit) * 2 * (size_t)opts->max_resident);
     e = hipMalloc((void **)&s->pool_buf, align256(opts->hbm_budget) + table_bytes);
@@ -314,19 +447,23 @@ void ea_server_destroy(ea_server *s)
     }
     s->cv.notify_all();
     if (s->worker.joinable()) s->worker.join();
+    for (auto &j : s->resident)
+        if (j->sim) ea_destroy(j->sim);
     if (s->stream) (void)hipStreamSynchronize(s->stream);
+    if (s->stream_big) (void)hipStreamSynchronize(s->stream_big);
     if (s->pool_buf) (void)hipFree(s->pool_buf);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    if (s->stream_big) (void)hipStreamDestroy(s->stream_big);
     delete s;
 }
 
 ea_status ea_server_footprint(const ea_job *job, size_t *bytes)
 {
     if (!job || !bytes) return fail(EA_ERR_ARG, "NULL argument");
-    BatchJobHost h;
-    ea_status st = plan_job(*job, 0, h);
+    ServerJob j;
+    ea_status st = plan_server_job(*job, j);
     if (st != EA_OK) return st;
-    *bytes = h.bytes;
+    *bytes = j.h.bytes;
     return EA_OK;
 }
 
@@ -334,7 +471,7 @@ ea_status ea_server_submit(ea_server *s, const ea_job *job, uint64_t *id)
 {
     if (!s || !job || !id) return fail(EA_ERR_ARG, "NULL argument");
     auto j = std::make_unique<ServerJob>();
-    ea_status st = plan_job(*job, 0, j->h);
+    ea_status st = plan_server_job(*job, *j);
     if (st != EA_OK) return st;
     if (align256(j->h.bytes) > s->pool.size)
         return fail(EA_ERR_ARG, "job needs %zu bytes, more than the whole budget %zu", j->h.bytes, s->pool.size);

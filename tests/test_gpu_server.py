@@ -99,8 +99,9 @@ def test_server_admission_limits(ea_gpu):
     srv = ea_gpu.Server(hbm_budget=fp, max_resident=4, max_pending=2)
     with pytest.raises(ea_gpu.EAError):  # larger than the whole budget
         srv.submit(Job(64, 0.5, 0.7, seed=1, n_sweeps=5, meas_t=[1, 2, 3, 4, 5], tw=[1, 2]))
-    with pytest.raises(ea_gpu.EAError):  # the batched kernel holds L <= 64
-        srv.submit(Job(96, 0.5, 0.7, seed=1, n_sweeps=5, meas_t=[5]))
+    for L in (100, 264):  # no lattice of that size exists in either form
+        with pytest.raises(ea_gpu.EAError):
+            srv.submit(Job(L, 0.5, 0.7, seed=1, n_sweeps=5, meas_t=[5]))
     a = srv.submit(big)
     b = srv.submit(big)
     with pytest.raises(ea_gpu.EAError):  # max_pending
@@ -114,3 +115,70 @@ def test_server_admission_limits(ea_gpu):
     assert srv.poll(b) == ea_gpu.JOB_DONE
     assert not srv.step()
     _same_obs(srv.result(a, 0), srv.result(b, 0), "identical jobs")
+
+
+def _alone_plain(ea_gpu, job):
+    """The job run alone through the plain form, measurement by measurement."""
+    g = ea_gpu.Sim(job.L, job.p, job.T, seed=job.seed, sample=job.sample, n_slots=len(job.tw))
+    res, t = [], 0
+    for te, slots, meas in job.events():
+        if te > t:
+            g.sweep(te - t)
+            t = te
+        for k in slots:
+            g.snapshot(k)
+        if meas:
+            res.append(g.measure())
+    return res
+
+
+def test_server_streams_large_lattices(ea_gpu):
+    """Lattices above 64 (streamed through the plain kernels on a second
+    stream) mixed with LDS-resident ones: every job equals its run alone."""
+    from paper_1411_5512_amd.workloads import Job
+    jobs = [
+        Job(96, 0.5, 0.7, seed=31, sample=0, n_sweeps=40, meas_t=[0, 3, 17, 40], tw=[3, 17]),
+        Job(16, 0.3, 0.8, seed=32, sample=1, n_sweeps=300, meas_t=[10, 100, 300], tw=[10]),
+        Job(128, 0.2, 0.7, seed=33, sample=0, n_sweeps=25, meas_t=[1, 25], tw=[1]),
+        Job(64, 0.5, 0.9, seed=34, sample=0, n_sweeps=60, meas_t=[0, 60], tw=[0]),
+        Job(72, 0.4, 1.1, seed=35, sample=2, n_sweeps=0, meas_t=[0], tw=[0]),
+        Job(256, 0.5, 0.7, seed=36, sample=0, n_sweeps=3, meas_t=[3], tw=[]),
+        Job(32, 0.5, 0.6, seed=37, sample=0, n_sweeps=200, meas_t=[50, 200], tw=[50]),
+    ]
+    srv = ea_gpu.Server(hbm_budget=1 << 28, max_resident=4, epoch_site_sweeps=32 ** 3 * 4)
+    srv.start()
+    ids = [srv.submit(j) for j in jobs]
+    srv.drain(300)
+    srv.stop()
+    st = srv.stats()
+    _say(f"server stats {st}")
+    assert st["completed"] == len(jobs)
+    for jid, job in zip(ids, jobs):
+        _say(f"streamed-mix job L={job.L} sweeps={job.n_sweeps}")
+        ref = _alone_plain(ea_gpu, job)
+        assert len(ref) == len(job.meas_t)
+        for k, want in enumerate(ref):
+            _same_obs(srv.result(jid, k), want, f"L={job.L} meas {k}")
+
+
+def test_server_streamed_job_matches_oracle(ea_gpu, oracle_mod):
+    """One streamed job, split over many epochs, against the oracle."""
+    from paper_1411_5512_amd.workloads import Job
+    job = Job(80, 0.5, 0.8, seed=41, sample=3, n_sweeps=6, meas_t=[0, 2, 5, 6], tw=[2])
+    srv = ea_gpu.Server(hbm_budget=1 << 26, max_resident=2)
+    jid = srv.submit(job)
+    n = 0
+    while srv.step():
+        n += 1
+        assert n < 1000
+    o = oracle_mod.Sim(job.L, job.p, job.T, seed=job.seed, sample=job.sample, n_slots=1)
+    t, k = 0, 0
+    for te, slots, meas in job.events():
+        o.sweep(te - t)
+        t = te
+        for s in slots:
+            o.snapshot(s)
+        if meas:
+            _same_obs(srv.result(jid, k), o.measure(), f"meas {k}")
+            k += 1
+    assert k == len(job.meas_t)
