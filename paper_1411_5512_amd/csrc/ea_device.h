@@ -125,18 +125,38 @@ __device__ __forceinline__ Decision classify(uint32_t a1, uint32_t a2, uint32_t 
     return d;
 }
 
-// Per-site acceptance, branch-free and without lane masks (a compare that
-// writes VCC followed by a select that reads it costs wait states on gfx950).
-// For site bit I the threshold is picked with two sign-extended bit fields:
-// any -> thr1 (n = 2), else odd -> thr2 (n = 1), else thr3 (n = 0); sites
-// with n >= 3 are covered by the "always" mask.  The unsigned comparison
-// u < thr is the sign bit of (~u & thr) | ((~u | thr) & (u - thr)) (Hacker's
-// Delight, unsigned comparison predicates), and a funnel shift appends that
-// bit to the accept word, so sites are visited from the highest bit down.
+// Per-site acceptance, branch-free.  For site bit I the threshold is picked
+// with two sign-extended bit fields: any -> thr1 (n = 2), else odd -> thr2
+// (n = 1), else thr3 (n = 0); sites with n >= 3 are covered by the "always"
+// mask.  The accept word is built from the highest site bit down, one
+// Philox block (four sites) at a time, by append_below4.
 //
 // v_bitop3_b32 truth tables are indexed by (src0 << 2) | (src1 << 1) | src2.
 constexpr int kBitopSelect = 0xCA;   // src0 ? src1 : src2, bitwise
-constexpr int kBitopBelow = 0x8E;    // (~u & t) | ((~u | t) & d) for (u, t, d)
+
+// accept = 16 accept + 8 [u3 < t3] + 4 [u2 < t2] + 2 [u1 < t1] + [u0 < t0].
+// Each unsigned compare writes its lane mask to an SGPR pair and an add with
+// carry-in (accept + accept + carry) appends the bit: two instructions per
+// site.  gfx950 needs two wait states between a VALU write of an SGPR and a
+// VALU read of it as a carry, so the four compares are issued first: every
+// mask is read three instructions after it is written.
+__device__ __forceinline__ uint32_t append_below4(uint32_t accept, uint32_t u3, uint32_t t3, uint32_t u2,
+                                                  uint32_t t2, uint32_t u1, uint32_t t1, uint32_t u0,
+                                                  uint32_t t0)
+{
+    uint64_t m3, m2, m1, m0, co;
+    asm("v_cmp_lt_u32_e64 %1, %6, %7\n\t"
+        "v_cmp_lt_u32_e64 %2, %8, %9\n\t"
+        "v_cmp_lt_u32_e64 %3, %10, %11\n\t"
+        "v_cmp_lt_u32_e64 %4, %12, %13\n\t"
+        "v_addc_co_u32_e64 %0, %5, %0, %0, %1\n\t"
+        "v_addc_co_u32_e64 %0, %5, %0, %0, %2\n\t"
+        "v_addc_co_u32_e64 %0, %5, %0, %0, %3\n\t"
+        "v_addc_co_u32_e64 %0, %5, %0, %0, %4"
+        : "+v"(accept), "=&s"(m3), "=&s"(m2), "=&s"(m1), "=&s"(m0), "=&s"(co)
+        : "v"(u3), "v"(t3), "v"(u2), "v"(t2), "v"(u1), "v"(t1), "v"(u0), "v"(t0));
+    return accept;
+}
 
 template <int I>
 __device__ __forceinline__ uint32_t bit_as_mask(uint32_t word)
@@ -149,16 +169,12 @@ __device__ __forceinline__ uint32_t bit_as_mask(uint32_t word)
 }
 
 template <int I>
-__device__ __forceinline__ uint32_t accept_site(uint32_t accept, uint32_t u, const Decision &d,
-                                                uint32_t thr1, uint32_t thr2, uint32_t thr3)
+__device__ __forceinline__ uint32_t site_threshold(const Decision &d, uint32_t thr1, uint32_t thr2, uint32_t thr3)
 {
     const uint32_t m_any = bit_as_mask<I>(d.any);
     const uint32_t m_odd = bit_as_mask<I>(d.odd);
-    const uint32_t t = __builtin_amdgcn_bitop3_b32(m_any, thr1,
-                                                   __builtin_amdgcn_bitop3_b32(m_odd, thr2, thr3, kBitopSelect),
-                                                   kBitopSelect);
-    // accept = 2 accept + (u < t): a compare into the carry and one add-with-carry
-    return accept + accept + (uint32_t)(u < t);
+    return __builtin_amdgcn_bitop3_b32(m_any, thr1, __builtin_amdgcn_bitop3_b32(m_odd, thr2, thr3, kBitopSelect),
+                                       kBitopSelect);
 }
 
 // Blocks J = W/4-1 down to 0: block J covers sites 4J..4J+3 and has counter
@@ -170,10 +186,10 @@ __device__ __forceinline__ uint32_t accept_blocks(uint32_t accept, const Decisio
                                                   uint32_t k1, uint32_t thr1, uint32_t thr2, uint32_t thr3)
 {
     const Words4 u = philox10(c0, quad0 + (uint32_t)J, c2, c3, k0, k1);
-    accept = accept_site<4 * J + 3>(accept, u.v[3], d, thr1, thr2, thr3);
-    accept = accept_site<4 * J + 2>(accept, u.v[2], d, thr1, thr2, thr3);
-    accept = accept_site<4 * J + 1>(accept, u.v[1], d, thr1, thr2, thr3);
-    accept = accept_site<4 * J + 0>(accept, u.v[0], d, thr1, thr2, thr3);
+    accept = append_below4(accept, u.v[3], site_threshold<4 * J + 3>(d, thr1, thr2, thr3), u.v[2],
+                           site_threshold<4 * J + 2>(d, thr1, thr2, thr3), u.v[1],
+                           site_threshold<4 * J + 1>(d, thr1, thr2, thr3), u.v[0],
+                           site_threshold<4 * J + 0>(d, thr1, thr2, thr3));
     if constexpr (J > 0)
         return accept_blocks<J - 1>(accept, d, c0, quad0, c2, c3, k0, k1, thr1, thr2, thr3);
     else
@@ -222,12 +238,8 @@ __device__ __forceinline__ uint32_t accept_blocks_lds(uint32_t accept, const uin
                                                       uint32_t k1)
 {
     const Words4 u = philox10(c0, quad0 + (uint32_t)J, c2, c3, k0, k1);
-#pragma unroll
-    for (int q = 3; q >= 0; --q) {
-        const int i = 4 * J + q;
-        accept = __builtin_amdgcn_alignbit(accept, __builtin_amdgcn_bitop3_b32(u.v[q], thr[i], u.v[q] - thr[i],
-                                                                               kBitopBelow), 31);
-    }
+    accept = append_below4(accept, u.v[3], thr[4 * J + 3], u.v[2], thr[4 * J + 2], u.v[1], thr[4 * J + 1],
+                           u.v[0], thr[4 * J]);
     if constexpr (J > 0)
         return accept_blocks_lds<J - 1, W>(accept, thr, c0, quad0, c2, c3, k0, k1);
     else
