@@ -177,7 +177,19 @@ typedef struct {
 typedef struct {
     void *stream;            /* hipStream_t to enqueue on, or NULL for a library stream */
     int32_t autotune;        /* 1: run each lattice size with its autotuned configuration */
+    int32_t split;           /* replicas split across two workgroups (see below): 0 automatic,
+                                1 never, 2 every job that can be (L >= 48, default configuration),
+                                as long as all slabs fit the device at once */
 } ea_batch_opts;
+
+/* Split replicas.  When one replica of the largest samples on one compute
+ * unit would set the length of a run, ea_batch_create may cut the replicas of
+ * samples with L >= 48 (default configuration only) into two z-slabs held by
+ * two workgroups that exchange their boundary planes every half-step through
+ * device memory.  The choice is made by simulating the dispatch of the unit
+ * list; results are identical either way.  A pair that never meets (its
+ * partner never became resident within seconds) ends its units and makes
+ * ea_batch_run / ea_batch_replay return EA_ERR_DEVICE. */
 
 /* Launch configuration of the batched kernel for one lattice size. */
 typedef struct {
@@ -227,6 +239,9 @@ ea_status ea_batch_result(ea_batch *b, int32_t job, int32_t k, ea_obs *out);
 
 /* Current spins of replica r of job j, int8 +-1 in canonical order [L^3]. */
 ea_status ea_batch_get_spins(ea_batch *b, int32_t job, int32_t r, int8_t *pm1);
+
+/* Workgroups per replica of job j: 1, or 2 if its replicas run split. */
+ea_status ea_batch_parts(ea_batch *b, int32_t job, int32_t *parts);
 
 /* ------------------------------------------------------------------------
  * Serving form: continuous batching of a stream of jobs.  The dynamics

@@ -228,12 +228,15 @@ def _obs_from(o, n_tw, tw, ac, c4a, c4):
 class Batch:
     """Many independent runs (L <= 64) in one persistent launch per span."""
 
-    def __init__(self, jobs, use_torch: bool = True, autotune: bool = False):
+    SPLIT_AUTO, SPLIT_NEVER, SPLIT_ALWAYS = 0, 1, 2
+
+    def __init__(self, jobs, use_torch: bool = True, autotune: bool = False, split: int = 0):
         self.jobs = list(jobs)
         keep = []
         arr = (abi.Job * len(self.jobs))(*[_job_struct(j, keep) for j in self.jobs])
         opts = abi.BatchOpts()
         opts.autotune = 1 if autotune else 0
+        opts.split = int(split)
         self._stream = None
         if use_torch:
             try:
@@ -246,6 +249,12 @@ class Batch:
         h = ctypes.c_void_p()
         abi.check(abi.lib().ea_batch_create(arr, len(self.jobs), ctypes.byref(opts), ctypes.byref(h)))
         self._h = h
+
+    def parts(self, j: int) -> int:
+        """Workgroups per replica of job j: 1, or 2 if its replicas were split."""
+        n = ctypes.c_int32(0)
+        abi.check(abi.lib().ea_batch_parts(self._h, int(j), ctypes.byref(n)))
+        return n.value
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

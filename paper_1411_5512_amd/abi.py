@@ -68,7 +68,7 @@ class Job(ctypes.Structure):
 
 
 class BatchOpts(ctypes.Structure):
-    _fields_ = [("stream", ctypes.c_void_p), ("autotune", ctypes.c_int32)]
+    _fields_ = [("stream", ctypes.c_void_p), ("autotune", ctypes.c_int32), ("split", ctypes.c_int32)]
 
 
 class TuneChoice(ctypes.Structure):
@@ -146,6 +146,7 @@ _SIGS = {
     "ea_batch_result": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Obs)]),
     "ea_batch_get_spins": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                           ctypes.POINTER(ctypes.c_int8)]),
+    "ea_batch_parts": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "ea_server_create": (ctypes.c_int, [ctypes.POINTER(ServerOpts), ctypes.POINTER(ctypes.c_void_p)]),
     "ea_server_destroy": (None, [ctypes.c_void_p]),
     "ea_server_footprint": (ctypes.c_int, [ctypes.POINTER(Job), ctypes.POINTER(ctypes.c_size_t)]),

@@ -7,6 +7,7 @@
 #include <map>
 #include <mutex>
 #include <numeric>
+#include <queue>
 
 namespace {
 
@@ -45,7 +46,9 @@ struct BatchJobHost {
     uint32_t thr[3] = {0, 0, 0};
     uint64_t pcut = 0;
     size_t off_spins = 0, off_bonds = 0, off_snaps = 0, off_mspins = 0, off_obs = 0, off_arrive = 0,
-           off_tnow = 0, off_meas_t = 0, off_tw = 0, bytes = 0;
+           off_tnow = 0, off_pub = 0, off_xbuf = 0, off_meas_t = 0, off_tw = 0, bytes = 0;
+    int parts = 1;            // workgroups per replica (2: split into z-slabs)
+    uint32_t *err = nullptr;  // device word a split pair sets when it gives up waiting
     char *base = nullptr;     // device region of this job
     uint64_t t_host = 0;      // sweeps done (host mirror)
     bool started = false;     // a span has run (events at t = 0 are taken)
@@ -54,6 +57,15 @@ struct BatchJobHost {
 bool batch_L_ok(int L) { return L >= 8 && L <= ea::kBatchMaxL && L % 8 == 0; }
 
 int batch_lds_words(int L, int rw) { return 8 * L * L * rw + 16; }
+
+// LDS of one slab of a split replica: its half of the lattice, the z
+// couplings of the plane below it and the broadcast words.
+int slab_lds_words(int L, int rw) { return 8 * (L / 2) * L * rw + 2 * L * rw + 16; }
+
+int job_lds_words(const BatchJobHost &h)
+{
+    return h.parts == 2 ? slab_lds_words(h.job.L, h.RW) : batch_lds_words(h.job.L, h.RW);
+}
 
 ea_status copy_schedule(const uint64_t *src, int32_t n, uint64_t n_sweeps, const char *what,
                         std::vector<uint32_t> &dst)
@@ -124,6 +136,10 @@ ea_status plan_job(const ea_job &in, int index, BatchJobHost &h, const TuneCfg *
     off += 4 * (size_t)in.n_meas;
     h.off_tnow = off;
     off += 8;
+    h.off_pub = off = align256(off);
+    off += 8 * 4;
+    h.off_xbuf = off = align256(off);
+    off += 4 * 32 * (size_t)in.L * (size_t)h.RW;
     h.off_meas_t = off = align256(off);
     off += 4 * (size_t)in.n_meas;
     h.off_tw = off = align256(off);
@@ -175,6 +191,10 @@ ea::BatchJobDev make_job_dev(const BatchJobHost &h)
     d.obs = (unsigned long long *)(h.base + h.off_obs);
     d.arrive = (uint32_t *)(h.base + h.off_arrive);
     d.t_now = (uint32_t *)(h.base + h.off_tnow);
+    d.parts = h.parts;
+    d.pub = (unsigned long long *)(h.base + h.off_pub);
+    d.xbuf = (uint32_t *)(h.base + h.off_xbuf);
+    d.err = h.err;
     return d;
 }
 
@@ -211,6 +231,8 @@ ea_status init_job_device(BatchJobHost &h, hipStream_t stream)
     const size_t n_ctl32 = (size_t)h.job.n_meas + 2;
     hipLaunchKernelGGL(ea::zero_u32_kernel, dim3(blocks_for(n_ctl32)), dim3(256), 0, stream,
                        (uint32_t *)(h.base + h.off_arrive), n_ctl32);
+    hipLaunchKernelGGL(ea::zero_u64_kernel, dim3(1), dim3(256), 0, stream,
+                       (unsigned long long *)(h.base + h.off_pub), (size_t)4);
     EA_HIP(hipGetLastError());
     h.t_host = 0;
     h.started = false;
@@ -267,6 +289,11 @@ ea_status read_job_spins(const BatchJobHost &h, int32_t r, int8_t *pm1, hipStrea
 
 // Check that a launch with this much dynamic LDS fits one workgroup, and
 // allow it (the kernel's default cap is lower).
+// The kernel's dynamic-LDS limit only ever grows, so that a batch created
+// later with smaller jobs does not lower it under one that still runs.
+std::mutex g_lds_mu;
+size_t g_lds_attr = 0;
+
 ea_status prepare_batch_lds(size_t dyn_bytes)
 {
     int dev = 0, lds_limit = 0;
@@ -275,14 +302,21 @@ ea_status prepare_batch_lds(size_t dyn_bytes)
     if (dyn_bytes + 4 * (size_t)ea::kSelectTableWords > (size_t)lds_limit)
         return fail(EA_ERR_ARG, "the largest job needs %zu bytes of LDS, the device offers %d", dyn_bytes,
                     lds_limit);
-    EA_HIP(hipFuncSetAttribute((const void *)ea::batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)dyn_bytes));
+    std::lock_guard<std::mutex> lk(g_lds_mu);
+    if (dyn_bytes > g_lds_attr) {
+        EA_HIP(hipFuncSetAttribute((const void *)ea::batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)dyn_bytes));
+        g_lds_attr = dyn_bytes;
+    }
     return EA_OK;
 }
 
-// Units of a set of jobs, largest remaining work first (the longest units
-// start first); the two replicas of a job are adjacent so that they reach
-// each measurement at about the same time.
+// Units of a set of jobs.  Split replicas come first, largest first, as
+// (slab 0, slab 1) pairs at even positions, so that the two workgroups of a
+// pair sit at the same position of the in-order dispatch on their XCDs and
+// are resident together; then the other units, largest remaining work first
+// (the longest units start first), the two replicas of a job adjacent so that
+// they reach each measurement at about the same time.
 void order_units(const std::vector<BatchJobHost *> &jobs, const std::vector<uint64_t> &span,
                  std::vector<ea::BatchUnit> &units)
 {
@@ -292,10 +326,104 @@ void order_units(const std::vector<BatchJobHost *> &jobs, const std::vector<uint
         const double L = (double)jobs[(size_t)a]->job.L;
         return L * L * L * (double)span[(size_t)a];
     };
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) { return work(a) > work(c); });
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) {
+        const int pa = jobs[(size_t)a]->parts, pc = jobs[(size_t)c]->parts;
+        if (pa != pc) return pa > pc;
+        return work(a) > work(c);
+    });
     units.clear();
     for (int32_t j : order)
-        for (int32_t r = 0; r < 2; ++r) units.push_back(ea::BatchUnit{j, r, 0u, 1});
+        for (int32_t r = 0; r < 2; ++r)
+            for (int32_t k = 0; k < jobs[(size_t)j]->parts; ++k) units.push_back(ea::BatchUnit{j, r, 0u, 1, k});
+}
+
+// Which jobs to split.  For each size threshold (none, 64, 56, 48) whose
+// slabs all fit the device at once (one per CU, so that both workgroups of
+// every pair are dispatched at the start), the in-order dispatch of the
+// resulting unit list onto n_cu one-unit CUs is simulated and the threshold
+// with the shortest estimated makespan is kept.  Time model per half-step
+// (measured on MI355X): a whole replica takes kHalfStepL64 x (L/64)^3; a
+// slab takes 0.55 of that, but at least kSlabFloor, the latency of the
+// boundary exchange (wait, remote reads, release).  Only jobs in their
+// default launch configuration (the slab kernel exists for that one) split.
+constexpr double kHalfStepL64 = 13.5e-6;
+constexpr double kSlabFloor = 9.9e-6;
+
+double unit_seconds(const BatchJobHost &h, bool slab)
+{
+    const double x = (double)h.job.L / 64.0;
+    const double whole = kHalfStepL64 * x * x * x;
+    const double per_half = slab ? std::max(0.55 * whole, kSlabFloor) : whole;
+    return 2.0 * (double)std::max<uint64_t>(1, h.job.n_sweeps) * per_half;
+}
+
+double simulate_dispatch(const std::vector<std::pair<double, int>> &units, int n_cu)
+{
+    // units: (cost, 2 for the first workgroup of a pair that starts together, else 1)
+    std::priority_queue<double, std::vector<double>, std::greater<double>> free_at;
+    for (int i = 0; i < n_cu; ++i) free_at.push(0.0);
+    double end = 0.0;
+    for (size_t i = 0; i < units.size(); ++i) {
+        if (units[i].second == 2 && i + 1 < units.size()) {
+            const double a = free_at.top();
+            free_at.pop();
+            const double b = free_at.top();
+            free_at.pop();
+            const double start = std::max(a, b);
+            free_at.push(start + units[i].first);
+            free_at.push(start + units[i + 1].first);
+            end = std::max(end, start + std::max(units[i].first, units[i + 1].first));
+            ++i;
+        } else {
+            const double a = free_at.top();
+            free_at.pop();
+            free_at.push(a + units[i].first);
+            end = std::max(end, a + units[i].first);
+        }
+    }
+    return end;
+}
+
+void choose_split(std::vector<BatchJobHost> &jobs, int n_cu, bool always)
+{
+    auto splittable = [](const BatchJobHost &h) {
+        const TuneCfg d = default_cfg(h.job.L);
+        return h.job.L >= ea::kSplitMinL && h.cfg.rw == d.rw && h.cfg.nt == d.nt && h.cfg.sel == ea::SEL_LDS &&
+               h.cfg.nt >= 128;
+    };
+    int best_lmin = 0;
+    double best = 0.0;
+    for (int lmin : {0, 64, 56, 48}) {
+        // every slab must be resident from the start: at most one per CU
+        size_t n_slabs = 0;
+        for (const BatchJobHost &h : jobs) n_slabs += (lmin && h.job.L >= lmin && splittable(h)) ? 4 : 0;
+        if (n_slabs > (size_t)n_cu) continue;
+        std::vector<std::pair<double, int>> split, rest;
+        for (const BatchJobHost &h : jobs) {
+            if (lmin && h.job.L >= lmin && splittable(h)) {
+                const double w = unit_seconds(h, true);
+                for (int r = 0; r < 2; ++r) {
+                    split.push_back({w, 2});
+                    split.push_back({w, 1});
+                }
+            } else {
+                const double w = unit_seconds(h, false);
+                rest.push_back({w, 1});
+                rest.push_back({w, 1});
+            }
+        }
+        std::stable_sort(rest.begin(), rest.end(),
+                         [](const std::pair<double, int> &a, const std::pair<double, int> &b) {
+                             return a.first > b.first;
+                         });
+        split.insert(split.end(), rest.begin(), rest.end());
+        const double m = simulate_dispatch(split, n_cu);
+        if (lmin == 0 || m < best || always) {
+            best = m;
+            best_lmin = lmin;
+        }
+    }
+    for (BatchJobHost &h : jobs) h.parts = (best_lmin && h.job.L >= best_lmin && splittable(h)) ? 2 : 1;
 }
 
 }  // namespace
@@ -309,6 +437,7 @@ struct ea_batch {
     ea::BatchJobDev *d_jobs = nullptr;
     ea::BatchUnit *d_units = nullptr;
     ea::BatchUnit *d_units_graph = nullptr;  // whole-run units read by the captured graph
+    uint32_t *d_err = nullptr;                // set by a split pair that gave up waiting
     std::vector<ea::BatchUnit> units;
     size_t lds_bytes = 0;
     std::vector<unsigned long long> h_obs;  // staging for ea_batch_result
@@ -319,7 +448,8 @@ struct ea_batch {
 
 namespace {
 
-ea_status batch_create_cfg(const ea_job *jobs, int32_t n_jobs, void *stream, const TuneCfg *cfgs, ea_batch **out);
+ea_status batch_create_cfg(const ea_job *jobs, int32_t n_jobs, void *stream, const TuneCfg *cfgs, int split,
+                           ea_batch **out);
 
 // ---------------------------------------------------------------------------
 // Autotuner.  For one lattice size it times every valid combination of row
@@ -431,7 +561,7 @@ ea_status tune_probe(int L, const TuneCfg &cfg, std::vector<long long> &results,
     }
     std::vector<TuneCfg> cfgs((size_t)n, cfg);
     ea_batch *b = nullptr;
-    ea_status st = batch_create_cfg(jobs.data(), n, nullptr, cfgs.data(), &b);
+    ea_status st = batch_create_cfg(jobs.data(), n, nullptr, cfgs.data(), 1, &b);
     if (st != EA_OK) return st;
     st = ea_batch_run(b, sweeps);  // warm-up
     if (st == EA_OK) st = ea_batch_reset(b);
@@ -513,7 +643,8 @@ ea_status tuned_cfg(int L, TuneCfg *out)
 
 namespace {
 
-ea_status batch_create_cfg(const ea_job *jobs, int32_t n_jobs, void *stream, const TuneCfg *cfgs, ea_batch **out)
+ea_status batch_create_cfg(const ea_job *jobs, int32_t n_jobs, void *stream, const TuneCfg *cfgs, int split,
+                           ea_batch **out)
 {
     if (!out) return fail(EA_ERR_ARG, "out is NULL");
     *out = nullptr;
@@ -532,14 +663,26 @@ ea_status batch_create_cfg(const ea_job *jobs, int32_t n_jobs, void *stream, con
         }
         region[(size_t)j] = off = align256(off);
         off += b->jobs[(size_t)j].bytes;
-        max_lds = std::max(max_lds, batch_lds_words(jobs[j].L, b->jobs[(size_t)j].RW));
     }
+    if (split != 1) {
+        int dev = 0, n_cu = 0;
+        hipError_t e0 = hipGetDevice(&dev);
+        if (e0 == hipSuccess) e0 = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e0 != hipSuccess) {
+            delete b;
+            return fail(EA_ERR_DEVICE, "device query: %s", hipGetErrorString(e0));
+        }
+        choose_split(b->jobs, n_cu, split == 2);
+    }
+    for (const BatchJobHost &h : b->jobs) max_lds = std::max(max_lds, job_lds_words(h));
     const size_t off_jobs = align256(off);
     off = off_jobs + sizeof(ea::BatchJobDev) * (size_t)n_jobs;
     const size_t off_units = align256(off);
-    off = off_units + sizeof(ea::BatchUnit) * 2 * (size_t)n_jobs;
+    off = off_units + sizeof(ea::BatchUnit) * 4 * (size_t)n_jobs;
     const size_t off_units_graph = align256(off);
-    off = off_units_graph + sizeof(ea::BatchUnit) * 2 * (size_t)n_jobs;
+    off = off_units_graph + sizeof(ea::BatchUnit) * 4 * (size_t)n_jobs;
+    const size_t off_err = align256(off);
+    off = off_err + 4;
     b->bytes = align256(off);
     b->lds_bytes = (size_t)max_lds * 4;  // dynamic part; the select tables are static
 
@@ -567,9 +710,11 @@ ea_status batch_create_cfg(const ea_job *jobs, int32_t n_jobs, void *stream, con
     std::vector<ea::BatchJobDev> dj((size_t)n_jobs);
     std::vector<BatchJobHost *> ptrs;
     std::vector<uint64_t> span;
+    b->d_err = (uint32_t *)(b->buf + off_err);
     for (int32_t j = 0; j < n_jobs; ++j) {
         BatchJobHost &h = b->jobs[(size_t)j];
         h.base = b->buf + region[(size_t)j];
+        h.err = b->d_err;
         dj[(size_t)j] = make_job_dev(h);
         st = upload_schedule(h, b->stream);
         if (st != EA_OK) {
@@ -599,6 +744,29 @@ ea_status batch_create_cfg(const ea_job *jobs, int32_t n_jobs, void *stream, con
     return EA_OK;
 }
 
+// Generate every job's initial state and clear the counters (also what a
+// captured run starts with).
+ea_status reset_batch_device(ea_batch *b)
+{
+    hipLaunchKernelGGL(ea::zero_u32_kernel, dim3(1), dim3(64), 0, b->stream, b->d_err, (size_t)1);
+    EA_HIP(hipGetLastError());
+    for (auto &h : b->jobs) {
+        ea_status st = init_job_device(h, b->stream);
+        if (st != EA_OK) return st;
+    }
+    return EA_OK;
+}
+
+// After a synchronised run: did a split pair give up waiting?
+ea_status check_batch_err(ea_batch *b)
+{
+    uint32_t err = 0;
+    EA_HIP(hipMemcpyAsync(&err, b->d_err, 4, hipMemcpyDeviceToHost, b->stream));
+    EA_HIP(hipStreamSynchronize(b->stream));
+    if (err) return fail(EA_ERR_DEVICE, "the two workgroups of a split replica did not meet; results are invalid");
+    return EA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -619,7 +787,9 @@ ea_status ea_batch_create(const ea_job *jobs, int32_t n_jobs, const ea_batch_opt
             if (st != EA_OK) return st;
         }
     }
-    return batch_create_cfg(jobs, n_jobs, opts ? opts->stream : nullptr, cfgs.data(), out);
+    const int split = opts ? opts->split : 0;
+    if (split < 0 || split > 2) return fail(EA_ERR_ARG, "split=%d is not 0, 1 or 2", split);
+    return batch_create_cfg(jobs, n_jobs, opts ? opts->stream : nullptr, cfgs.data(), split, out);
 }
 
 ea_status ea_tune(int32_t L, int32_t force, ea_tune_choice *chosen, ea_tune_choice *tried, int32_t max_tried,
@@ -676,11 +846,7 @@ void ea_batch_destroy(ea_batch *b)
 ea_status ea_batch_reset(ea_batch *b)
 {
     if (!b) return fail(EA_ERR_ARG, "batch is NULL");
-    for (auto &h : b->jobs) {
-        ea_status st = init_job_device(h, b->stream);
-        if (st != EA_OK) return st;
-    }
-    return EA_OK;
+    return reset_batch_device(b);
 }
 
 ea_status ea_batch_run(ea_batch *b, uint64_t t_stop)
@@ -706,7 +872,7 @@ ea_status ea_batch_run(ea_batch *b, uint64_t t_stop)
     }
     // the unit table is read by the kernel: keep the host copy stable until it ran
     EA_HIP(hipStreamSynchronize(b->stream));
-    return EA_OK;
+    return check_batch_err(b);
 }
 
 ea_status ea_batch_capture(ea_batch *b)
@@ -723,11 +889,7 @@ ea_status ea_batch_capture(ea_batch *b)
                           hipMemcpyHostToDevice, b->stream));
     EA_HIP(hipStreamSynchronize(b->stream));
     EA_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    ea_status st = EA_OK;
-    for (auto &h : b->jobs) {
-        st = init_job_device(h, b->stream);
-        if (st != EA_OK) break;
-    }
+    ea_status st = reset_batch_device(b);
     if (st == EA_OK)
         hipLaunchKernelGGL(ea::batch_kernel, dim3((unsigned)full.size()), dim3(ea::kBatchThreads), b->lds_bytes,
                            b->stream, b->d_jobs, b->d_units_graph);
@@ -757,7 +919,7 @@ ea_status ea_batch_replay(ea_batch *b)
         h.t_host = h.job.n_sweeps;
         h.started = true;
     }
-    return EA_OK;
+    return check_batch_err(b);
 }
 
 ea_status ea_batch_time(ea_batch *b, int32_t job, uint64_t *t)
@@ -781,6 +943,14 @@ ea_status ea_batch_result(ea_batch *b, int32_t job, int32_t k, ea_obs *out)
                           8 * (size_t)h.obs_stride, hipMemcpyDeviceToHost, b->stream));
     EA_HIP(hipStreamSynchronize(b->stream));
     return fill_obs(h, b->h_obs.data(), k, out);
+}
+
+ea_status ea_batch_parts(ea_batch *b, int32_t job, int32_t *parts)
+{
+    if (!b || !parts) return fail(EA_ERR_ARG, "NULL argument");
+    if (job < 0 || job >= (int32_t)b->jobs.size()) return fail(EA_ERR_ARG, "job %d out of range", job);
+    *parts = b->jobs[(size_t)job].parts;
+    return EA_OK;
 }
 
 ea_status ea_batch_get_spins(ea_batch *b, int32_t job, int32_t r, int8_t *pm1)

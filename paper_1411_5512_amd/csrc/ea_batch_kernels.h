@@ -20,6 +20,7 @@ namespace ea {
 
 constexpr int kBatchThreads = 1024;
 constexpr int kBatchMaxL = 64;
+constexpr int kSplitMinL = 48;  // smallest size whose replicas may be split into two z-slabs
 
 __host__ __device__ constexpr int words_per_row_c(int R)
 {
@@ -68,8 +69,12 @@ struct BatchJobDev {
     const uint32_t *meas_t;   // [n_meas], strictly increasing
     const uint32_t *tw_t;     // [n_tw], strictly increasing
     unsigned long long *obs;  // [n_meas][obs_stride]
-    uint32_t *arrive;         // [n_meas] replicas that reached the measurement
+    uint32_t *arrive;         // [n_meas] workgroups that reached the measurement
     uint32_t *t_now;          // [2] sweeps done per replica
+    int32_t parts;            // workgroups per replica: 1, or 2 for a replica split into z-slabs
+    uint32_t *xbuf;           // split: [replica][slab][sweep parity][colour][first/last plane][L * rw]
+    unsigned long long *pub;  // split: [replica][slab] boundary publications (see batch_run_split)
+    uint32_t *err;            // set when a split pair gave up waiting for its partner
 };
 
 // One workgroup's work: replica `replica` of job `job` from its current time
@@ -79,6 +84,7 @@ struct BatchUnit {
     int32_t replica;
     uint32_t t_stop;
     int32_t first;  // 1 on the job's first span: events at t = 0 are taken too
+    int32_t slab;   // split jobs: which z-slab (0 or 1); 0 otherwise
 };
 
 // Observable slots of one measurement (popcounts, like the plain form):
@@ -168,58 +174,32 @@ __device__ __forceinline__ void batch_store_spins(uint32_t *dst, int nt)
     for (int i = (int)threadIdx.x; i < 2 * S::POS; i += nt) dst[i] = batch_lds[i];
 }
 
-// Measurement at time t (index m) of replica r.
+// Publish this workgroup's part of replica r's configuration at measurement
+// m (rows [row0, row0 + rows) of both colours, taken from LDS spin words
+// batch_lds[c * src_stride + i]); the last workgroup of the job to arrive
+// computes the replica-pair observables, the overlap and C4 (eqs. 2, 3), from
+// the published copies.  flag_word is a free LDS word for a broadcast.
 template <int L, int RW>
-__device__ void batch_measure(const BatchJobDev &J, int r, int m, int n_taken)
+__device__ void batch_publish_and_pair(const BatchJobDev &J, int r, int m, int row0, int rows, int src_stride,
+                                       int flag_word)
 {
     using S = Shape<L, RW>;
     constexpr int W = S::W, POS = S::POS;
     const int nt = J.nt;
     unsigned long long *o = J.obs + (size_t)m * (size_t)J.obs_stride;
-    uint32_t unsat = 0, down = 0;
+    uint32_t *dst = J.mspins + ((size_t)m * 2 + (size_t)r) * 2 * POS;
+    const int n = rows * RW;
 #pragma unroll 1
-    for (int c = 0; c < 2; ++c) {
-        const uint32_t *own = lds_spin<S>(c);
-        const uint32_t *oth = lds_spin<S>(c ^ 1);
-        for (int p = (int)threadIdx.x; p < POS; p += nt) {
-            const int row = p / RW;
-            const int w = p - row * RW;
-            const int y = row % L;
-            const int z = row / L;
-            const int par = (y + z + c) & 1;
-            const int wp = w == RW - 1 ? 0 : w + 1;
-            const int yp = (y == L - 1 ? 0 : y + 1) + L * z;
-            const int zp = y + L * (z == L - 1 ? 0 : z + 1);
-            const uint32_t Sv = own[p];
-            const uint32_t O = oth[row * RW + w];
-            const uint32_t xp = par ? take_plus1<W>(O, oth[row * RW + wp]) : O;
-            unsat += __popc(Sv ^ xp ^ lds_bond<S>(0, c)[p]) +
-                     __popc(xor3(Sv, oth[yp * RW + w], lds_bond<S>(1, c)[p])) +
-                     __popc(xor3(Sv, oth[zp * RW + w], lds_bond<S>(2, c)[p]));
-            down += __popc(Sv);
-        }
-    }
-    wave_add(o + M_UNSAT + r, unsat);
-    wave_add(o + M_DOWN + r, down);
-#pragma unroll 1
-    for (int k = 0; k < n_taken; ++k) {
-        const uint32_t *ref = J.snaps + ((size_t)k * 2 + (size_t)r) * 2 * POS;
-        uint32_t diff = 0;
-        for (int i = (int)threadIdx.x; i < 2 * POS; i += nt) diff += __popc(batch_lds[i] ^ ref[i]);
-        wave_add(o + M_AUTO + 2 * k + r, diff);
-    }
-
-    // Publish this replica's configuration; the second replica to arrive
-    // computes the overlap and C4 from both copies.
-    batch_store_spins<S>(J.mspins + ((size_t)m * 2 + (size_t)r) * 2 * POS, nt);
+    for (int c = 0; c < 2; ++c)
+        for (int i = (int)threadIdx.x; i < n; i += nt) dst[c * POS + row0 * RW + i] = batch_lds[c * src_stride + i];
     __threadfence();
     __syncthreads();
-    uint32_t *flag = batch_lds + S::LATTICE_WORDS;
+    uint32_t *flag = batch_lds + flag_word;
     if (threadIdx.x == 0) *flag = atomicAdd(J.arrive + m, 1u);
     __syncthreads();
-    const bool second = *flag == 1u;
+    const bool last = *flag == (uint32_t)(2 * J.parts - 1);
     __syncthreads();
-    if (!second) return;
+    if (!last) return;
     __threadfence();
 
     const uint32_t *q0 = J.mspins + (size_t)m * 4 * POS;
@@ -267,6 +247,49 @@ __device__ void batch_measure(const BatchJobDev &J, int r, int m, int n_taken)
     }
 }
 
+// Measurement at time t (index m) of replica r (whole replica in LDS).
+template <int L, int RW>
+__device__ void batch_measure(const BatchJobDev &J, int r, int m, int n_taken)
+{
+    using S = Shape<L, RW>;
+    constexpr int W = S::W, POS = S::POS;
+    const int nt = J.nt;
+    unsigned long long *o = J.obs + (size_t)m * (size_t)J.obs_stride;
+    uint32_t unsat = 0, down = 0;
+#pragma unroll 1
+    for (int c = 0; c < 2; ++c) {
+        const uint32_t *own = lds_spin<S>(c);
+        const uint32_t *oth = lds_spin<S>(c ^ 1);
+        for (int p = (int)threadIdx.x; p < POS; p += nt) {
+            const int row = p / RW;
+            const int w = p - row * RW;
+            const int y = row % L;
+            const int z = row / L;
+            const int par = (y + z + c) & 1;
+            const int wp = w == RW - 1 ? 0 : w + 1;
+            const int yp = (y == L - 1 ? 0 : y + 1) + L * z;
+            const int zp = y + L * (z == L - 1 ? 0 : z + 1);
+            const uint32_t Sv = own[p];
+            const uint32_t O = oth[row * RW + w];
+            const uint32_t xp = par ? take_plus1<W>(O, oth[row * RW + wp]) : O;
+            unsat += __popc(Sv ^ xp ^ lds_bond<S>(0, c)[p]) +
+                     __popc(xor3(Sv, oth[yp * RW + w], lds_bond<S>(1, c)[p])) +
+                     __popc(xor3(Sv, oth[zp * RW + w], lds_bond<S>(2, c)[p]));
+            down += __popc(Sv);
+        }
+    }
+    wave_add(o + M_UNSAT + r, unsat);
+    wave_add(o + M_DOWN + r, down);
+#pragma unroll 1
+    for (int k = 0; k < n_taken; ++k) {
+        const uint32_t *ref = J.snaps + ((size_t)k * 2 + (size_t)r) * 2 * POS;
+        uint32_t diff = 0;
+        for (int i = (int)threadIdx.x; i < 2 * POS; i += nt) diff += __popc(batch_lds[i] ^ ref[i]);
+        wave_add(o + M_AUTO + 2 * k + r, diff);
+    }
+    batch_publish_and_pair<L, RW>(J, r, m, 0, L * L, POS, S::LATTICE_WORDS);
+}
+
 // Run one unit: load the replica and the couplings into LDS, sweep up to
 // t_stop taking the events scheduled in (t0, t_stop] (and at t0 itself on the
 // job's first span), then write the replica back.
@@ -312,14 +335,336 @@ __device__ void batch_run_unit(const BatchJobDev &J, int r, uint32_t t_stop, boo
     if (threadIdx.x == 0) J.t_now[r] = t;
 }
 
+// ---------------------------------------------------------------------------
+// Split replicas.  In a batch of uneven sizes one replica of the largest
+// sample on one CU sets the length of the launch.  Such a replica can instead
+// be cut into two z-slabs of NZ = L/2 planes, each held in LDS by its own
+// workgroup.  A site on a slab's first or last plane has one neighbour on the
+// other slab's adjacent plane (periodic in z), of the other colour; those
+// boundary words pass through a small exchange area in global memory.
+//
+// In each half-step wave 0 updates the slab's two boundary planes: it waits
+// until the partner slab has published its boundary words of the previous
+// half-step (a counter stored with release, read with acquire, agent scope),
+// updates its own boundary words and publishes them.  The other waves update
+// the interior planes meanwhile, which need nothing from the partner, so the
+// exchange latency hides behind interior work; the half-step still ends with
+// one workgroup barrier.  Publication counter of a slab: 1 once its state at
+// t = 0 is out, 2t + h + 2 after half-step h of sweep t.  Boundary words
+// written in sweep t go to slot t & 1 (the state at t = 0 to slot 1): a
+// measurement at t reads both colours of the partner's slot (t - 1) & 1
+// while the partner may already be writing sweep t into the other slot.  A wait gives up
+// after kSplitSpinTicks of the 100 MHz real-time counter (20 s), flags J.err
+// and ends the unit, so a launch always drains.
+
+constexpr unsigned long long kSplitSpinTicks = 2000000000ull;
+
+template <int L, int RW>
+struct Slab {
+    static constexpr int R = L / 2, W = R / RW;
+    static constexpr int NZ = L / 2;            // planes per slab
+    static constexpr int PL = L * RW;           // words of one plane of one colour
+    static constexpr int SPOS = NZ * PL;        // slab words of one colour
+    static constexpr int POS = L * L * RW;      // whole-lattice words of one colour
+    static constexpr int HALO = 8 * SPOS;       // [colour][PL] z couplings of the plane below the slab
+    static constexpr int FLAG = HALO + 2 * PL;  // broadcast words
+    static constexpr int LDS_WORDS = FLAG + 16;
+    static_assert(NZ >= 3 && R % RW == 0 && W % 4 == 0 && W <= 32, "invalid slab");
+};
+
+template <class S>
+__device__ __forceinline__ uint32_t *slab_spin(int c)
+{
+    return batch_lds + c * S::SPOS;
+}
+
+template <class S>
+__device__ __forceinline__ uint32_t *slab_bond(int d, int c)
+{
+    return batch_lds + (2 + 2 * d + c) * S::SPOS;
+}
+
+// Boundary words of (replica r, slab, slot, colour c, plane k: 0 first, 1 last).
+template <class S>
+__device__ __forceinline__ uint32_t *slab_xbuf(const BatchJobDev &J, int r, int slab, int slot, int c, int k)
+{
+    return J.xbuf +
+           (((((size_t)r * 2 + (size_t)slab) * 2 + (size_t)slot) * 2 + (size_t)c) * 2 + (size_t)k) * S::PL;
+}
+
+__device__ __forceinline__ uint32_t load_agent(const uint32_t *p)
+{
+    return __hip_atomic_load(const_cast<uint32_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wave 0: wait until the counter reaches `want`; false on time-out.
+__device__ __forceinline__ bool slab_wait(unsigned long long *pub, unsigned long long want)
+{
+    int ok = 1;
+    if (threadIdx.x == 0) {
+        const unsigned long long start = __builtin_amdgcn_s_memrealtime();
+        while (__hip_atomic_load(pub, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < want) {
+            __builtin_amdgcn_s_sleep(1);
+            if (__builtin_amdgcn_s_memrealtime() - start > kSplitSpinTicks) {
+                ok = 0;
+                break;
+            }
+        }
+    }
+    ok = __shfl(ok, 0, 64);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return ok != 0;
+}
+
+// Wave 0: make this wave's boundary stores visible, then set the counter.
+__device__ __forceinline__ void slab_publish(unsigned long long *pub, unsigned long long value)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (threadIdx.x == 0) __hip_atomic_store(pub, value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// New value of slab word p (colour c, sweep t), given its z-1 and z+1
+// neighbour words of the other colour and the coupling to the z-1 neighbour.
+template <int L, int RW, int SEL>
+__device__ __forceinline__ uint32_t slab_new_word(const BatchJobDev &J, int r, int c, uint32_t t, int z0, int p,
+                                                  uint32_t Ozm, uint32_t Ozp, uint32_t Bzm)
+{
+    using S = Slab<L, RW>;
+    constexpr int W = S::W;
+    const uint32_t *own = slab_spin<S>(c);
+    const uint32_t *oth = slab_spin<S>(c ^ 1);
+    const uint32_t *bx_own = slab_bond<S>(0, c), *by_own = slab_bond<S>(1, c), *bz_own = slab_bond<S>(2, c);
+    const uint32_t *bx_oth = slab_bond<S>(0, c ^ 1), *by_oth = slab_bond<S>(1, c ^ 1);
+    const unsigned row = (unsigned)p / RW;  // slab row y + L zl
+    const unsigned w = (unsigned)p - row * RW;
+    const unsigned y = row % L;
+    const unsigned zl = row / L;
+    const int par = (int)((y + zl + (unsigned)z0 + (unsigned)c) & 1u);
+    const unsigned wm = w == 0 ? RW - 1 : w - 1;
+    const unsigned wp = w == RW - 1 ? 0 : w + 1;
+    const unsigned ym = (y == 0 ? L - 1 : y - 1) + L * zl, yp = (y == L - 1 ? 0 : y + 1) + L * zl;
+    const unsigned base = row * RW;
+    const uint32_t S0 = own[p];
+    const uint32_t O = oth[base + w], Om = oth[base + wm], Op = oth[base + wp];
+    const uint32_t Xo = bx_oth[base + w], Xom = bx_oth[base + wm];
+    const uint32_t xp = par ? take_plus1<W>(O, Op) : O;
+    const uint32_t xm = par ? (O ^ Xo) : take_minus1<W>(O ^ Xo, Om ^ Xom);
+    const uint32_t a1 = S0 ^ xp ^ bx_own[p];
+    const uint32_t a2 = S0 ^ xm;
+    const uint32_t a3 = xor3(S0, oth[yp * RW + w], by_own[p]);
+    const uint32_t a4 = xor3(S0, oth[ym * RW + w], by_oth[ym * RW + w]);
+    const uint32_t a5 = xor3(S0, Ozp, bz_own[p]);
+    const uint32_t a6 = xor3(S0, Ozm, Bzm);
+    const Decision d = classify(a1, a2, a3, a4, a5, a6);
+    const uint32_t quad0 = (uint32_t)(((row + (unsigned)(L * z0)) * S::R + w * W) >> 2);
+    const uint32_t c2 = counter_word2(TAG_METRO, (uint32_t)c, (uint32_t)r);
+    uint32_t flips;
+    if constexpr (SEL == SEL_LDS)
+        flips = flip_mask_lds<W>(d, t, quad0, c2, J.sample, J.k0, J.k1, batch_tables());
+    else
+        flips = flip_mask<W>(d, t, quad0, c2, J.sample, J.k0, J.k1, J.thr1, J.thr2, J.thr3);
+    return S0 ^ flips;
+}
+
+// Half-step (t, colour c) of one slab.  Returns false (wave 0 only) if the
+// partner never published.
+template <int L, int RW, int SEL>
+__device__ __forceinline__ bool slab_half_step(const BatchJobDev &J, int r, int slab, int c, uint32_t t,
+                                               unsigned long long want, unsigned long long done)
+{
+    using S = Slab<L, RW>;
+    const int z0 = slab * S::NZ;
+    uint32_t *own = slab_spin<S>(c);
+    const uint32_t *oth = slab_spin<S>(c ^ 1);
+    const uint32_t *bz_oth = slab_bond<S>(2, c ^ 1);
+    int tid = (int)threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    if (tid >= 64) {
+        // interior planes 1 .. NZ-2
+#pragma unroll 1
+        for (int p = S::PL + tid - 64; p < S::SPOS - S::PL; p += J.nt - 64)
+            own[p] = slab_new_word<L, RW, SEL>(J, r, c, t, z0, p, oth[p - S::PL], oth[p + S::PL], bz_oth[p - S::PL]);
+        return true;
+    }
+    if (!slab_wait(J.pub + 2 * r + (slab ^ 1), want)) return false;
+    // colour c ^ 1 was last written in the previous half-step: this sweep's
+    // first half-step, or the previous sweep's second
+    const int rslot = (int)((c == r ? t + 1 : t) & 1u);
+    const int wslot = (int)(t & 1u);
+    const uint32_t *part_last = slab_xbuf<S>(J, r, slab ^ 1, rslot, c ^ 1, 1);   // the plane below this slab
+    const uint32_t *part_first = slab_xbuf<S>(J, r, slab ^ 1, rslot, c ^ 1, 0);  // the plane above it
+    const uint32_t *halo_bz = batch_lds + S::HALO + (c ^ 1) * S::PL;
+#pragma unroll 1
+    for (int i = tid; i < 2 * S::PL; i += 64) {
+        const int k = i >= S::PL ? 1 : 0;
+        const int j = i - k * S::PL;
+        const int p = k ? S::SPOS - S::PL + j : j;
+        uint32_t v;
+        if (k == 0)
+            v = slab_new_word<L, RW, SEL>(J, r, c, t, z0, p, load_agent(part_last + j), oth[p + S::PL], halo_bz[j]);
+        else
+            v = slab_new_word<L, RW, SEL>(J, r, c, t, z0, p, oth[p - S::PL], load_agent(part_first + j),
+                                          bz_oth[p - S::PL]);
+        own[p] = v;
+        slab_xbuf<S>(J, r, slab, wslot, c, k)[j] = v;
+    }
+    slab_publish(J.pub + 2 * r + slab, done);
+    return true;
+}
+
+// Measurement m at time t of one slab: its partial sums, then its part of
+// the published configuration.  The partner's first plane (the +z neighbour
+// of this slab's last plane) comes from the exchange area; wave 0 has waited
+// for the partner's state at t.
+template <int L, int RW>
+__device__ void slab_measure(const BatchJobDev &J, int r, int slab, int m, int n_taken, uint32_t t)
+{
+    using S = Slab<L, RW>;
+    constexpr int W = S::W;
+    const int nt = J.nt;
+    const int z0 = slab * S::NZ;
+    unsigned long long *o = J.obs + (size_t)m * (size_t)J.obs_stride;
+    uint32_t unsat = 0, down = 0;
+#pragma unroll 1
+    for (int c = 0; c < 2; ++c) {
+        const uint32_t *own = slab_spin<S>(c);
+        const uint32_t *oth = slab_spin<S>(c ^ 1);
+        const uint32_t *part_first = slab_xbuf<S>(J, r, slab ^ 1, (int)((t + 1) & 1u), c ^ 1, 0);
+        for (int p = (int)threadIdx.x; p < S::SPOS; p += nt) {
+            const int row = p / RW;
+            const int w = p - row * RW;
+            const int y = row % L;
+            const int zl = row / L;
+            const int par = (y + zl + z0 + c) & 1;
+            const int wp = w == RW - 1 ? 0 : w + 1;
+            const int yp = (y == L - 1 ? 0 : y + 1) + L * zl;
+            const uint32_t Sv = own[p];
+            const uint32_t O = oth[row * RW + w];
+            const uint32_t xp = par ? take_plus1<W>(O, oth[row * RW + wp]) : O;
+            const uint32_t Ozp = zl + 1 < S::NZ ? oth[p + S::PL] : load_agent(part_first + (p - (S::SPOS - S::PL)));
+            unsat += __popc(Sv ^ xp ^ slab_bond<S>(0, c)[p]) +
+                     __popc(xor3(Sv, oth[yp * RW + w], slab_bond<S>(1, c)[p])) +
+                     __popc(xor3(Sv, Ozp, slab_bond<S>(2, c)[p]));
+            down += __popc(Sv);
+        }
+    }
+    wave_add(o + M_UNSAT + r, unsat);
+    wave_add(o + M_DOWN + r, down);
+#pragma unroll 1
+    for (int k = 0; k < n_taken; ++k) {
+        const uint32_t *ref = J.snaps + ((size_t)k * 2 + (size_t)r) * 2 * S::POS + (size_t)z0 * S::PL;
+        uint32_t diff = 0;
+#pragma unroll 1
+        for (int c = 0; c < 2; ++c)
+            for (int i = (int)threadIdx.x; i < S::SPOS; i += nt) diff += __popc(batch_lds[c * S::SPOS + i] ^ ref[c * S::POS + i]);
+        wave_add(o + M_AUTO + 2 * k + r, diff);
+    }
+    batch_publish_and_pair<L, RW>(J, r, m, z0 * L, S::NZ * L, S::SPOS, S::FLAG);
+}
+
+// Copy this slab's two colour parts between LDS and a [colour][POS] array.
+template <class S>
+__device__ __forceinline__ void slab_store(uint32_t *dst, int z0, int nt)
+{
+#pragma unroll 1
+    for (int c = 0; c < 2; ++c)
+        for (int i = (int)threadIdx.x; i < S::SPOS; i += nt)
+            dst[(size_t)c * S::POS + (size_t)z0 * S::PL + i] = batch_lds[c * S::SPOS + i];
+}
+
+// Run one slab of a split replica up to t_stop (events as in batch_run_unit).
+template <int L, int RW, int SEL>
+__device__ void batch_run_slab(const BatchJobDev &J, int r, int slab, uint32_t t_stop, bool first)
+{
+    using S = Slab<L, RW>;
+    const int nt = J.nt;
+    if ((int)threadIdx.x >= nt) return;
+    const uint32_t t0 = J.t_now[r];
+    if (!first && t0 >= t_stop) return;
+    const int z0 = slab * S::NZ;
+    const int zb = (z0 + L - 1) % L;  // the plane below the slab
+    const uint32_t *src = J.spins + (size_t)r * 2 * S::POS;
+    for (int c = 0; c < 2; ++c)
+        for (int i = (int)threadIdx.x; i < S::SPOS; i += nt)
+            batch_lds[c * S::SPOS + i] = src[(size_t)c * S::POS + (size_t)z0 * S::PL + i];
+    for (int dc = 0; dc < 6; ++dc)
+        for (int i = (int)threadIdx.x; i < S::SPOS; i += nt)
+            batch_lds[(2 + dc) * S::SPOS + i] = J.bonds[(size_t)dc * S::POS + (size_t)z0 * S::PL + i];
+    for (int c = 0; c < 2; ++c)
+        for (int i = (int)threadIdx.x; i < S::PL; i += nt)
+            batch_lds[S::HALO + c * S::PL + i] = J.bonds[(size_t)(4 + c) * S::POS + (size_t)zb * S::PL + i];
+    if constexpr (SEL == SEL_LDS) fill_select_tables(batch_tables(), J.thr1, J.thr2, J.thr3, (int)threadIdx.x, nt);
+    uint32_t *abort_flag = batch_lds + S::FLAG + 1;
+    if (threadIdx.x == 0) *abort_flag = 0;
+    __syncthreads();
+    unsigned long long *my_pub = J.pub + 2 * r + slab;
+    if (first && threadIdx.x < 64) {
+        // the state at t = 0 of both colours' boundary planes
+        for (int c = 0; c < 2; ++c)
+            for (int i = (int)threadIdx.x; i < 2 * S::PL; i += 64) {
+                const int k = i >= S::PL ? 1 : 0;
+                const int j = i - k * S::PL;
+                slab_xbuf<S>(J, r, slab, 1, c, k)[j] = batch_lds[c * S::SPOS + (k ? S::SPOS - S::PL : 0) + j];
+            }
+        slab_publish(my_pub, 1ull);
+    }
+
+    int im = 0, iw = 0;
+    while (im < J.n_meas && (J.meas_t[im] < t0 || (!first && J.meas_t[im] == t0))) ++im;
+    while (iw < J.n_tw && (J.tw_t[iw] < t0 || (!first && J.tw_t[iw] == t0))) ++iw;
+
+    uint32_t t = t0;
+    for (;;) {
+        if (iw < J.n_tw && J.tw_t[iw] == t) {
+            slab_store<S>(J.snaps + ((size_t)iw * 2 + (size_t)r) * 2 * S::POS, z0, nt);
+            ++iw;
+            __threadfence();
+            __syncthreads();
+        }
+        if (im < J.n_meas && J.meas_t[im] == t) {
+            if (threadIdx.x < 64 && !slab_wait(J.pub + 2 * r + (slab ^ 1), 2ull * t + 1)) {
+                if (threadIdx.x == 0) {
+                    *abort_flag = 1;
+                    atomicOr(J.err, 1u);
+                }
+            }
+            __syncthreads();
+            if (*abort_flag) return;
+            slab_measure<L, RW>(J, r, slab, im, iw, t);
+            ++im;
+            __syncthreads();
+        }
+        if (t >= t_stop) break;
+#pragma unroll 1
+        for (int h = 0; h < 2; ++h) {
+            const unsigned long long want = 2ull * t + (unsigned)h + 1, done = want + 1;
+            if (!slab_half_step<L, RW, SEL>(J, r, slab, r ^ h, t, want, done) && threadIdx.x == 0) {
+                *abort_flag = 1;
+                atomicOr(J.err, 1u);
+            }
+            __syncthreads();
+            if (*abort_flag) return;
+        }
+        ++t;
+    }
+    slab_store<S>(J.spins + (size_t)r * 2 * S::POS, z0, nt);
+    if (threadIdx.x == 0) J.t_now[r] = t;
+}
+
 // Dispatch on the packing (finest valid alternative or the default) and the
 // select variant for one lattice size.
 template <int L>
-__device__ __forceinline__ void batch_dispatch_L(const BatchJobDev &J, int r, uint32_t t_stop, bool first)
+__device__ __forceinline__ void batch_dispatch_L(const BatchJobDev &J, int r, int slab, uint32_t t_stop, bool first)
 {
     constexpr int R = L / 2;
     constexpr int RW0 = words_per_row_c(R);
     constexpr int RW1 = finer_words_per_row_c(R, RW0);
+    if constexpr (L >= kSplitMinL) {
+        if (J.parts == 2) {
+            if (J.rw == RW0 && J.sel == SEL_LDS) batch_run_slab<L, RW0, SEL_LDS>(J, r, slab, t_stop, first);
+            return;
+        }
+    }
     if (J.rw == RW0) {
         if (J.sel == SEL_LDS) batch_run_unit<L, RW0, SEL_LDS>(J, r, t_stop, first);
         else batch_run_unit<L, RW0, SEL_REG>(J, r, t_stop, first);
@@ -338,14 +683,14 @@ __global__ __launch_bounds__(kBatchThreads) void batch_kernel(const BatchJobDev 
     const BatchJobDev J = jobs[u.job];
     const bool first = u.first != 0;
     switch (J.L) {
-    case 8: batch_dispatch_L<8>(J, u.replica, u.t_stop, first); break;
-    case 16: batch_dispatch_L<16>(J, u.replica, u.t_stop, first); break;
-    case 24: batch_dispatch_L<24>(J, u.replica, u.t_stop, first); break;
-    case 32: batch_dispatch_L<32>(J, u.replica, u.t_stop, first); break;
-    case 40: batch_dispatch_L<40>(J, u.replica, u.t_stop, first); break;
-    case 48: batch_dispatch_L<48>(J, u.replica, u.t_stop, first); break;
-    case 56: batch_dispatch_L<56>(J, u.replica, u.t_stop, first); break;
-    case 64: batch_dispatch_L<64>(J, u.replica, u.t_stop, first); break;
+    case 8: batch_dispatch_L<8>(J, u.replica, u.slab, u.t_stop, first); break;
+    case 16: batch_dispatch_L<16>(J, u.replica, u.slab, u.t_stop, first); break;
+    case 24: batch_dispatch_L<24>(J, u.replica, u.slab, u.t_stop, first); break;
+    case 32: batch_dispatch_L<32>(J, u.replica, u.slab, u.t_stop, first); break;
+    case 40: batch_dispatch_L<40>(J, u.replica, u.slab, u.t_stop, first); break;
+    case 48: batch_dispatch_L<48>(J, u.replica, u.slab, u.t_stop, first); break;
+    case 56: batch_dispatch_L<56>(J, u.replica, u.slab, u.t_stop, first); break;
+    case 64: batch_dispatch_L<64>(J, u.replica, u.slab, u.t_stop, first); break;
     default: break;
     }
 }

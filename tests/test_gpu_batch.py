@@ -171,3 +171,122 @@ def test_batch_graph_replays(ea_gpu):
                 assert np.array_equal(g.spins(j, r), eager.spins(j, r)), (rep, j, r)
         other.sweep(10)
         other.measure()
+
+
+# ---------------------------------------------------------------------------
+# Split replicas: two workgroups per replica exchanging boundary planes.
+
+def _split_jobs():
+    from paper_1411_5512_amd.workloads import Job
+    return [
+        Job(64, 0.5, 0.7, seed=21, sample=0, n_sweeps=12, meas_t=[0, 1, 5, 12], tw=[0, 5]),
+        Job(48, 0.3, 0.9, seed=22, sample=1, n_sweeps=10, meas_t=[3, 10], tw=[3]),
+        Job(56, 0.5, 1.1, seed=23, sample=0, n_sweeps=8, meas_t=[8], tw=[2]),
+        Job(64, 0.2, 0.0, seed=24, sample=0, n_sweeps=6, meas_t=[6], tw=[]),
+        Job(16, 0.5, 0.8, seed=25, sample=0, n_sweeps=20, meas_t=[20], tw=[10]),
+        Job(48, 0.5, 0.8, seed=26, sample=0, n_sweeps=0, meas_t=[0], tw=[0]),
+    ]
+
+
+def test_split_batch_matches_oracle(ea_gpu, oracle_mod):
+    jobs = _split_jobs()
+    b = ea_gpu.Batch(jobs, split=ea_gpu.Batch.SPLIT_ALWAYS)
+    assert [b.parts(j) for j in range(len(jobs))] == [2, 2, 2, 2, 1, 2]
+    b.run()
+    for j, job in enumerate(jobs):
+        _say(f"split job {j}: L={job.L} p={job.p} T={job.T} sweeps={job.n_sweeps}")
+        o = oracle_mod.Sim(job.L, job.p, job.T, seed=job.seed, sample=job.sample, n_slots=len(job.tw))
+        ref = _run_schedule(o, job)
+        assert b.time(j) == job.n_sweeps
+        for k, want in enumerate(ref):
+            _same_obs(b.result(j, k), want, f"split job {j} meas {k}")
+        for r in (0, 1):
+            assert np.array_equal(b.spins(j, r), o.spins(r)), f"split job {j} replica {r}"
+
+
+def test_split_spans_reset_and_graph(ea_gpu):
+    jobs = _split_jobs()
+    whole = ea_gpu.Batch(jobs, split=ea_gpu.Batch.SPLIT_NEVER)
+    whole.run()
+    parts = ea_gpu.Batch(jobs, split=ea_gpu.Batch.SPLIT_ALWAYS)
+    for t in (0, 1, 4, 4, 9):
+        parts.run(t)
+    parts.run()
+
+    def same(a, label):
+        for j, job in enumerate(jobs):
+            for k in range(len(job.meas_t)):
+                _same_obs(a.result(j, k), whole.result(j, k), f"{label} job {j} meas {k}")
+            for r in (0, 1):
+                assert np.array_equal(a.spins(j, r), whole.spins(j, r)), (label, j, r)
+
+    same(parts, "spans")
+    parts.reset()
+    parts.run()
+    same(parts, "reset")
+    g = ea_gpu.Batch(jobs, split=ea_gpu.Batch.SPLIT_ALWAYS)
+    g.capture()
+    other = ea_gpu.Sim(16, 0.5, 0.8, seed=3)
+    for rep in range(3):
+        g.replay()
+        same(g, f"replay {rep}")
+        other.sweep(10)
+        other.measure()
+
+
+def test_split_matches_unsplit_full_mix(ea_gpu):
+    """The 256-job mixed workload (L in {24,32,48,64}) in one launch with its
+    L = 64 replicas split (256 slabs, one per CU) equals the unsplit run,
+    every measurement and final state, at 300 sweeps."""
+    from paper_1411_5512_amd import workloads as wl
+    jobs = wl.batch_jobs(n_jobs=256, n_sweeps=300)
+    sp = ea_gpu.Batch(jobs, split=ea_gpu.Batch.SPLIT_ALWAYS)
+    split_jobs = [j for j in range(len(jobs)) if sp.parts(j) == 2]
+    _say(f"split {len(split_jobs)} jobs, sizes {sorted({jobs[j].L for j in split_jobs})}")
+    assert split_jobs and all(jobs[j].L == 64 for j in split_jobs)
+    sp.run()
+    ref = ea_gpu.Batch(jobs, split=ea_gpu.Batch.SPLIT_NEVER)
+    ref.run()
+    for j, job in enumerate(jobs):
+        for k in range(len(job.meas_t)):
+            _same_obs(sp.result(j, k), ref.result(j, k), f"job {j} meas {k}")
+        if j in split_jobs[:8]:
+            for r in (0, 1):
+                assert np.array_equal(sp.spins(j, r), ref.spins(j, r)), (j, r)
+
+
+def test_split_automatic_choice(ea_gpu):
+    """Automatic choice: a few large samples (the run is one replica's
+    latency) are split; the 256-job mix (enough work for every CU) is not."""
+    from paper_1411_5512_amd import workloads as wl
+    from paper_1411_5512_amd.workloads import Job
+    few = [Job(64, 0.5, 0.7, seed=40 + i, n_sweeps=50, meas_t=[10, 50], tw=[10]) for i in range(8)]
+    a = ea_gpu.Batch(few)
+    assert all(a.parts(j) == 2 for j in range(len(few)))
+    a.run()
+    ref = ea_gpu.Batch(few, split=ea_gpu.Batch.SPLIT_NEVER)
+    ref.run()
+    for j, job in enumerate(few):
+        for k in range(len(job.meas_t)):
+            _same_obs(a.result(j, k), ref.result(j, k), f"few job {j} meas {k}")
+    mix = ea_gpu.Batch(wl.batch_jobs(n_jobs=256, n_sweeps=100))
+    assert all(mix.parts(j) == 1 for j in range(256))
+
+
+def test_split_windowed_parity_late_times(ea_gpu, oracle_mod):
+    from paper_1411_5512_amd.workloads import Job
+    jobs = [Job(64, 0.5, 0.7, seed=1, n_sweeps=20000, meas_t=[20000], tw=[]),
+            Job(48, 0.3, 0.6, seed=2, n_sweeps=20000, meas_t=[20000], tw=[])]
+    b = ea_gpu.Batch(jobs, split=ea_gpu.Batch.SPLIT_ALWAYS)
+    assert b.parts(0) == 2 and b.parts(1) == 2
+    b.run(15000)
+    states = [[b.spins(j, r) for r in (0, 1)] for j in range(2)]
+    b.run(15003)
+    for j, job in enumerate(jobs):
+        o = oracle_mod.Sim(job.L, job.p, job.T, seed=job.seed, sample=job.sample)
+        for r in (0, 1):
+            o.set_spins(r, states[j][r])
+        o.set_time(15000)
+        o.sweep(3)
+        for r in (0, 1):
+            assert np.array_equal(b.spins(j, r), o.spins(r)), (j, r)
