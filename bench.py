@@ -77,6 +77,7 @@ def cpu_baseline(job, sweeps: int):
 
 
 def bench_plain(ea, torch, job, steps: int, burst: int):
+    tuned = ea.tune_plain(job.L)  # untimed: picks the bit packing of the plain form for this size
     sim = ea.Sim(job.L, job.p, job.T, seed=job.seed, sample=job.sample, n_slots=len(job.tw))
     stream = sim.stream
     run_plain_job(sim, job)  # warm-up: builds the captured graph
@@ -100,6 +101,7 @@ def bench_plain(ea, torch, job, steps: int, burst: int):
     return {
         "workload": f"L={job.L} p={job.p} T={job.T}, 1 sample x 2 replicas, {job.n_sweeps} sweeps, "
                     f"{len(job.meas_t)} measurements, tw={job.tw}; one launch per half-step",
+        "words_per_row": tuned["words_per_row"],
         "ps_per_flip": round(ms * 1e-3 / job.flips * 1e12, 4),
         "ms_per_step": round(ms, 3),
         "steps": steps,
@@ -112,6 +114,7 @@ def bench_plain(ea, torch, job, steps: int, burst: int):
 def plain_rate(ea, torch, L: int, sweeps: int = 256) -> float:
     """ps per attempted flip of the plain form at size L (p = 0.5, T = 0.7),
     a burst of captured sweeps timed with events on the run's stream."""
+    ea.tune_plain(L)  # untimed: picks the bit packing of the plain form for this size
     sim = ea.Sim(L, 0.5, 0.7, seed=1)
     sim.sweep(64)  # builds the captured graph
     b0 = torch.cuda.Event(enable_timing=True)

@@ -84,6 +84,11 @@ typedef struct {
     void *stream;         /* hipStream_t to enqueue on, or NULL */
     void *dev_buf;        /* optional caller-owned device buffer, or NULL */
     size_t dev_buf_bytes; /* its size in bytes */
+    int32_t words_per_row; /* bit packing: 32-bit words per row of L/2 same-colour sites,
+                              each holding a whole number of 4-site blocks and at most 32
+                              sites; 0 = the library's choice (autotuned by ea_tune_plain
+                              if it ran for L, else enough words that one half-step launch
+                              has at least 65536 threads).  Results never depend on it. */
 } ea_config;
 
 /* Observables at the current time t, integer sums over the N sites (the
@@ -110,8 +115,11 @@ typedef struct {
     int64_t *c4;
 } ea_obs;
 
-/* Device bytes a run of side L with n_tw snapshot slots needs. */
+/* Device bytes a run of side L with n_tw snapshot slots needs, in the
+ * packing the library would choose now (words_per_row = 0); ea_footprint_ex
+ * takes L, n_tw_slots and words_per_row from a config. */
 ea_status ea_footprint(int32_t L, int32_t n_tw, size_t *bytes);
+ea_status ea_footprint_ex(const ea_config *cfg, size_t *bytes);
 
 /* Acceptance thresholds of eq. (9): out[k-1] for dE = 4k, k = 1..3. */
 ea_status ea_thresholds(double T, uint32_t out[3]);
@@ -123,6 +131,9 @@ ea_status ea_thresholds(double T, uint32_t out[3]);
 ea_status ea_create(int32_t L, double p, double T, uint64_t seed, ea_sim **out);
 ea_status ea_create_ex(const ea_config *cfg, ea_sim **out);
 void ea_destroy(ea_sim *sim);
+
+/* The run's bit packing (words per row). */
+ea_status ea_words_per_row(const ea_sim *sim, int32_t *rw);
 
 /* Restart the run in place for another disorder sample: regenerate the
  * couplings and both replicas' initial spins for (seed, sample), set t = 0
@@ -210,6 +221,15 @@ typedef struct {
  * the choice came from the cache). */
 ea_status ea_tune(int32_t L, int32_t force, ea_tune_choice *chosen, ea_tune_choice *tried, int32_t max_tried,
                   int32_t *n_tried);
+
+/* Autotune the plain form's bit packing for side L: time a burst of sweeps
+ * for every valid words-per-row, reject any whose final spins differ from the
+ * coarsest packing's, keep the fastest for later ea_create calls with
+ * words_per_row = 0 (and append it to EA_TUNE_CACHE if set).  tried[i]
+ * reports words_per_row, threads per half-step launch, ms and parity_ok
+ * (select = 1); *n_tried = 0 when the choice came from the cache. */
+ea_status ea_tune_plain(int32_t L, int32_t force, int32_t *chosen_rw, ea_tune_choice *tried, int32_t max_tried,
+                        int32_t *n_tried);
 
 /* Copy the job list (the caller's schedule arrays may be freed afterwards),
  * allocate device memory for every job and generate the initial states.

@@ -28,9 +28,15 @@ def thresholds(T: float) -> np.ndarray:
     return out
 
 
-def footprint(L: int, n_tw: int = 0) -> int:
+def footprint(L: int, n_tw: int = 0, words_per_row: int = 0) -> int:
+    """Device bytes of a plain run (words_per_row = 0: the library's packing)."""
     out = ctypes.c_size_t(0)
-    abi.check(abi.lib().ea_footprint(int(L), int(n_tw), ctypes.byref(out)))
+    if words_per_row == 0:
+        abi.check(abi.lib().ea_footprint(int(L), int(n_tw), ctypes.byref(out)))
+    else:
+        cfg = abi.Config()
+        cfg.L, cfg.n_tw_slots, cfg.words_per_row = int(L), int(n_tw), int(words_per_row)
+        abi.check(abi.lib().ea_footprint_ex(ctypes.byref(cfg), ctypes.byref(out)))
     return int(out.value)
 
 
@@ -45,6 +51,17 @@ def tune(L: int, force: bool = False) -> dict:
         return {"words_per_row": c.words_per_row, "threads": c.threads,
                 "select": "lds" if c.select == 0 else "reg", "ms": c.ms, "parity_ok": bool(c.parity_ok)}
     return {"chosen": d(chosen), "tried": [d(tried[i]) for i in range(n.value)]}
+
+
+def tune_plain(L: int, force: bool = False) -> dict:
+    """Autotune the plain form's bit packing for side L (see ea_tune_plain)."""
+    rw = ctypes.c_int32(0)
+    tried = (abi.TuneChoice * 64)()
+    n = ctypes.c_int32(0)
+    abi.check(abi.lib().ea_tune_plain(int(L), int(force), ctypes.byref(rw), tried, 64, ctypes.byref(n)))
+    return {"words_per_row": rw.value,
+            "tried": [{"words_per_row": tried[i].words_per_row, "threads": tried[i].threads, "ms": tried[i].ms,
+                       "parity_ok": bool(tried[i].parity_ok)} for i in range(n.value)]}
 
 
 def _torch_stream_and_buffer(nbytes: int, use_torch: bool):
@@ -81,7 +98,7 @@ class Sim:
     """One run: L^3 lattice, couplings with P(J=-1) = p, two replicas at T."""
 
     def __init__(self, L: int, p: float, T: float, seed: int, sample: int = 0,
-                 n_slots: int = 0, use_torch: bool = True):
+                 n_slots: int = 0, use_torch: bool = True, words_per_row: int = 0):
         self.L, self.p, self.T = int(L), float(p), float(T)
         self.seed, self.sample, self.n_slots = int(seed), int(sample), int(n_slots)
         self.N = self.L ** 3
@@ -89,8 +106,11 @@ class Sim:
         cfg = abi.Config()
         cfg.L, cfg.p, cfg.T = self.L, self.p, self.T
         cfg.seed, cfg.sample, cfg.n_tw_slots = self.seed, self.sample, self.n_slots
-        need = footprint(self.L, self.n_slots) if 8 <= self.L <= 256 and self.L % 8 == 0 \
-            and 0 <= self.n_slots <= 64 else 0
+        cfg.words_per_row = int(words_per_row)
+        need = ctypes.c_size_t(0)
+        if abi.lib().ea_footprint_ex(ctypes.byref(cfg), ctypes.byref(need)) != 0:
+            need = ctypes.c_size_t(0)  # invalid arguments: ea_create_ex reports them
+        need = need.value
         self._stream, self._buf = _torch_stream_and_buffer(need, use_torch and need > 0)
         if self._stream is not None:
             cfg.stream = ctypes.c_void_p(self._stream.cuda_stream)
@@ -101,6 +121,12 @@ class Sim:
         h = ctypes.c_void_p()
         abi.check(abi.lib().ea_create_ex(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
+
+    @property
+    def words_per_row(self) -> int:
+        rw = ctypes.c_int32(0)
+        abi.check(abi.lib().ea_words_per_row(self._h, ctypes.byref(rw)))
+        return rw.value
 
     # -- lifetime -------------------------------------------------------
     def close(self):

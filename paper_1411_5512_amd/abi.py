@@ -35,6 +35,7 @@ class Config(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("dev_buf", ctypes.c_void_p),
         ("dev_buf_bytes", ctypes.c_size_t),
+        ("words_per_row", ctypes.c_int32),
     ]
 
 
@@ -138,6 +139,10 @@ _SIGS = {
     "ea_batch_destroy": (None, [ctypes.c_void_p]),
     "ea_batch_reset": (ctypes.c_int, [ctypes.c_void_p]),
     "ea_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "ea_tune_plain": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(TuneChoice), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "ea_footprint_ex": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_size_t)]),
+    "ea_words_per_row": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "ea_tune": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(TuneChoice),
                                ctypes.POINTER(TuneChoice), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "ea_batch_capture": (ctypes.c_int, [ctypes.c_void_p]),

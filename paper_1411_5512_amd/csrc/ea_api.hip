@@ -4,11 +4,15 @@
 #include "ea.h"
 #include "ea_batch_kernels.h"
 
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -43,18 +47,78 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 // holds a whole number of 4-site random-word blocks.
 int words_per_row(int R) { return ea::words_per_row_c(R); }
 
+// Any packing of a row of R sites into rw words of whole 4-site blocks, at
+// most 32 sites per word.
+bool rw_valid(int R, int rw) { return rw >= 1 && R % 4 == 0 && (R / 4) % rw == 0 && R / rw <= 32; }
+
+// Packing of the plain form for side L when the caller leaves it open: the
+// autotuned one (ea_tune_plain, or a line of the EA_TUNE_CACHE file), else
+// the coarsest packing refined until one half-step launch has at least
+// kPlainMinThreads threads (one wave per SIMD of every CU): below that a
+// launch lasts as long as one thread's chain of dependent instructions.
+constexpr long kPlainMinThreads = 65536;
+std::mutex g_plain_mu;
+std::map<int, int> g_plain_tuned;  // L -> words per row
+bool g_plain_file_read = false;
+
+std::string device_arch_name()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t colon = a.find(':');
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+// Lines "<arch> plain <L> <rw> <ms>" of the tuning cache (caller holds g_plain_mu).
+void read_plain_tune_file()
+{
+    if (g_plain_file_read) return;
+    g_plain_file_read = true;
+    const char *path = std::getenv("EA_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    const std::string arch = device_arch_name();
+    char line[256], a[64], tag[16];
+    int L, rw;
+    while (std::fgets(line, sizeof line, f))
+        if (std::sscanf(line, "%63s %15s %d %d", a, tag, &L, &rw) == 4 && arch == a && std::string(tag) == "plain" &&
+            L >= 8 && L <= kMaxL && L % 8 == 0 && rw_valid(L / 2, rw))
+            g_plain_tuned[L] = rw;
+    std::fclose(f);
+}
+
+int plain_default_rw(int L)
+{
+    const int R = L / 2;
+    int rw = words_per_row(R);
+    for (int d = rw + 1; d <= R / 4 && 2 * (long)L * L * rw < kPlainMinThreads; ++d)
+        if (rw_valid(R, d)) rw = d;
+    return rw;
+}
+
+int plain_rw(int L)
+{
+    std::lock_guard<std::mutex> lk(g_plain_mu);
+    read_plain_tune_file();
+    auto it = g_plain_tuned.find(L);
+    return it != g_plain_tuned.end() ? it->second : plain_default_rw(L);
+}
+
 struct Layout {
     int L, R, RW, W, rows, plane;
     size_t spin_words, bond_words, snap_words, meas_count;
     size_t off_spins, off_bonds, off_snaps, off_meas, off_ctl, total;
 };
 
-Layout make_layout(int L, int n_slots)
+Layout make_layout(int L, int n_slots, int rw)
 {
     Layout y{};
     y.L = L;
     y.R = L / 2;
-    y.RW = words_per_row(y.R);
+    y.RW = rw;
     y.W = y.R / y.RW;
     y.rows = L * L;
     y.plane = y.rows * y.RW;
@@ -241,7 +305,26 @@ ea_status ea_footprint(int32_t L, int32_t n_tw, size_t *bytes)
     if (!bytes) return fail(EA_ERR_ARG, "bytes is NULL");
     if (!valid_L(L)) return fail(EA_ERR_ARG, "L=%d must be a multiple of 8 in [8, %d]", L, kMaxL);
     if (n_tw < 0 || n_tw > kMaxSlots) return fail(EA_ERR_ARG, "n_tw=%d outside [0, %d]", n_tw, kMaxSlots);
-    *bytes = make_layout(L, n_tw).total;
+    *bytes = make_layout(L, n_tw, plain_rw(L)).total;
+    return EA_OK;
+}
+
+ea_status ea_footprint_ex(const ea_config *cfg, size_t *bytes)
+{
+    if (!cfg || !bytes) return fail(EA_ERR_ARG, "NULL argument");
+    if (!valid_L(cfg->L)) return fail(EA_ERR_ARG, "L=%d must be a multiple of 8 in [8, %d]", cfg->L, kMaxL);
+    if (cfg->n_tw_slots < 0 || cfg->n_tw_slots > kMaxSlots)
+        return fail(EA_ERR_ARG, "n_tw_slots=%d outside [0, %d]", cfg->n_tw_slots, kMaxSlots);
+    const int rw = cfg->words_per_row ? cfg->words_per_row : plain_rw(cfg->L);
+    if (!rw_valid(cfg->L / 2, rw)) return fail(EA_ERR_ARG, "invalid words_per_row=%d", rw);
+    *bytes = make_layout(cfg->L, cfg->n_tw_slots, rw).total;
+    return EA_OK;
+}
+
+ea_status ea_words_per_row(const ea_sim *s, int32_t *rw)
+{
+    if (!s || !rw) return fail(EA_ERR_ARG, "NULL argument");
+    *rw = s->lay.RW;
     return EA_OK;
 }
 
@@ -274,7 +357,11 @@ ea_status ea_create_ex(const ea_config *cfg, ea_sim **out)
     if (cfg->n_tw_slots < 0 || cfg->n_tw_slots > kMaxSlots)
         return fail(EA_ERR_ARG, "n_tw_slots=%d outside [0, %d]", cfg->n_tw_slots, kMaxSlots);
 
-    Layout lay = make_layout(cfg->L, cfg->n_tw_slots);
+    const int rw = cfg->words_per_row ? cfg->words_per_row : plain_rw(cfg->L);
+    if (!rw_valid(cfg->L / 2, rw))
+        return fail(EA_ERR_ARG, "words_per_row=%d does not split a row of %d sites into whole 4-site blocks of "
+                                "at most 32", rw, cfg->L / 2);
+    Layout lay = make_layout(cfg->L, cfg->n_tw_slots, rw);
     if (cfg->dev_buf) {
         if (cfg->dev_buf_bytes < lay.total)
             return fail(EA_ERR_ARG, "dev_buf holds %zu bytes, %zu needed", cfg->dev_buf_bytes, lay.total);
@@ -462,6 +549,86 @@ ea_status ea_sync(ea_sim *s)
 {
     if (!s) return fail(EA_ERR_ARG, "sim is NULL");
     EA_HIP(hipStreamSynchronize(s->stream));
+    return EA_OK;
+}
+
+// Autotuner of the plain form's packing: for every valid words-per-row of
+// side L, a run (p = 0.5, T = 0.8) is timed over a burst of captured sweeps
+// after a warm-up; candidates whose final spins differ from the first
+// (coarsest) candidate's are rejected, the fastest of the rest is kept for
+// the process and appended to the EA_TUNE_CACHE file if that is set.
+ea_status ea_tune_plain(int32_t L, int32_t force, int32_t *chosen_rw, ea_tune_choice *tried, int32_t max_tried,
+                        int32_t *n_tried)
+{
+    if (!chosen_rw) return fail(EA_ERR_ARG, "chosen_rw is NULL");
+    if (!valid_L(L)) return fail(EA_ERR_ARG, "L=%d must be a multiple of 8 in [8, %d]", L, kMaxL);
+    if (n_tried) *n_tried = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_plain_mu);
+        read_plain_tune_file();
+        auto it = g_plain_tuned.find(L);
+        if (it != g_plain_tuned.end() && !force) {
+            *chosen_rw = it->second;
+            return EA_OK;
+        }
+    }
+    const int R = L / 2;
+    const uint64_t N = (uint64_t)L * L * L;
+    uint64_t sweeps = (1ull << 26) / N;
+    sweeps = std::max<uint64_t>(64, std::min<uint64_t>(1024, sweeps)) / 64 * 64;
+    std::vector<int8_t> ref, cur(2 * (size_t)N);
+    int best = 0, n = 0;
+    double best_ms = 0.0;
+    for (int rw = 1; rw <= R / 4; ++rw) {
+        if (!rw_valid(R, rw)) continue;
+        ea_config c{};
+        c.L = L;
+        c.p = 0.5;
+        c.T = 0.8;
+        c.seed = 7;
+        c.words_per_row = rw;
+        ea_sim *sim = nullptr;
+        ea_status st = ea_create_ex(&c, &sim);
+        if (st != EA_OK) return st;
+        double ms = 0.0;
+        st = ea_sweep(sim, 64);
+        if (st == EA_OK) st = ea_sync(sim);
+        if (st == EA_OK) {
+            const auto t0 = std::chrono::steady_clock::now();
+            st = ea_sweep(sim, sweeps);
+            if (st == EA_OK) st = ea_sync(sim);
+            ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        }
+        for (int r = 0; st == EA_OK && r < 2; ++r) st = ea_get_spins(sim, r, cur.data() + (size_t)r * N);
+        ea_destroy(sim);
+        if (st != EA_OK) return st;
+        if (ref.empty()) ref = cur;
+        const bool ok = cur == ref;
+        if (tried && n < max_tried) {
+            tried[n].words_per_row = rw;
+            tried[n].threads = 2 * L * L * rw;
+            tried[n].select = 1;
+            tried[n].ms = ms;
+            tried[n].parity_ok = ok ? 1 : 0;
+        }
+        ++n;
+        if (ok && (best == 0 || ms < best_ms)) {
+            best = rw;
+            best_ms = ms;
+        }
+    }
+    if (n_tried) *n_tried = n;
+    *chosen_rw = best;
+    std::lock_guard<std::mutex> lk(g_plain_mu);
+    g_plain_tuned[L] = best;
+    const char *path = std::getenv("EA_TUNE_CACHE");
+    if (path && *path) {
+        FILE *f = std::fopen(path, "a");
+        if (f) {
+            std::fprintf(f, "%s plain %d %d %.4f\n", device_arch_name().c_str(), L, best, best_ms);
+            std::fclose(f);
+        }
+    }
     return EA_OK;
 }
 

@@ -158,7 +158,7 @@ ea_status plan_streamed_job(const ea_job &in, int index, BatchJobHost &h)
                     ea::kBatchMaxL, kMaxL);
     ea_status st = plan_common(in, index, h);
     if (st != EA_OK) return st;
-    const Layout lay = make_layout(in.L, in.n_tw);
+    const Layout lay = make_layout(in.L, in.n_tw, plain_rw(in.L));
     h.RW = lay.RW;
     h.W = lay.W;
     h.POS = in.L * in.L * h.RW;
@@ -275,9 +275,7 @@ ea_status read_job_spins(const BatchJobHost &h, int32_t r, int8_t *pm1, hipStrea
     EA_HIP(hipMemcpyAsync(words.data(), h.base + h.off_spins + 4 * (size_t)r * 2 * h.POS, 4 * words.size(),
                           hipMemcpyDeviceToHost, stream));
     EA_HIP(hipStreamSynchronize(stream));
-    Layout y = make_layout(h.job.L, 0);
-    y.RW = h.RW;
-    y.W = h.W;
+    Layout y = make_layout(h.job.L, 0, h.RW);
     const int64_t N = (int64_t)h.job.L * h.job.L * h.job.L;
     for (int64_t i = 0; i < N; ++i) {
         SiteAddr a = address_of(y, i);
@@ -480,6 +478,7 @@ std::string device_arch()
     return colon == std::string::npos ? a : a.substr(0, colon);
 }
 
+// Lines "<arch> batch <L> <rw> <nt> <sel> <ms>" of the tuning cache.
 void read_tune_file()
 {
     if (g_tune_file_read) return;
@@ -489,14 +488,16 @@ void read_tune_file()
     FILE *f = std::fopen(path, "r");
     if (!f) return;
     const std::string arch = device_arch();
-    char a[64];
+    char line[256], a[64], tag[16];
     int L, rw, nt, sel;
-    while (std::fscanf(f, "%63s %d %d %d %d%*[^\n]", a, &L, &rw, &nt, &sel) == 5) {
+    while (std::fgets(line, sizeof line, f)) {
+        if (std::sscanf(line, "%63s %15s %d %d %d %d", a, tag, &L, &rw, &nt, &sel) != 6) continue;
+        if (arch != a || std::string(tag) != "batch") continue;
         TuneCfg c;
         c.rw = rw;
         c.nt = nt;
         c.sel = sel;
-        if (arch == a && batch_L_ok(L) && cfg_valid(L, c)) g_tuned[L] = c;
+        if (batch_L_ok(L) && cfg_valid(L, c)) g_tuned[L] = c;
     }
     std::fclose(f);
 }
@@ -507,7 +508,7 @@ void append_tune_file(int L, const TuneCfg &c, double ms)
     if (!path || !*path) return;
     FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%s %d %d %d %d %.4f\n", device_arch().c_str(), L, c.rw, c.nt, c.sel, ms);
+    std::fprintf(f, "%s batch %d %d %d %d %.4f\n", device_arch().c_str(), L, c.rw, c.nt, c.sel, ms);
     std::fclose(f);
 }
 

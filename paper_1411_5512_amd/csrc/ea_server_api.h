@@ -226,6 +226,7 @@ ea_status server_epoch(ea_server *s, int32_t *progressed)
                 c.stream = s->stream_big;
                 c.dev_buf = j->h.base;
                 c.dev_buf_bytes = j->h.bytes;
+                c.words_per_row = j->h.RW;  // the packing its footprint was planned with
                 st = ea_create_ex(&c, &j->sim);
                 j->results.assign((size_t)j->h.job.n_meas * (size_t)j->h.obs_stride, 0ull);
             } else {

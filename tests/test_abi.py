@@ -47,11 +47,18 @@ def test_thresholds_match_oracle(ealib, oracle_mod):
 
 def test_footprint_and_bad_arguments(ealib):
     import paper_1411_5512_amd as ea
-    # bit-packed: 2 replicas x N bits of spins + 3N bits of couplings (plus padding)
-    for L in (16, 64, 128):
-        fp = ea.footprint(L)
-        assert 5 * L ** 3 // 8 <= fp < 5 * L ** 3 // 8 + 4096 + 8 * 2000
-    assert ea.footprint(64, 3) - ea.footprint(64, 0) >= 3 * 2 * 64 ** 3 // 8
+    # densest packing (32 sites per word where the row allows): 2 replicas x N
+    # bits of spins + 3N bits of couplings (plus padding); W sites per 32-bit
+    # word cost 32 / W times that
+    for L, rw, W in ((16, 1, 8), (64, 1, 32), (128, 2, 32), (64, 8, 4), (96, 4, 12)):
+        fp = ea.footprint(L, words_per_row=rw)
+        dense = 5 * L ** 3 // 8 * 32 // W
+        assert dense <= fp < dense + 4096 + 8 * 2000, (L, rw)
+        assert ea.footprint(L) >= ea.footprint(L, words_per_row={16: 1, 64: 1, 128: 2, 96: 2}[L])
+    assert ea.footprint(64, 3, words_per_row=1) - ea.footprint(64, 0, words_per_row=1) >= 3 * 2 * 64 ** 3 // 8
+    for L, rw in ((64, 3), (64, 16), (96, 5), (16, 0 - 1)):  # not whole 4-site blocks, or W < 4
+        with pytest.raises(ea.EAError):
+            ea.footprint(L, words_per_row=rw)
     for L in (0, 4, 12, 260, 264, -8):
         with pytest.raises(ea.EAError):
             ea.footprint(L)

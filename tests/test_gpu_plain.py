@@ -174,3 +174,33 @@ def test_errors_on_gpu(ea_gpu):
     assert g.time == (1 << 32) - 1
     with pytest.raises(ea_gpu.EAError):
         g.set_spins(0, np.zeros(16 ** 3, dtype=np.int8))
+
+
+@pytest.mark.parametrize("L,rw", [(24, 1), (24, 3), (64, 1), (64, 2), (64, 4), (64, 8),
+                                  (96, 2), (96, 3), (96, 6), (96, 12), (128, 4), (128, 16)])
+def test_packings_match_oracle(ea_gpu, oracle_mod, L, rw):
+    """Every bit packing of the plain form (W = L/(2 rw) sites per word)
+    gives the oracle's trajectory and observables."""
+    _say(f"packing L={L} rw={rw}")
+    g = ea_gpu.Sim(L, 0.4, 0.8, seed=8, sample=2, n_slots=1, words_per_row=rw)
+    assert g.words_per_row == rw
+    o = oracle_mod.Sim(L, 0.4, 0.8, seed=8, sample=2, n_slots=1)
+    g.snapshot(0)
+    o.snapshot(0)
+    g.sweep(3)
+    o.sweep(3)
+    _compare_state(g, o, f"L={L} rw={rw}")
+    _compare_obs(g.measure(), o.measure(), f"L={L} rw={rw}")
+
+
+def test_tune_plain(ea_gpu):
+    for L in (32, 64, 96):
+        r = ea_gpu.tune_plain(L, force=True)
+        _say(f"tune_plain L={L}: {r}")
+        assert r["tried"] and all(c["parity_ok"] for c in r["tried"])
+        assert r["words_per_row"] in [c["words_per_row"] for c in r["tried"]]
+        assert ea_gpu.tune_plain(L)["tried"] == []  # cached
+        g = ea_gpu.Sim(L, 0.5, 0.8, seed=1)
+        assert g.words_per_row == r["words_per_row"]
+    with pytest.raises(ea_gpu.EAError):
+        ea_gpu.tune_plain(12)
