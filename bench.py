@@ -41,6 +41,52 @@ METRIC = "ps per spin flip (batched vs plain, 1 MI355X, bit-exact); HBM/VALU % o
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 ALG_OPS_PER_FLIP = 40 / 4 + 1
 
+# HBM bytes per launch of the batched kernel on this workload, measured with
+# rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by a device-to-device copy of
+# known size) and recorded with a hash of the kernel sources they were taken
+# on; reported only while the sources still hash the same.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batch_kernel_mixed256_traffic.txt")
+KERNEL_SOURCES = ("ea_device.h", "ea_kernels.h", "ea_batch_kernels.h", "ea_batch_api.h")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        h.update(name.encode() + b"\0")
+        with open(os.path.join(ROOT, "paper_1411_5512_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """(bytes per launch, provenance) if the recorded counters match the
+    current kernel sources and workload, else (None, reason)."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            kv = dict(line.split(None, 1) for line in f if line.strip() and not line.startswith("#"))
+    except OSError:
+        return None, "no counter record"
+    kv = {k: v.strip() for k, v in kv.items()}
+    if kv.get("source_sha256") != kernel_source_hash():
+        return None, "kernel changed since the counters were taken"
+    return int(kv["fetch_bytes"]) + int(kv["write_bytes"]), kv.get("workload", "")
+
+
+def algorithmic_bytes(jobs) -> int:
+    """State traffic the batched form cannot avoid, packed bits: per replica
+    the spins and couplings loaded once and the spins stored once; per
+    snapshot the replica written; per measurement each replica published and
+    read back for the pair observables, and each taken snapshot read."""
+    total = 0
+    for j in jobs:
+        rep = j.L ** 3 // 8  # bytes of one replica's spins
+        total += 2 * (rep + 3 * rep + rep) + 2 * rep * len(j.tw)
+        for t in j.meas_t:
+            taken = sum(1 for w in j.tw if w <= t)
+            total += 2 * (rep + rep + taken * rep)
+    return total
+
 
 def log(msg: str):
     print(msg, file=sys.stderr, flush=True)
@@ -266,6 +312,8 @@ def main():
                 assert list(o.autocorr[:, slot]) == [job.L ** 3] * 2, (j, k)
     n_results = sum(len(j.meas_t) for j in jobs)
 
+    traffic, traffic_src = measured_traffic()
+    alg_bytes = algorithmic_bytes(jobs)
     out = {
         "metric": METRIC,
         "value": round(ps_per_flip, 4),
@@ -299,9 +347,13 @@ def main():
             "peak": round(VALU_PEAK_TOPS, 2),
             "unit": "Tops/s (32-bit lane-ops)",
             "frac": round(achieved / VALU_PEAK_TOPS, 4),
-            "traffic": None,
+            "traffic": traffic,
             "launch_ms": round(launch_s * 1e3, 3),
             "alg_ops_per_flip": ALG_OPS_PER_FLIP,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "traffic_source": traffic_src,
+            "alg_bytes_per_launch": alg_bytes,
+            "hbm_frac": round(((traffic or alg_bytes) / launch_s / 1e9) / 8000.0, 5),
             "flips_per_launch": flips_per_step,
         },
     }
