@@ -1,0 +1,84 @@
+"""Host-side logic that needs no GPU: run descriptions, schedules, the
+benchmark's bookkeeping (algorithmic bytes, the counter record's source
+check) and its command-line contract."""
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_log_schedule():
+    from paper_1411_5512_amd.workloads import log_schedule
+    s = log_schedule(100_000, 20)
+    assert s[0] == 1 and s[-1] == 100_000
+    assert s == sorted(set(s)) and len(s) == 20
+    # rounding makes the first steps uneven; from t ~ 100 on they are 5/19 decades
+    ratios = np.diff(np.log10(s))[8:]
+    assert np.allclose(ratios, 5 / 19, atol=0.01)
+    assert log_schedule(10, 20) == list(range(1, 11))  # de-duplicated
+    assert log_schedule(0, 5) == [] and log_schedule(7, 1) == [7]
+
+
+def test_batch_jobs_shape_and_determinism():
+    from paper_1411_5512_amd import workloads as wl
+    a, b = wl.batch_jobs(256, 100_000), wl.batch_jobs(256, 100_000)
+    assert [(j.L, j.p, j.T, j.seed) for j in a] == [(j.L, j.p, j.T, j.seed) for j in b]
+    assert {j.L for j in a} == {24, 32, 48, 64}
+    assert {j.p for j in a} == {0.5, 0.3, 0.2} and {j.T for j in a} == {0.6, 0.8, 1.0}
+    assert [j.seed for j in a] == list(range(256))
+    for j in a:
+        assert j.tw == [100, 1000, 10_000]
+        assert set(j.tw) <= set(j.meas_t) and j.meas_t[-1] == 100_000
+        assert j.flips == 2 * j.L ** 3 * j.n_sweeps
+    # events: snapshot slots and measurements in time order, each time once
+    times = [t for t, _, _ in a[0].events()]
+    assert times == sorted(set(a[0].meas_t) | set(a[0].tw))
+
+
+def test_serve_jobs_stream():
+    from paper_1411_5512_amd import workloads as wl
+    stream = wl.serve_jobs(n_jobs=500, sweep_range=(1_000, 1_000_000))
+    arrivals = [a for a, _ in stream]
+    assert all(x < y for x, y in zip(arrivals, arrivals[1:]))
+    assert 0.8 < arrivals[-1] / 500 < 1.2  # mean gap 1
+    sizes = {j.L for _, j in stream}
+    assert sizes == {16, 24, 32, 48, 64, 96, 128}
+    for _, j in stream:
+        assert 0.1 <= j.p <= 0.5 and 0.5 <= j.T <= 1.2
+        assert 1_000 <= j.n_sweeps <= 1_000_000 and j.meas_t[-1] == j.n_sweeps
+
+
+def test_algorithmic_bytes_small_case():
+    import bench
+    from paper_1411_5512_amd.workloads import Job
+    j = Job(16, 0.5, 0.8, seed=1, n_sweeps=100, meas_t=[10, 100], tw=[10])
+    rep = 16 ** 3 // 8
+    want = 2 * (rep + 3 * rep + rep) + 2 * rep * 1   # load, store, one snapshot
+    want += 2 * (rep + rep + 1 * rep) * 2            # two measurements, one snapshot taken by each
+    assert bench.algorithmic_bytes([j]) == want
+
+
+def test_traffic_record_tied_to_sources(tmp_path, monkeypatch):
+    import bench
+    rec = tmp_path / "traffic.txt"
+    rec.write_text(f"# comment\nsource_sha256 {bench.kernel_source_hash()}\nfetch_bytes 10\nwrite_bytes 32\n"
+                   "workload w\n")
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(rec))
+    assert bench.measured_traffic() == (42, "w")
+    rec.write_text("source_sha256 0000\nfetch_bytes 10\nwrite_bytes 32\n")
+    t, why = bench.measured_traffic()
+    assert t is None and "changed" in why
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.txt"))
+    assert bench.measured_traffic()[0] is None
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0 and "one GPU" in r.stderr
