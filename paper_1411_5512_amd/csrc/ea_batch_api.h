@@ -35,6 +35,7 @@ bool cfg_valid(int L, const TuneCfg &c)
     const int R = L / 2, rw0 = ea::words_per_row_c(R), rw1 = ea::finer_words_per_row_c(R, rw0);
     if (c.rw != rw0 && (rw1 == 0 || c.rw != rw1)) return false;
     if (c.nt < 64 || c.nt > ea::kBatchThreads || c.nt % 64) return false;
+    if (c.nt < L * c.rw) return false;  // every thread owns at least one column of a z-plane
     return c.sel == ea::SEL_LDS || c.sel == ea::SEL_REG;
 }
 
@@ -529,6 +530,7 @@ std::vector<TuneCfg> tune_candidates(int L, size_t lds_limit)
                 c.rw = rw;
                 c.nt = std::min(nt, round_up64(words));
                 c.sel = sel;
+                if (!cfg_valid(L, c)) continue;
                 bool dup = false;
                 for (const TuneCfg &o : out) dup = dup || (o.rw == c.rw && o.nt == c.nt && o.sel == c.sel);
                 if (!dup) out.push_back(c);

@@ -98,7 +98,7 @@ __device__ __forceinline__ int batch_c4_base(int n_tw) { return M_AUTO + 2 * n_t
 // [direction][colour][POS] couplings and one word for a broadcast flag.
 // Declared at file scope so that every access is a plain ds_read/ds_write.
 extern __shared__ uint32_t batch_lds[];
-__shared__ uint32_t batch_select_tables[kSelectTableWords];
+__shared__ __align__(16) uint32_t batch_select_tables[kSelectTableWords];
 
 __device__ __forceinline__ uint32_t *batch_tables() { return batch_select_tables; }
 
@@ -131,33 +131,42 @@ __device__ __forceinline__ void batch_half_step(const BatchJobDev &J, int r, int
     // sweep loop would keep some thirty address registers live and spill.
     int tid = (int)threadIdx.x;
     asm volatile("" : "+v"(tid));
-    // one word at a time: a word already carries W/4 independent Philox
-    // blocks of instruction-level parallelism, and unrolling further spills
+    // Each thread keeps one (y, w) column of the z-planes and walks z in
+    // steps of nt / PLANE (threads past the last whole column stay idle), so
+    // the y and x neighbour offsets are computed once per half-step.  One
+    // word at a time: a word already carries W/4 independent Philox blocks of
+    // instruction-level parallelism, and unrolling further spills.
+    constexpr unsigned PLANE = (unsigned)(L * RW);
+    const unsigned q = (unsigned)tid % PLANE;
+    const unsigned w = q % RW;
+    const unsigned y = q / RW;
+    const unsigned dz = (unsigned)J.nt / PLANE;
+    const unsigned z_first = (unsigned)tid < dz * PLANE ? (unsigned)tid / PLANE : (unsigned)L;
+    const unsigned qm = q - w + (w == 0 ? RW - 1 : w - 1);  // word w - 1 of the row (cyclic)
+    const unsigned qp = q - w + (w == RW - 1 ? 0 : w + 1);  // word w + 1
+    const unsigned qym = (y == 0 ? L - 1 : y - 1) * RW + w;
+    const unsigned qyp = (y == L - 1 ? 0 : y + 1) * RW + w;
+    const unsigned par0 = (y + (unsigned)c) & 1u;
+    const unsigned quad_col = (y * S::R + w * W) >> 2;  // y R + w W is a multiple of 4
 #pragma unroll 1
-    for (int p = tid; p < S::POS; p += J.nt) {
-        const unsigned row = (unsigned)p / RW;
-        const unsigned w = (unsigned)p - row * RW;
-        const unsigned y = row % L;
-        const unsigned z = row / L;
-        const int par = (int)((y + z + (unsigned)c) & 1u);
-        const unsigned wm = w == 0 ? RW - 1 : w - 1;
-        const unsigned wp = w == RW - 1 ? 0 : w + 1;
-        const unsigned ym = (y == 0 ? L - 1 : y - 1) + L * z, yp = (y == L - 1 ? 0 : y + 1) + L * z;
-        const unsigned zm = y + L * (z == 0 ? L - 1 : z - 1), zp = y + L * (z == L - 1 ? 0 : z + 1);
-        const unsigned base = row * RW;
+    for (unsigned z = z_first; z < (unsigned)L; z += dz) {
+        const unsigned base = z * PLANE;
+        const unsigned p = base + q;
+        const int par = (int)((par0 ^ z) & 1u);
+        const unsigned zm = (z == 0 ? L - 1 : z - 1) * PLANE + q, zp = (z == L - 1 ? 0 : z + 1) * PLANE + q;
         const uint32_t S0 = own[p];
-        const uint32_t O = oth[base + w], Om = oth[base + wm], Op = oth[base + wp];
-        const uint32_t Xo = bx_oth[base + w], Xom = bx_oth[base + wm];
+        const uint32_t O = oth[p], Om = oth[base + qm], Op = oth[base + qp];
+        const uint32_t Xo = bx_oth[p], Xom = bx_oth[base + qm];
         const uint32_t xp = par ? take_plus1<W>(O, Op) : O;
         const uint32_t xm = par ? (O ^ Xo) : take_minus1<W>(O ^ Xo, Om ^ Xom);
         const uint32_t a1 = S0 ^ xp ^ bx_own[p];
         const uint32_t a2 = S0 ^ xm;
-        const uint32_t a3 = xor3(S0, oth[yp * RW + w], by_own[p]);
-        const uint32_t a4 = xor3(S0, oth[ym * RW + w], by_oth[ym * RW + w]);
-        const uint32_t a5 = xor3(S0, oth[zp * RW + w], bz_own[p]);
-        const uint32_t a6 = xor3(S0, oth[zm * RW + w], bz_oth[zm * RW + w]);
+        const uint32_t a3 = xor3(S0, oth[base + qyp], by_own[p]);
+        const uint32_t a4 = xor3(S0, oth[base + qym], by_oth[base + qym]);
+        const uint32_t a5 = xor3(S0, oth[zp], bz_own[p]);
+        const uint32_t a6 = xor3(S0, oth[zm], bz_oth[zm]);
         const Decision d = classify(a1, a2, a3, a4, a5, a6);
-        const uint32_t quad0 = (uint32_t)((row * S::R + w * W) >> 2);
+        const uint32_t quad0 = quad_col + ((z * (unsigned)(L * S::R)) >> 2);  // (row R + w W) / 4, row = y + L z
         uint32_t flips;
         if constexpr (SEL == SEL_LDS)
             flips = flip_mask_lds<W>(d, t, quad0, c2, J.sample, J.k0, J.k1, batch_tables());

@@ -206,13 +206,20 @@ __device__ __forceinline__ uint32_t flip_mask(const Decision &d, uint32_t c0, ui
 }
 
 // ---------------------------------------------------------------------------
-// Threshold select through an LDS table.  Per word, the two class masks are
-// turned into one nibble per site, 8 (any) + 4 (odd) = the byte offset of the
-// site's threshold in a 4-entry table {thr3, thr2, thr1, 0}; two 256-entry
-// tables spread a byte of each mask into nibbles.  Per site this costs one
-// bit-field extract and one LDS read instead of two extracts and two selects.
+// Threshold select through LDS tables, four sites per read.  A 4-site block
+// q = 0..3 has class bits any_q (n >= 2) and odd_q (n odd); the 8-bit index
+// any_nibble | odd_nibble << 4 selects a 16-byte entry holding the four
+// thresholds (any -> thr1, else odd -> thr2, else thr3; a site with n >= 3
+// is covered by the "always" mask, its entry is 0).  Two 256-entry spread
+// tables turn a byte of each class mask (two blocks) into both blocks' entry
+// byte offsets, in the low and high 16 bits of one word: per 8 sites two
+// table reads, an OR, two extracts and two 16-byte reads.
+//
+// Layout (words): [0, 1024) the quad table, [1024, 1280) the "any" spread
+// table, [1280, 1536) the "odd" spread table.
 
-constexpr int kSelectTableWords = 4 + 2 * 256;
+constexpr int kSelectQuadWords = 4 * 256;
+constexpr int kSelectTableWords = kSelectQuadWords + 2 * 256;
 
 // Fill the tables (any thread count; caller synchronises before use).
 __device__ __forceinline__ void fill_select_tables(uint32_t *tab, uint32_t thr1, uint32_t thr2, uint32_t thr3,
@@ -220,13 +227,14 @@ __device__ __forceinline__ void fill_select_tables(uint32_t *tab, uint32_t thr1,
 {
     for (int i = tid; i < kSelectTableWords; i += nthreads) {
         uint32_t v;
-        if (i < 4) {
-            v = i == 0 ? thr3 : (i == 1 ? thr2 : (i == 2 ? thr1 : 0u));
+        if (i < kSelectQuadWords) {
+            const int idx = i >> 2, q = i & 3;
+            const int any = (idx >> q) & 1, odd = (idx >> (4 + q)) & 1;
+            v = any ? (odd ? 0u : thr1) : (odd ? thr2 : thr3);
         } else {
-            const int x = (i - 4) & 255;
-            const int shift = i < 4 + 256 ? 3 : 2;
-            v = 0;
-            for (int k = 0; k < 8; ++k) v |= (uint32_t)((x >> k) & 1) << (4 * k + shift);
+            const int b = (i - kSelectQuadWords) & 255;
+            const int shift = i < kSelectQuadWords + 256 ? 4 : 8;  // any: bits 4..7, odd: bits 8..11
+            v = ((uint32_t)(b & 15) << shift) | ((uint32_t)(b >> 4) << (16 + shift));
         }
         tab[i] = v;
     }
@@ -247,24 +255,33 @@ __device__ __forceinline__ uint32_t accept_blocks_lds(uint32_t accept, const uin
 }
 
 // Flip mask of one packed word of W sites, thresholds from the LDS tables
-// (tab = kSelectTableWords words filled by fill_select_tables).  All W
-// thresholds are read before the random words are computed, so the LDS
-// latency overlaps the Philox rounds.
+// (tab = kSelectTableWords words filled by fill_select_tables, 16-byte
+// aligned).  All W thresholds are read before the random words are
+// computed, so the LDS latency overlaps the Philox rounds.
 template <int W>
 __device__ __forceinline__ uint32_t flip_mask_lds(const Decision &d, uint32_t c0, uint32_t quad0, uint32_t c2,
                                                   uint32_t c3, uint32_t k0, uint32_t k1, const uint32_t *tab)
 {
-    const uint32_t *spread_any = tab + 4;
-    const uint32_t *spread_odd = tab + 4 + 256;
-    uint32_t code[(W + 7) / 8];
-#pragma unroll
-    for (int j = 0; j < (W + 7) / 8; ++j)
-        code[j] = spread_any[__builtin_amdgcn_ubfe(d.any, 8 * j, 8)] |
-                  spread_odd[__builtin_amdgcn_ubfe(d.odd, 8 * j, 8)];
+    const uint32_t *spread_any = tab + kSelectQuadWords;
+    const uint32_t *spread_odd = tab + kSelectQuadWords + 256;
     uint32_t thr[W];
 #pragma unroll
-    for (int i = 0; i < W; ++i)
-        thr[i] = *(const uint32_t *)((const char *)tab + __builtin_amdgcn_ubfe(code[i >> 3], 4 * (i & 7), 4));
+    for (int j = 0; j < (W + 7) / 8; ++j) {
+        const uint32_t off = spread_any[__builtin_amdgcn_ubfe(d.any, 8 * j, 8)] |
+                             spread_odd[__builtin_amdgcn_ubfe(d.odd, 8 * j, 8)];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int g = 2 * j + h;  // 4-site block
+            if (g < W / 4) {
+                const uint32_t byte_off = h ? off >> 16 : off & 0xffffu;
+                const uint4 q = *(const uint4 *)((const char *)tab + byte_off);
+                thr[4 * g + 0] = q.x;
+                thr[4 * g + 1] = q.y;
+                thr[4 * g + 2] = q.z;
+                thr[4 * g + 3] = q.w;
+            }
+        }
+    }
     return d.always | accept_blocks_lds<W / 4 - 1, W>(0u, thr, c0, quad0, c2, c3, k0, k1);
 }
 
