@@ -15,11 +15,13 @@
 // the dynamics never depend on how the sweeps are split or what else runs.
 //
 // Lattices too large for one workgroup's LDS (L > 64) are "streamed" jobs:
-// each is a plain-form simulation placed in its pool region, advanced during
-// the epoch through the HBM-streaming kernels on a second stream, so that its
-// half-steps run on the device alongside the batched launch.  A streamed
-// job's span is sized by time, so that the streamed work of an epoch takes
-// about as long as the previous epoch's batched launch.
+// each is a plain-form simulation placed in its pool region with a stream of
+// its own, advanced during the epoch through the HBM-streaming kernels by up
+// to kStreamWorkers host threads at once, so that the half-steps of several
+// such jobs and the batched launch run on the device together.  A streamed
+// job's span is sized by time (its own measured seconds per sweep), so that
+// the streamed work of an epoch takes about as long as the previous epoch's
+// batched launch.
 #pragma once
 
 #include <algorithm>
@@ -35,6 +37,8 @@
 namespace {
 
 using steady = std::chrono::steady_clock;
+
+constexpr int kStreamWorkers = 4;  // host threads that drive streamed jobs in an epoch
 
 // First-fit allocator over one device buffer (offsets, 256-byte granules).
 struct DevicePool {
@@ -93,9 +97,10 @@ struct ServerJob {
     size_t pool_off = 0;
     steady::time_point t_submit, t_done;
     std::vector<unsigned long long> results;  // [n_meas][obs_stride] after completion
-    bool streamed = false;                     // L > 64: plain-form kernels on the second stream
+    bool streamed = false;                     // L > 64: plain-form kernels on a stream of its own
     ea_sim *sim = nullptr;                     // its simulation, in the pool region
     int next_meas = 0, next_tw = 0;            // schedule positions of a streamed job
+    double sweep_s = 0.0;                      // measured seconds per sweep of a streamed job
 };
 
 ea_status plan_server_job(const ea_job &in, ServerJob &j)
@@ -112,9 +117,8 @@ struct ea_server {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    hipStream_t stream_big = nullptr;  // streamed jobs (always the server's own)
-    double last_batch_s = 0.0;         // wall time of the last epoch's batched launch
-    double streamed_site_s = 0.0;      // measured seconds per site-sweep of streamed work
+    hipEvent_t ev_batch[2] = {nullptr, nullptr};  // around each batched launch
+    double last_batch_s = 0.0;                    // duration of the last batched launch
     char *pool_buf = nullptr;
     DevicePool pool;
     ea::BatchJobDev *d_jobs = nullptr;
@@ -223,7 +227,7 @@ ea_status server_epoch(ea_server *s, int32_t *progressed)
                 c.seed = j->h.job.seed;
                 c.sample = j->h.job.sample;
                 c.n_tw_slots = j->h.job.n_tw;
-                c.stream = s->stream_big;
+                c.stream = nullptr;  // a stream of its own
                 c.dev_buf = j->h.base;
                 c.dev_buf_bytes = j->h.bytes;
                 c.words_per_row = j->h.RW;  // the packing its footprint was planned with
@@ -273,36 +277,58 @@ ea_status server_epoch(ea_server *s, int32_t *progressed)
                               s->stream));
         EA_HIP(hipMemcpyAsync(s->d_units, units.data(), sizeof(ea::BatchUnit) * units.size(),
                               hipMemcpyHostToDevice, s->stream));
+        EA_HIP(hipEventRecord(s->ev_batch[0], s->stream));
         hipLaunchKernelGGL(ea::batch_kernel, dim3((unsigned)units.size()), dim3(ea::kBatchThreads), lds, s->stream,
                            s->d_jobs, s->d_units);
         EA_HIP(hipGetLastError());
+        EA_HIP(hipEventRecord(s->ev_batch[1], s->stream));
     }
-    // streamed jobs, on the second stream while the batched launch runs; each
-    // gets an equal share of the expected epoch time
-    double streamed_sites = 0.0;
+    // streamed jobs, each on its own stream, while the batched launch runs:
+    // kStreamWorkers host threads share them out, each thread's jobs splitting
+    // the expected epoch time
     if (!streamed.empty()) {
-        const double target = std::max(s->last_batch_s, 2e-3) / (double)streamed.size();
-        for (size_t i = 0; i < run.size(); ++i) {
-            ServerJob *j = run[i];
-            if (!j->streamed) continue;
-            const double N = (double)j->h.job.L * j->h.job.L * j->h.job.L;
-            const double per_sweep = s->streamed_site_s > 0.0 ? s->streamed_site_s * N : 2e-5;
-            const uint64_t want = (uint64_t)std::max(1.0, std::floor(target / per_sweep));
-            span[i] = std::min<uint64_t>(want, j->h.job.n_sweeps - j->h.t_host);
-            ea_status st = server_advance_streamed(*j, j->h.t_host + span[i]);
-            if (st != EA_OK) return st;
-            streamed_sites += N * (double)span[i];
-        }
+        const double target = std::max(s->last_batch_s, 2e-3);
+        const int n_workers = std::min<int>(kStreamWorkers, (int)streamed.size());
+        std::vector<std::vector<size_t>> lists((size_t)n_workers);
+        int n = 0;
+        for (size_t i = 0; i < run.size(); ++i)
+            if (run[i]->streamed) lists[(size_t)(n++ % n_workers)].push_back(i);
+        std::vector<std::string> errs((size_t)n_workers);
+        auto advance = [&](int k) {
+            (void)hipSetDevice(s->device);
+            const double budget = target / (double)lists[(size_t)k].size();
+            for (size_t i : lists[(size_t)k]) {
+                ServerJob *j = run[i];
+                const double per_sweep = j->sweep_s > 0.0 ? j->sweep_s : 2e-5;
+                const uint64_t want = (uint64_t)std::max(1.0, std::floor(budget / per_sweep));
+                span[i] = std::min<uint64_t>(want, j->h.job.n_sweeps - j->h.t_host);
+                const auto a = steady::now();
+                ea_status st = server_advance_streamed(*j, j->h.t_host + span[i]);
+                if (st == EA_OK) st = ea_sync(j->sim);
+                if (st != EA_OK) {
+                    errs[(size_t)k] = ea_last_error();
+                    return;
+                }
+                if (span[i] > 0) {
+                    const double per = std::chrono::duration<double>(steady::now() - a).count() / (double)span[i];
+                    j->sweep_s = j->sweep_s > 0.0 ? 0.5 * (j->sweep_s + per) : per;
+                }
+            }
+        };
+        std::vector<std::thread> helpers;
+        for (int k = 1; k < n_workers; ++k) helpers.emplace_back(advance, k);
+        advance(0);
+        for (auto &h : helpers) h.join();
+        for (const std::string &e : errs)
+            if (!e.empty()) return fail(EA_ERR_DEVICE, "streamed job: %s", e.c_str());
     }
-    if (!streamed.empty()) EA_HIP(hipStreamSynchronize(s->stream_big));
-    const auto t_streamed = steady::now();
     EA_HIP(hipStreamSynchronize(s->stream));
-    const auto t1 = steady::now();
-    if (!batched.empty()) s->last_batch_s = std::chrono::duration<double>(t1 - t0).count();
-    if (streamed_sites > 0.0) {
-        const double per_site = std::chrono::duration<double>(t_streamed - t0).count() / streamed_sites;
-        s->streamed_site_s = s->streamed_site_s > 0.0 ? 0.5 * (s->streamed_site_s + per_site) : per_site;
+    if (!batched.empty()) {
+        float ms = 0.0f;
+        EA_HIP(hipEventElapsedTime(&ms, s->ev_batch[0], s->ev_batch[1]));
+        s->last_batch_s = 1e-3 * (double)ms;
     }
+    const auto t1 = steady::now();
 
     // bookkeeping; finished jobs hand their results over and free their memory
     double epoch_flips = 0.0;
@@ -419,10 +445,12 @@ ea_status ea_server_create(const ea_server_opts *opts, ea_server **out)
         }
         s->own_stream = true;
     }
-    e = hipStreamCreateWithFlags(&s->stream_big, hipStreamNonBlocking);
-    if (e != hipSuccess) {
-        ea_server_destroy(s);
-        return fail(EA_ERR_DEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+    for (int k = 0; k < 2; ++k) {
+        e = hipEventCreate(&s->ev_batch[k]);
+        if (e != hipSuccess) {
+            ea_server_destroy(s);
+            return fail(EA_ERR_DEVICE, "hipEventCreate: %s", hipGetErrorString(e));
+        }
     }
     const size_t table_bytes = align256(sizeof(ea::BatchJobDev) * (size_t)opts->max_resident) +
                                align256(sizeof(ea::BatchUnit) * 2 * (size_t)opts->max_resident);
@@ -451,10 +479,10 @@ void ea_server_destroy(ea_server *s)
     for (auto &j : s->resident)
         if (j->sim) ea_destroy(j->sim);
     if (s->stream) (void)hipStreamSynchronize(s->stream);
-    if (s->stream_big) (void)hipStreamSynchronize(s->stream_big);
     if (s->pool_buf) (void)hipFree(s->pool_buf);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
-    if (s->stream_big) (void)hipStreamDestroy(s->stream_big);
+    for (hipEvent_t ev : s->ev_batch)
+        if (ev) (void)hipEventDestroy(ev);
     delete s;
 }
 
