@@ -204,3 +204,24 @@ def test_tune_plain(ea_gpu):
         assert g.words_per_row == r["words_per_row"]
     with pytest.raises(ea_gpu.EAError):
         ea_gpu.tune_plain(12)
+
+
+@pytest.mark.parametrize("p", [0.5, 0.15])
+def test_crossover_windows_L128(ea_gpu, oracle_mod, p):
+    """L = 128, T = 0.7 across the crossover (nested couplings, seed 1): the
+    oracle reproduces the GPU from t = 0 and from the GPU state after 3000
+    sweeps, magnetisation included."""
+    from paper_1411_5512_amd import workloads as wl
+    job = [j for j in wl.crossover_jobs(10_000) if j.p == p][0]
+    g = ea_gpu.Sim(job.L, job.p, job.T, seed=job.seed, sample=job.sample)
+    for t0, k in [(0, 2), (3000, 2)]:
+        g.sweep(t0 - g.time)
+        o = oracle_mod.Sim(job.L, job.p, job.T, seed=job.seed, sample=job.sample)
+        for r in (0, 1):
+            o.set_spins(r, g.spins(r))
+        o.set_time(t0)
+        g.sweep(k)
+        o.sweep(k)
+        _say(f"crossover L=128 p={p} window t0={t0}")
+        _compare_state(g, o, f"p={p} t0={t0}")
+        _compare_obs(g.measure(), o.measure(), f"p={p} t0={t0}")
