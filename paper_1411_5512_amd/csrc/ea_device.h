@@ -56,6 +56,41 @@ __device__ __forceinline__ Words4 philox10(uint32_t x0, uint32_t x1, uint32_t x2
     return r;
 }
 
+// Two blocks whose counters differ only in word 1, computed round by round
+// side by side: the two dependency chains interleave, so each round's
+// multiplies of one block issue while the other's are in flight.
+__device__ __forceinline__ void philox10_pair(uint32_t x0, uint32_t x1a, uint32_t x1b, uint32_t x2, uint32_t x3,
+                                              uint32_t k0, uint32_t k1, Words4 &a, Words4 &b)
+{
+    uint32_t a0 = x0, a1 = x1a, a2 = x2, a3 = x3;
+    uint32_t b0 = x0, b1 = x1b, b2 = x2, b3 = x3;
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t ma0 = (uint64_t)a0 * 0xD2511F53u, mb0 = (uint64_t)b0 * 0xD2511F53u;
+        const uint64_t ma2 = (uint64_t)a2 * 0xCD9E8D57u, mb2 = (uint64_t)b2 * 0xCD9E8D57u;
+        const uint32_t ya0 = xor3((uint32_t)(ma2 >> 32), a1, k0), yb0 = xor3((uint32_t)(mb2 >> 32), b1, k0);
+        const uint32_t ya2 = xor3((uint32_t)(ma0 >> 32), a3, k1), yb2 = xor3((uint32_t)(mb0 >> 32), b3, k1);
+        a1 = (uint32_t)ma2;
+        b1 = (uint32_t)mb2;
+        a3 = (uint32_t)ma0;
+        b3 = (uint32_t)mb0;
+        a0 = ya0;
+        b0 = yb0;
+        a2 = ya2;
+        b2 = yb2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    a.v[0] = a0;
+    a.v[1] = a1;
+    a.v[2] = a2;
+    a.v[3] = a3;
+    b.v[0] = b0;
+    b.v[1] = b1;
+    b.v[2] = b2;
+    b.v[3] = b3;
+}
+
 enum : uint32_t { TAG_METRO = 0u, TAG_BOND = 1u, TAG_INIT = 2u };
 
 __device__ __forceinline__ uint32_t counter_word2(uint32_t tag, uint32_t colour, uint32_t replica)
@@ -185,15 +220,28 @@ __device__ __forceinline__ uint32_t accept_blocks(uint32_t accept, const Decisio
                                                   uint32_t quad0, uint32_t c2, uint32_t c3, uint32_t k0,
                                                   uint32_t k1, uint32_t thr1, uint32_t thr2, uint32_t thr3)
 {
-    const Words4 u = philox10(c0, quad0 + (uint32_t)J, c2, c3, k0, k1);
-    accept = append_below4(accept, u.v[3], site_threshold<4 * J + 3>(d, thr1, thr2, thr3), u.v[2],
-                           site_threshold<4 * J + 2>(d, thr1, thr2, thr3), u.v[1],
-                           site_threshold<4 * J + 1>(d, thr1, thr2, thr3), u.v[0],
-                           site_threshold<4 * J + 0>(d, thr1, thr2, thr3));
-    if constexpr (J > 0)
-        return accept_blocks<J - 1>(accept, d, c0, quad0, c2, c3, k0, k1, thr1, thr2, thr3);
-    else
-        return accept;
+    if constexpr (J > 0) {
+        // blocks J and J - 1 side by side
+        Words4 u, v;
+        philox10_pair(c0, quad0 + (uint32_t)J, quad0 + (uint32_t)(J - 1), c2, c3, k0, k1, u, v);
+        accept = append_below4(accept, u.v[3], site_threshold<4 * J + 3>(d, thr1, thr2, thr3), u.v[2],
+                               site_threshold<4 * J + 2>(d, thr1, thr2, thr3), u.v[1],
+                               site_threshold<4 * J + 1>(d, thr1, thr2, thr3), u.v[0],
+                               site_threshold<4 * J + 0>(d, thr1, thr2, thr3));
+        accept = append_below4(accept, v.v[3], site_threshold<4 * J - 1>(d, thr1, thr2, thr3), v.v[2],
+                               site_threshold<4 * J - 2>(d, thr1, thr2, thr3), v.v[1],
+                               site_threshold<4 * J - 3>(d, thr1, thr2, thr3), v.v[0],
+                               site_threshold<4 * J - 4>(d, thr1, thr2, thr3));
+        if constexpr (J > 1)
+            return accept_blocks<J - 2>(accept, d, c0, quad0, c2, c3, k0, k1, thr1, thr2, thr3);
+        else
+            return accept;
+    } else {
+        const Words4 u = philox10(c0, quad0, c2, c3, k0, k1);
+        return append_below4(accept, u.v[3], site_threshold<3>(d, thr1, thr2, thr3), u.v[2],
+                             site_threshold<2>(d, thr1, thr2, thr3), u.v[1], site_threshold<1>(d, thr1, thr2, thr3),
+                             u.v[0], site_threshold<0>(d, thr1, thr2, thr3));
+    }
 }
 
 // Flip mask of one packed word of W sites (bits W..31 stay zero).
@@ -245,13 +293,22 @@ __device__ __forceinline__ uint32_t accept_blocks_lds(uint32_t accept, const uin
                                                       uint32_t quad0, uint32_t c2, uint32_t c3, uint32_t k0,
                                                       uint32_t k1)
 {
-    const Words4 u = philox10(c0, quad0 + (uint32_t)J, c2, c3, k0, k1);
-    accept = append_below4(accept, u.v[3], thr[4 * J + 3], u.v[2], thr[4 * J + 2], u.v[1], thr[4 * J + 1],
-                           u.v[0], thr[4 * J]);
-    if constexpr (J > 0)
-        return accept_blocks_lds<J - 1, W>(accept, thr, c0, quad0, c2, c3, k0, k1);
-    else
-        return accept;
+    if constexpr (J > 0) {
+        // blocks J and J - 1 side by side
+        Words4 u, v;
+        philox10_pair(c0, quad0 + (uint32_t)J, quad0 + (uint32_t)(J - 1), c2, c3, k0, k1, u, v);
+        accept = append_below4(accept, u.v[3], thr[4 * J + 3], u.v[2], thr[4 * J + 2], u.v[1], thr[4 * J + 1],
+                               u.v[0], thr[4 * J]);
+        accept = append_below4(accept, v.v[3], thr[4 * J - 1], v.v[2], thr[4 * J - 2], v.v[1], thr[4 * J - 3],
+                               v.v[0], thr[4 * J - 4]);
+        if constexpr (J > 1)
+            return accept_blocks_lds<J - 2, W>(accept, thr, c0, quad0, c2, c3, k0, k1);
+        else
+            return accept;
+    } else {
+        const Words4 u = philox10(c0, quad0, c2, c3, k0, k1);
+        return append_below4(accept, u.v[3], thr[3], u.v[2], thr[2], u.v[1], thr[1], u.v[0], thr[0]);
+    }
 }
 
 // Flip mask of one packed word of W sites, thresholds from the LDS tables
