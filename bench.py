@@ -109,7 +109,22 @@ def run_plain_job(sim, job):
     sim.sync()
 
 
-def cpu_baseline(job, sweeps: int):
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(job, sweeps: int, agg_procs: int, agg_sweeps: int):
+    """The oracle on the host: one thread on the first `sweeps` sweeps of the
+    job, then `agg_procs` independent processes (one sample each, seeds
+    1..agg_procs) running `agg_sweeps` sweeps at once for an all-core rate."""
+    import subprocess
     import oracle
     oracle.build()
     o = oracle.Sim(job.L, job.p, job.T, seed=job.seed, sample=job.sample)
@@ -117,9 +132,24 @@ def cpu_baseline(job, sweeps: int):
     o.sweep(sweeps)
     dt = time.perf_counter() - t0
     flips = sweeps * 2 * job.L ** 3
-    return {"value": round(dt / flips * 1e12, 1), "unit": "ps/flip", "cores": 1, "kind": "oracle",
-            "sample": f"plain run L={job.L} p={job.p} T={job.T} seed={job.seed}: its first {sweeps} sweeps "
-                      f"({flips} attempted flips, {dt:.1f} s, one thread)"}
+    out = {"value": round(dt / flips * 1e12, 1), "unit": "ps/flip", "cores": 1, "kind": "oracle",
+           "cpu": _cpu_model(),
+           "sample": f"plain run L={job.L} p={job.p} T={job.T} seed={job.seed}: its first {sweeps} sweeps "
+                     f"({flips} attempted flips, {dt:.1f} s, one thread)"}
+    if agg_procs > 0 and agg_sweeps > 0:
+        code = ("import sys, time; sys.path.insert(0, sys.argv[1]); import oracle; "
+                "o = oracle.Sim(int(sys.argv[2]), float(sys.argv[3]), float(sys.argv[4]), seed=int(sys.argv[5])); "
+                "t = time.perf_counter(); o.sweep(int(sys.argv[6])); print(time.perf_counter() - t)")
+        procs = [subprocess.Popen([sys.executable, "-c", code, ROOT, str(job.L), str(job.p), str(job.T),
+                                   str(1 + i), str(agg_sweeps)], stdout=subprocess.PIPE, text=True)
+                 for i in range(agg_procs)]
+        times = [float(p.communicate(timeout=600)[0].strip().splitlines()[-1]) for p in procs]
+        agg_flips = agg_procs * agg_sweeps * 2 * job.L ** 3
+        out["all_cores"] = {"value": round(max(times) / agg_flips * 1e12, 2), "unit": "ps/flip",
+                            "cores": agg_procs,
+                            "sample": f"{agg_procs} processes at once, one sample each (seeds 1..{agg_procs}), "
+                                      f"{agg_sweeps} sweeps of L={job.L}; slowest process {max(times):.1f} s"}
+    return out
 
 
 def bench_plain(ea, torch, job, steps: int, burst: int):
@@ -234,6 +264,8 @@ def main():
     ap.add_argument("--burst", type=int, default=2048, help="sweeps in the plain kernel-timing burst")
     ap.add_argument("--cpu-sweeps", type=int, default=60, help="oracle sweeps for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-agg-sweeps", type=int, default=20,
+                    help="sweeps per process of the all-core oracle rate (0 = skip)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="run every size with its default configuration")
     ap.add_argument("--serve-jobs", type=int, default=300, help="jobs in the serving leg (0 = skip)")
@@ -370,7 +402,9 @@ def main():
         out["batched_speedup_vs_plain"] = round(plain["ps_per_flip"] / ps_per_flip, 2)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(wl.mid_job(args.sweeps), args.cpu_sweeps)
+        n_cpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+        out["cpu_baseline"] = cpu_baseline(wl.mid_job(args.sweeps), args.cpu_sweeps, min(16, n_cpu),
+                                           args.cpu_agg_sweeps)
     print(json.dumps(out), flush=True)
 
 
