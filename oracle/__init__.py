@@ -90,6 +90,8 @@ def lib():
         L.eao_snapshot_time.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.eao_snapshot_time.restype = ctypes.c_uint64
         L.eao_measure.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Obs)]
+        L.eao_c4_shells.argtypes = [ctypes.c_void_p, ctypes.c_int, i64p]
+        L.eao_c4_shells.restype = None
         L.eao_measure.restype = None
         for name in ("eao_get_spins", "eao_set_spins"):
             getattr(L, name).argtypes = [ctypes.c_void_p, ctypes.c_int, i8p]
@@ -213,6 +215,14 @@ class Sim:
         lib().eao_measure(self._h, ctypes.byref(o))
         return Obs(int(o.t), np.array(o.unsat[:], dtype=np.int64),
                    np.array(o.mag[:], dtype=np.int64), int(o.overlap), ac, c4)
+
+    def c4_shells(self, n_shells: int | None = None) -> np.ndarray:
+        """Full-vector C4 sums by minimum-image squared distance (eq. 3);
+        n_shells defaults to (L/2)^2 + 1 (all |r| <= L/2)."""
+        n = (self.L // 2) ** 2 + 1 if n_shells is None else int(n_shells)
+        out = np.zeros(n, dtype=np.int64)
+        lib().eao_c4_shells(self._h, n, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+        return out
 
     def spins(self, r: int) -> np.ndarray:
         out = np.zeros(self.N, dtype=np.int8)

@@ -318,6 +318,35 @@ uint64_t eao_snapshot_time(const eao_sim *sim, int slot)
 
 /* Observables straight from their definitions, eqs. (1), (2), (3) and (7),
  * without the 1/N normalisation. */
+void eao_c4_shells(const eao_sim *sim, int n_shells, int64_t *out)
+{
+    int L = sim->L;
+    int64_t N = sim->N;
+    for (int k = 0; k < n_shells; ++k) out[k] = 0;
+    int8_t *q = (int8_t *)malloc((size_t)N);
+    if (!q) return;
+    for (int64_t s = 0; s < N; ++s) q[s] = (int8_t)(sim->S[0][s] * sim->S[1][s]);
+    for (int rz = 0; rz < L; ++rz) {
+        int mz = rz < L - rz ? rz : L - rz;
+        for (int ry = 0; ry < L; ++ry) {
+            int my = ry < L - ry ? ry : L - ry;
+            for (int rx = 0; rx < L; ++rx) {
+                int mx = rx < L - rx ? rx : L - rx;
+                int k = mx * mx + my * my + mz * mz;
+                if (k >= n_shells) continue;
+                int64_t acc = 0;
+                for (int64_t s = 0; s < N; ++s) {
+                    int x, y, z;
+                    coords_of(L, s, &x, &y, &z);
+                    acc += q[s] * q[site_of(L, x + rx, y + ry, z + rz)];
+                }
+                out[k] += acc;
+            }
+        }
+    }
+    free(q);
+}
+
 void eao_measure(const eao_sim *sim, eao_obs *out)
 {
     int L = sim->L;

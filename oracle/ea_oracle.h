@@ -102,6 +102,13 @@ uint64_t eao_snapshot_time(const eao_sim *sim, int slot);
 
 void eao_measure(const eao_sim *sim, eao_obs *out);
 
+/* Full-vector four-point correlation by distance shells (eq. 3 with every
+ * displacement r, not only the axes): out[k] = sum over all r in Z_L^3 whose
+ * minimum-image squared length |r|^2 = sum_d min(r_d, L - r_d)^2 equals k of
+ * sum_s q(s) q(s + r), q = S_0 S_1, for k = 0 .. n_shells - 1 (shells beyond
+ * are not reported).  Direct double sum, O(N^2). */
+void eao_c4_shells(const eao_sim *sim, int n_shells, int64_t *out);
+
 void eao_get_spins(const eao_sim *sim, int r, int8_t *S);
 void eao_set_spins(eao_sim *sim, int r, const int8_t *S);
 void eao_get_bonds(const eao_sim *sim, int8_t *J);
