@@ -192,6 +192,14 @@ class Sim:
         return Obs(int(o.t), np.array(o.unsat[:], dtype=np.int64), np.array(o.mag[:], dtype=np.int64),
                    int(o.overlap), tw[:ns].copy(), ac[:, :ns].copy(), c4a if c4 else None)
 
+    def c4_shells(self, n_shells: int | None = None) -> np.ndarray:
+        """Full-vector C4 sums by minimum-image squared distance (see
+        ea_c4_shells); n_shells defaults to (L/2)^2 + 1 (|r| <= L/2)."""
+        n = (self.L // 2) ** 2 + 1 if n_shells is None else int(n_shells)
+        out = np.zeros(n, dtype=np.int64)
+        abi.check(abi.lib().ea_c4_shells(self._h, n, abi.ptr(out, ctypes.c_int64)))
+        return out
+
     # -- state ------------------------------------------------------------
     def spins(self, r: int) -> np.ndarray:
         out = np.zeros(self.N, dtype=np.int8)

@@ -57,6 +57,7 @@ bool rw_valid(int R, int rw) { return rw >= 1 && R % 4 == 0 && (R / 4) % rw == 0
 // kPlainMinThreads threads (one wave per SIMD of every CU): below that a
 // launch lasts as long as one thread's chain of dependent instructions.
 constexpr long kPlainMinThreads = 65536;
+constexpr int kMaxShellL = 128;  // largest side with full-vector C4 (its cost grows as L^6 / 64)
 std::mutex g_plain_mu;
 std::map<int, int> g_plain_tuned;  // L -> words per row
 bool g_plain_file_read = false;
@@ -162,6 +163,8 @@ struct ea_sim {
     // captured graph of kGraphSweeps sweeps (built on first use)
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    // scratch of ea_c4_shells (allocated on first use)
+    unsigned long long *c4_scratch = nullptr;
 
     ea::Geom geom() const
     {
@@ -428,6 +431,7 @@ void ea_destroy(ea_sim *s)
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
     if (s->graph) (void)hipGraphDestroy(s->graph);
+    if (s->c4_scratch) (void)hipFree(s->c4_scratch);
     if (s->own_buf && s->buf) (void)hipFree(s->buf);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
@@ -527,6 +531,37 @@ ea_status ea_measure(ea_sim *s, ea_obs *out)
     }
     if (out->c4)
         for (int i = 0; i < 3 * (y.R + 1); ++i) out->c4[i] = N - 2 * (int64_t)m[c4_base + i];
+    return EA_OK;
+}
+
+ea_status ea_c4_shells(ea_sim *s, int32_t n_shells, int64_t *out)
+{
+    if (!s || !out) return fail(EA_ERR_ARG, "NULL argument");
+    const int L = s->lay.L;
+    if (L > kMaxShellL) return fail(EA_ERR_ARG, "full-vector C4 is offered for L <= %d (L=%d)", kMaxShellL, L);
+    const int max_shells = 3 * (L / 2) * (L / 2) + 1;
+    if (n_shells < 1 || n_shells > max_shells)
+        return fail(EA_ERR_ARG, "n_shells=%d outside [1, %d]", n_shells, max_shells);
+    const int dw = (2 * L + 63) / 64;
+    const size_t q_words = (size_t)L * L * dw;
+    if (!s->c4_scratch) {
+        hipError_t e = hipMalloc((void **)&s->c4_scratch, 8 * (q_words + (size_t)max_shells));
+        if (e != hipSuccess) {
+            s->c4_scratch = nullptr;
+            return fail(EA_ERR_NOMEM, "hipMalloc(c4 scratch): %s", hipGetErrorString(e));
+        }
+    }
+    unsigned long long *qd = s->c4_scratch, *shells = s->c4_scratch + q_words;
+    hipLaunchKernelGGL(ea::zero_u64_kernel, dim3(blocks_for((size_t)n_shells)), dim3(256), 0, s->stream, shells,
+                       (size_t)n_shells);
+    ea::Geom g = s->geom();
+    EA_DISPATCH_W(s->lay.W, hipLaunchKernelGGL((ea::dense_q_kernel<WW>), dim3(blocks_for(q_words)), dim3(256), 0,
+                                               s->stream, s->lat, g, dw, qd));
+    hipLaunchKernelGGL(ea::c4_shell_kernel, dim3((unsigned)((L + ea::kShellRx - 1) / ea::kShellRx), (unsigned)(L * L)),
+                       dim3(256), 0, s->stream, qd, L, dw, n_shells, shells);
+    EA_HIP(hipGetLastError());
+    EA_HIP(hipMemcpyAsync(out, shells, 8 * (size_t)n_shells, hipMemcpyDeviceToHost, s->stream));
+    EA_HIP(hipStreamSynchronize(s->stream));
     return EA_OK;
 }
 

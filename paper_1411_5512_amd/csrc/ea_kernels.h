@@ -244,6 +244,110 @@ __global__ __launch_bounds__(256) void c4_kernel(Lattice lat, Geom g, unsigned l
     wave_add(acc + blockIdx.y, diff);
 }
 
+// --------------------------------------------------------------------------
+// Full-vector C4 (eq. 3 over every displacement r), summed by minimum-image
+// distance shells k = |r|^2.  q = S_0 xor S_1 is first rewritten in natural
+// x order, one doubled row per (y, z): bits [0, L) hold x = 0..L-1 and bits
+// [L, 2L) repeat them, in dw 64-bit words, so that the row shifted
+// cyclically by rx is the window of L bits starting at bit rx.
+
+// One thread per (row, word of the doubled row).
+template <int W>
+__global__ __launch_bounds__(256) void dense_q_kernel(Lattice lat, Geom g, int dw, unsigned long long *qd)
+{
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= g.rows * dw) return;
+    const int row = gid / dw;
+    const int j = gid - row * dw;
+    const int y = row % g.L;
+    const int z = row / g.L;
+    unsigned long long bits = 0;
+    for (int b = 0; b < 64; ++b) {
+        const int gbit = 64 * j + b;
+        if (gbit >= 2 * g.L) break;
+        const int x = gbit % g.L;
+        const int c = (x + y + z) & 1;
+        const int xh = x >> 1;
+        const size_t word = (size_t)row * g.RW + (size_t)(xh / W);
+        const int bit = xh % W;
+        const uint32_t s0 = lat.spins[plane_off(g, 0, c) + word], s1 = lat.spins[plane_off(g, 1, c) + word];
+        bits |= (unsigned long long)(((s0 ^ s1) >> bit) & 1u) << b;
+    }
+    qd[gid] = bits;
+}
+
+constexpr int kShellRx = 8;  // displacements along x per workgroup
+
+__device__ __forceinline__ int min_image_sq(int r, int L)
+{
+    const int m = r < L - r ? r : L - r;
+    return m * m;
+}
+
+// Workgroup (rx chunk, ry + L rz): every thread takes source rows with a
+// stride, counts the sites where q differs from q at x + r for the
+// kShellRx displacements, the workgroup adds the counts, and
+// sum_x q(x) q(x + r) = N - 2 * count is added to the shell of r.
+__global__ __launch_bounds__(256) void c4_shell_kernel(const unsigned long long *qd, int L, int dw,
+                                                       int n_shells, unsigned long long *shells)
+{
+    __shared__ unsigned int part[kShellRx][256 / 64];
+    const int rx0 = blockIdx.x * kShellRx;
+    const int ry = (int)(blockIdx.y % (unsigned)L), rz = (int)(blockIdx.y / (unsigned)L);
+    const int kyz = min_image_sq(ry, L) + min_image_sq(rz, L);
+    int kmin = 1 << 30;
+    for (int i = 0; i < kShellRx; ++i)
+        if (rx0 + i < L) kmin = min(kmin, kyz + min_image_sq(rx0 + i, L));
+    if (kmin >= n_shells) return;  // whole workgroup: no barrier passed yet
+    const int nw = (L + 63) / 64;  // words of one row
+    const int tail = L - 64 * (nw - 1);  // bits used in the last word
+    const unsigned long long last_mask = tail == 64 ? ~0ull : ((1ull << tail) - 1ull);
+    unsigned int cnt[kShellRx];
+#pragma unroll
+    for (int i = 0; i < kShellRx; ++i) cnt[i] = 0;
+    const int rows = L * L;
+    for (int row = (int)threadIdx.x; row < rows; row += (int)blockDim.x) {
+        const int y = row % L, z = row / L;
+        const int prow = (y + ry) % L + L * ((z + rz) % L);
+        const unsigned long long *src = qd + (size_t)row * dw;
+        const unsigned long long *par = qd + (size_t)prow * dw;
+#pragma unroll
+        for (int i = 0; i < kShellRx; ++i) {
+            const int rx = rx0 + i;
+            if (rx >= L) break;
+            const int w0 = rx >> 6, off = rx & 63;
+            unsigned int c = 0;
+            for (int j = 0; j < nw; ++j) {
+                const unsigned long long lo = par[w0 + j];
+                const unsigned long long hi = w0 + j + 1 < dw ? par[w0 + j + 1] : 0ull;
+                unsigned long long win = off ? ((lo >> off) | (hi << (64 - off))) : lo;
+                unsigned long long d = src[j] ^ win;
+                if (j == nw - 1) d &= last_mask;
+                c += (unsigned int)__popcll(d);
+            }
+            cnt[i] += c;
+        }
+    }
+    // workgroup sums: within a wave by shuffles, then across the four waves
+#pragma unroll
+    for (int i = 0; i < kShellRx; ++i) {
+        const uint32_t v = wave_sum(cnt[i]);
+        if ((threadIdx.x & 63) == 0) part[i][threadIdx.x >> 6] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kShellRx) {
+        const int i = (int)threadIdx.x;
+        const int rx = rx0 + i;
+        const int k = kyz + min_image_sq(rx, L);
+        if (rx < L && k < n_shells) {
+            unsigned long long diff = 0;
+            for (int w = 0; w < (int)(blockDim.x / 64); ++w) diff += part[i][w];
+            const long long n = (long long)L * L * L;
+            atomicAdd(shells + k, (unsigned long long)(n - 2 * (long long)diff));
+        }
+    }
+}
+
 // Plain word copy (snapshots) and fill (clearing counters); kernels rather
 // than runtime memset/memcpy so that the same work can sit in a graph.
 __global__ __launch_bounds__(256) void copy_words_kernel(uint32_t *dst, const uint32_t *src, size_t n)

@@ -290,3 +290,24 @@ def test_split_windowed_parity_late_times(ea_gpu, oracle_mod):
         o.sweep(3)
         for r in (0, 1):
             assert np.array_equal(b.spins(j, r), o.spins(r)), (j, r)
+
+
+def test_coherence_length_grows(ea_gpu):
+    """Ageing (Sec. IV): the integral estimate xi_1 of the coherence length,
+    from the disorder average over 48 samples at p = 0.5, T = 0.7, grows
+    between t = 10 and t = 2000 sweeps."""
+    from paper_1411_5512_amd import analysis as an
+    from paper_1411_5512_amd.workloads import Job
+    L = 32
+    jobs = [Job(L, 0.5, 0.7, seed=100 + i, n_sweeps=2000, meas_t=[10, 2000]) for i in range(48)]
+    b = ea_gpu.Batch(jobs)
+    b.run()
+    xi = []
+    for k in range(2):
+        curves = []
+        for j in range(len(jobs)):
+            r, c = an.c4_of_axes(b.result(j, k).c4, L)
+            curves.append(c)
+        xi.append(an.xi_k_samples(r, np.array(curves), k=1)[0])
+    _say(f"xi_1(t=10) = {xi[0]:.3f}, xi_1(t=2000) = {xi[1]:.3f}")
+    assert 0 < xi[0] < xi[1] < L / 2

@@ -225,3 +225,53 @@ def test_crossover_windows_L128(ea_gpu, oracle_mod, p):
         _say(f"crossover L=128 p={p} window t0={t0}")
         _compare_state(g, o, f"p={p} t0={t0}")
         _compare_obs(g.measure(), o.measure(), f"p={p} t0={t0}")
+
+
+def _fft_shells(q, L, n_shells):
+    f = np.fft.fftn(q.reshape(L, L, L).astype(np.float64))
+    corr = np.rint(np.fft.ifftn(np.conj(f) * f).real).astype(np.int64)
+    m = np.minimum(np.arange(L), L - np.arange(L)) ** 2
+    k = m[:, None, None] + m[None, :, None] + m[None, None, :]
+    out = np.zeros(n_shells, dtype=np.int64)
+    sel = k < n_shells
+    np.add.at(out, k[sel], corr[sel])
+    return out
+
+
+@pytest.mark.parametrize("L,rw", [(8, 0), (16, 0), (16, 1), (24, 0), (32, 2)])
+def test_c4_shells_match_oracle(ea_gpu, oracle_mod, L, rw):
+    g = ea_gpu.Sim(L, 0.5, 0.8, seed=6, sample=1, words_per_row=rw)
+    o = oracle_mod.Sim(L, 0.5, 0.8, seed=6, sample=1)
+    g.sweep(9)
+    o.sweep(9)
+    _say(f"c4 shells L={L} rw={g.words_per_row}")
+    for n in (None, 3 * (L // 2) ** 2 + 1, 5):
+        assert np.array_equal(g.c4_shells(n), o.c4_shells(n)), (L, n)
+
+
+@pytest.mark.parametrize("L", [64, 96, 128])
+def test_c4_shells_full_size(ea_gpu, L):
+    """At full size (no oracle): equal to an FFT autocorrelation of the GPU's
+    own q, and the shell identities (r = 0, unit shell = axis C4 at 1, sum of
+    every shell = Q^2)."""
+    g = ea_gpu.Sim(L, 0.3, 0.7, seed=1)
+    g.sweep(50)
+    _say(f"c4 shells full size L={L}")
+    q = g.spins(0).astype(np.int64) * g.spins(1)
+    n_all = 3 * (L // 2) ** 2 + 1
+    got = g.c4_shells(n_all)
+    assert np.array_equal(got, _fft_shells(q, L, n_all))
+    obs = g.measure()
+    assert got[0] == L ** 3 and got[1] == 2 * int(obs.c4[:, 1].sum())
+    assert int(got.sum()) == obs.overlap ** 2
+    assert np.array_equal(g.c4_shells(), got[:(L // 2) ** 2 + 1])
+
+
+def test_c4_shells_errors(ea_gpu):
+    g = ea_gpu.Sim(16, 0.5, 0.8, seed=1)
+    for n in (0, 3 * 64 + 2):
+        with pytest.raises(ea_gpu.EAError):
+            g.c4_shells(n)
+    big = ea_gpu.Sim(136, 0.5, 0.8, seed=1)
+    with pytest.raises(ea_gpu.EAError):
+        big.c4_shells(10)
