@@ -87,8 +87,11 @@ def xi_k_samples(r, curves, k: int = 1, n_sigma: float = 3.0, tail: bool = True,
         m = (r >= 1.0) & (r <= r_cut)
         if m.sum() >= 4:
             p0 = (max(mean[m][0], 1e-12), 0.5, max(r_cut / 2, 1.0), 1.5)
+            import warnings
             try:
-                params, _ = optimize.curve_fit(c4_form, r[m], mean[m], p0=p0, maxfev=20000)
+                with warnings.catch_warnings():
+                    warnings.simplefilter("ignore", optimize.OptimizeWarning)
+                    params, _ = optimize.curve_fit(c4_form, r[m], mean[m], p0=p0, maxfev=20000)
             except RuntimeError:
                 params = None
         if params is not None:
