@@ -270,6 +270,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="run every size with its default configuration")
     ap.add_argument("--serve-jobs", type=int, default=300, help="jobs in the serving leg (0 = skip)")
     ap.add_argument("--serve-load", type=float, default=0.8, help="offered load of the serving leg")
+    ap.add_argument("--serve-load2", type=float, default=0.5,
+                    help="a second, lighter offered load reported beside it (0 = skip)")
     ap.add_argument("--serve-sweeps", type=int, default=10_000, help="upper end of the serving sweep range")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (a known-size kernel "
@@ -395,6 +397,10 @@ def main():
         log("serving form ...")
         out["serving"] = bench_serving(ea, torch, wl, args.serve_jobs, args.serve_load, args.serve_sweeps,
                                        ps_per_flip)
+        if args.serve_load2 > 0:
+            log(f"serving form at load {args.serve_load2} ...")
+            out["serving_light"] = bench_serving(ea, torch, wl, args.serve_jobs, args.serve_load2,
+                                                 args.serve_sweeps, ps_per_flip)
     if not args.no_plain:
         log("plain form ...")
         plain = bench_plain(ea, torch, wl.mid_job(args.sweeps), args.plain_steps, args.burst)

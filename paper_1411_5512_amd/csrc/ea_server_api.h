@@ -316,8 +316,15 @@ ea_status server_epoch(ea_server *s, int32_t *progressed)
             }
         };
         std::vector<std::thread> helpers;
-        for (int k = 1; k < n_workers; ++k) helpers.emplace_back(advance, k);
-        advance(0);
+        std::vector<int> here = {0};  // lists this thread advances itself
+        for (int k = 1; k < n_workers; ++k) {
+            try {
+                helpers.emplace_back(advance, k);
+            } catch (const std::exception &) {
+                here.push_back(k);  // no thread to spare: run the list here
+            }
+        }
+        for (int k : here) advance(k);
         for (auto &h : helpers) h.join();
         for (const std::string &e : errs)
             if (!e.empty()) return fail(EA_ERR_DEVICE, "streamed job: %s", e.c_str());

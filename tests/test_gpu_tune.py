@@ -52,3 +52,30 @@ def test_tune_rejects_bad_sizes(ea_gpu):
     for L in (0, 12, 72, 128):
         with pytest.raises(ea_gpu.EAError):
             ea_gpu.tune(L)
+
+
+def test_tune_cache_file_roundtrip(ea_gpu, tmp_path):
+    """EA_TUNE_CACHE: a first process tunes and appends its choices, a second
+    process reads them back without probing."""
+    import os
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = tmp_path / "tune_cache.txt"
+    env = dict(os.environ, EA_TUNE_CACHE=str(cache))
+    code = ("import paper_1411_5512_amd as ea; r = ea.tune(16); p = ea.tune_plain(24); "
+            "c = r['chosen']; print(c['words_per_row'], c['threads'], c['select'], len(r['tried']), "
+            "p['words_per_row'], len(p['tried']))")
+
+    def run():
+        out = subprocess.run([sys.executable, "-c", code], env=env, cwd=root, capture_output=True, text=True,
+                             timeout=300)
+        assert out.returncode == 0, out.stderr[-2000:]
+        return out.stdout.split()
+
+    first = run()
+    assert int(first[3]) >= 2 and int(first[5]) >= 2  # probed
+    lines = cache.read_text().splitlines()
+    assert any(" batch 16 " in ln for ln in lines) and any(" plain 24 " in ln for ln in lines)
+    second = run()
+    assert second[3] == "0" and second[5] == "0"  # read from the file
+    assert second[:3] == first[:3] and second[4] == first[4]
