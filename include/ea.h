@@ -142,9 +142,9 @@ ea_status ea_words_per_row(const ea_sim *sim, int32_t *rw);
  * k = 0 .. n_shells - 1.  n_shells = (L/2)^2 + 1 covers |r| <= L/2, the range
  * of the integral estimators (eqs. 5, 6); 3 (L/2)^2 + 1 covers every r.
  * Dividing a shell by N and by the number of lattice vectors in it gives the
- * shell average of C4.  L <= 128 (the work grows as L^6 / 64: ~30 ms at
- * L = 128).  Synchronises; allocates a device scratch buffer of
- * 8 (L^2 ceil(2L/64) + 3 (L/2)^2 + 1) bytes on the first call, kept until
+ * shell average of C4.  L <= 128 (the work grows as L^6 / 64).
+ * Synchronises; allocates a device scratch buffer of
+ * 8 (2 L^2 ceil(L/64) + 3 (L/2)^2 + 1) bytes on the first call, kept until
  * ea_destroy.  EA_ERR_ARG for L > 128 or n_shells outside [1, 3 (L/2)^2 + 1]. */
 ea_status ea_c4_shells(ea_sim *sim, int32_t n_shells, int64_t *out);
 

@@ -542,7 +542,8 @@ ea_status ea_c4_shells(ea_sim *s, int32_t n_shells, int64_t *out)
     const int max_shells = 3 * (L / 2) * (L / 2) + 1;
     if (n_shells < 1 || n_shells > max_shells)
         return fail(EA_ERR_ARG, "n_shells=%d outside [1, %d]", n_shells, max_shells);
-    const int dw = (2 * L + 63) / 64;
+    const int nw = (L + 63) / 64;  // words per row; the doubled row has 2 nw
+    const int dw = 2 * nw;
     const size_t q_words = (size_t)L * L * dw;
     if (!s->c4_scratch) {
         hipError_t e = hipMalloc((void **)&s->c4_scratch, 8 * (q_words + (size_t)max_shells));
@@ -557,8 +558,11 @@ ea_status ea_c4_shells(ea_sim *s, int32_t n_shells, int64_t *out)
     ea::Geom g = s->geom();
     EA_DISPATCH_W(s->lay.W, hipLaunchKernelGGL((ea::dense_q_kernel<WW>), dim3(blocks_for(q_words)), dim3(256), 0,
                                                s->stream, s->lat, g, dw, qd));
-    hipLaunchKernelGGL(ea::c4_shell_kernel, dim3((unsigned)((L + ea::kShellRx - 1) / ea::kShellRx), (unsigned)(L * L)),
-                       dim3(256), 0, s->stream, qd, L, dw, n_shells, shells);
+    const dim3 grid((unsigned)((L + ea::kShellRx - 1) / ea::kShellRx), (unsigned)(L * L));
+    if (nw == 1)
+        hipLaunchKernelGGL((ea::c4_shell_kernel<1>), grid, dim3(256), 0, s->stream, qd, L, n_shells, shells);
+    else
+        hipLaunchKernelGGL((ea::c4_shell_kernel<2>), grid, dim3(256), 0, s->stream, qd, L, n_shells, shells);
     EA_HIP(hipGetLastError());
     EA_HIP(hipMemcpyAsync(out, shells, 8 * (size_t)n_shells, hipMemcpyDeviceToHost, s->stream));
     EA_HIP(hipStreamSynchronize(s->stream));

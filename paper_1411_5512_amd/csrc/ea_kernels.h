@@ -276,7 +276,7 @@ __global__ __launch_bounds__(256) void dense_q_kernel(Lattice lat, Geom g, int d
     qd[gid] = bits;
 }
 
-constexpr int kShellRx = 8;  // displacements along x per workgroup
+constexpr int kShellRx = 16;  // displacements along x per workgroup
 
 __device__ __forceinline__ int min_image_sq(int r, int L)
 {
@@ -285,12 +285,16 @@ __device__ __forceinline__ int min_image_sq(int r, int L)
 }
 
 // Workgroup (rx chunk, ry + L rz): every thread takes source rows with a
-// stride, counts the sites where q differs from q at x + r for the
-// kShellRx displacements, the workgroup adds the counts, and
-// sum_x q(x) q(x + r) = N - 2 * count is added to the shell of r.
-__global__ __launch_bounds__(256) void c4_shell_kernel(const unsigned long long *qd, int L, int dw,
-                                                       int n_shells, unsigned long long *shells)
+// stride, holds the source row (NW words) and the partner row at
+// (y + ry, z + rz) (doubled, 2 NW words) in registers, counts the sites where
+// q differs from q at x + r for the kShellRx displacements rx of the chunk,
+// the workgroup adds the counts, and sum_x q(x) q(x + r) = N - 2 * count is
+// added to the shell of r.  NW = ceil(L / 64) words per row (L <= 128).
+template <int NW>
+__global__ __launch_bounds__(256) void c4_shell_kernel(const unsigned long long *qd, int L, int n_shells,
+                                                       unsigned long long *shells)
 {
+    constexpr int DW = 2 * NW;  // words of a doubled row
     __shared__ unsigned int part[kShellRx][256 / 64];
     const int rx0 = blockIdx.x * kShellRx;
     const int ry = (int)(blockIdx.y % (unsigned)L), rz = (int)(blockIdx.y / (unsigned)L);
@@ -299,8 +303,7 @@ __global__ __launch_bounds__(256) void c4_shell_kernel(const unsigned long long 
     for (int i = 0; i < kShellRx; ++i)
         if (rx0 + i < L) kmin = min(kmin, kyz + min_image_sq(rx0 + i, L));
     if (kmin >= n_shells) return;  // whole workgroup: no barrier passed yet
-    const int nw = (L + 63) / 64;  // words of one row
-    const int tail = L - 64 * (nw - 1);  // bits used in the last word
+    const int tail = L - 64 * (NW - 1);  // bits used in the last word of a row
     const unsigned long long last_mask = tail == 64 ? ~0ull : ((1ull << tail) - 1ull);
     unsigned int cnt[kShellRx];
 #pragma unroll
@@ -309,20 +312,28 @@ __global__ __launch_bounds__(256) void c4_shell_kernel(const unsigned long long 
     for (int row = (int)threadIdx.x; row < rows; row += (int)blockDim.x) {
         const int y = row % L, z = row / L;
         const int prow = (y + ry) % L + L * ((z + rz) % L);
-        const unsigned long long *src = qd + (size_t)row * dw;
-        const unsigned long long *par = qd + (size_t)prow * dw;
+        unsigned long long src[NW], par[DW];
+#pragma unroll
+        for (int j = 0; j < NW; ++j) src[j] = qd[(size_t)row * DW + j];
+#pragma unroll
+        for (int j = 0; j < DW; ++j) par[j] = qd[(size_t)prow * DW + j];
 #pragma unroll
         for (int i = 0; i < kShellRx; ++i) {
-            const int rx = rx0 + i;
+            const int rx = rx0 + i;  // uniform across the workgroup
             if (rx >= L) break;
             const int w0 = rx >> 6, off = rx & 63;
             unsigned int c = 0;
-            for (int j = 0; j < nw; ++j) {
-                const unsigned long long lo = par[w0 + j];
-                const unsigned long long hi = w0 + j + 1 < dw ? par[w0 + j + 1] : 0ull;
-                unsigned long long win = off ? ((lo >> off) | (hi << (64 - off))) : lo;
+#pragma unroll
+            for (int j = 0; j < NW; ++j) {
+                // words w0 + j and w0 + j + 1 of the doubled row (w0 is 0 or 1)
+                unsigned long long lo = par[j], hi = j + 1 < DW ? par[j + 1] : 0ull;
+                if (NW > 1 && w0 == 1) {
+                    lo = par[j + 1];
+                    hi = j + 2 < DW ? par[j + 2] : 0ull;
+                }
+                const unsigned long long win = off ? ((lo >> off) | (hi << (64 - off))) : lo;
                 unsigned long long d = src[j] ^ win;
-                if (j == nw - 1) d &= last_mask;
+                if (j == NW - 1) d &= last_mask;
                 c += (unsigned int)__popcll(d);
             }
             cnt[i] += c;
