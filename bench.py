@@ -59,9 +59,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic():
-    """(bytes per launch, provenance) if the recorded counters match the
-    current kernel sources and workload, else (None, reason)."""
+def measured_record():
+    """The recorded counters (dict) if they were taken on the current kernel
+    sources, else (None, reason)."""
     try:
         with open(TRAFFIC_FILE) as f:
             kv = dict(line.split(None, 1) for line in f if line.strip() and not line.startswith("#"))
@@ -70,7 +70,15 @@ def measured_traffic():
     kv = {k: v.strip() for k, v in kv.items()}
     if kv.get("source_sha256") != kernel_source_hash():
         return None, "kernel changed since the counters were taken"
-    return int(kv["fetch_bytes"]) + int(kv["write_bytes"]), kv.get("workload", "")
+    return kv, kv.get("workload", "")
+
+
+def measured_traffic():
+    """(HBM bytes per launch, provenance) from the record, or (None, reason)."""
+    kv, why = measured_record()
+    if kv is None:
+        return None, why
+    return int(kv["fetch_bytes"]) + int(kv["write_bytes"]), why
 
 
 def algorithmic_bytes(jobs) -> int:
@@ -347,6 +355,8 @@ def main():
     n_results = sum(len(j.meas_t) for j in jobs)
 
     traffic, traffic_src = measured_traffic()
+    record, _ = measured_record()
+    valu_issue = float(record["valu_issue"]) if record and "valu_issue" in record else None
     alg_bytes = algorithmic_bytes(jobs)
     out = {
         "metric": METRIC,
@@ -387,6 +397,7 @@ def main():
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "traffic_source": traffic_src,
             "alg_bytes_per_launch": alg_bytes,
+            "valu_issue_measured": valu_issue,  # SQ_INSTS_VALU over the device's issue slots (record)
             "hbm_frac": round(((traffic or alg_bytes) / launch_s / 1e9) / 8000.0, 5),
             "flips_per_launch": flips_per_step,
         },
