@@ -157,6 +157,20 @@ ea_status ea_reset(ea_sim *sim, uint64_t seed, uint32_t sample);
  * t + n would reach 2^32 (the sweep index is one counter word). */
 ea_status ea_sweep(ea_sim *sim, uint64_t n);
 
+/* Advance n_sims runs of the same L and words_per_row by n sweeps each in
+ * one launch per half-step (up to 16 runs per launch), giving exactly the
+ * spins that n_sims separate ea_sweep calls give (Sec. III's update; every
+ * run keeps its own key, sample, T and sweep counter).  For several small
+ * independent samples, such as Sec. IV's L = 128 averages, whose single
+ * half-steps are too short to fill the device.  The work is enqueued on the
+ * first run's stream after everything already queued on the others, and the
+ * others' later work waits for it; asynchronous.  EA_ERR_ARG if sims is NULL
+ * or n_sims < 1, a run is NULL or listed twice, L or words_per_row differ,
+ * or t + n would reach 2^32 for any run; then no run advances.  A group runs
+ * fastest when its members use the densest packing (fewest words per row),
+ * since it needs no extra threads to fill the device. */
+ea_status ea_sweep_group(ea_sim *const *sims, int32_t n_sims, uint64_t n);
+
 /* Store the current spins as reference S(t_w) in slot k, t_w = t. */
 ea_status ea_snapshot(ea_sim *sim, int32_t slot);
 

@@ -15,7 +15,7 @@ import numpy as np
 from . import abi
 from .abi import EAError
 
-__all__ = ["Sim", "Batch", "Server", "EAError", "thresholds", "footprint", "version", "tune"]
+__all__ = ["Sim", "Batch", "Server", "EAError", "thresholds", "footprint", "version", "tune", "sweep_group"]
 
 
 def version() -> str:
@@ -222,6 +222,14 @@ class Sim:
         if J.size != 3 * self.N:
             raise ValueError("wrong coupling count")
         abi.check(abi.lib().ea_set_bonds(self._h, abi.ptr(J, ctypes.c_int8)))
+
+
+def sweep_group(sims, n: int = 1):
+    """Advance several runs of one L and packing by n sweeps each in shared
+    launches (see ea_sweep_group); same spins as separate Sim.sweep calls."""
+    sims = list(sims)
+    arr = (ctypes.c_void_p * max(len(sims), 1))(*[s._h.value if s._h is not None else None for s in sims])
+    abi.check(abi.lib().ea_sweep_group(arr, len(sims), int(n)))
 
 
 def _job_struct(job, keep):

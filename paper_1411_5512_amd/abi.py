@@ -125,6 +125,7 @@ _SIGS = {
     "ea_destroy": (None, [ctypes.c_void_p]),
     "ea_reset": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32]),
     "ea_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "ea_sweep_group": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_uint64]),
     "ea_snapshot": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "ea_measure": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Obs)]),
     "ea_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),

@@ -165,6 +165,8 @@ struct ea_sim {
     hipGraphExec_t graph_exec = nullptr;
     // scratch of ea_c4_shells (allocated on first use)
     unsigned long long *c4_scratch = nullptr;
+    // event ordering this run's stream with a group sweep (created on first use)
+    hipEvent_t group_event = nullptr;
 
     ea::Geom geom() const
     {
@@ -432,6 +434,7 @@ void ea_destroy(ea_sim *s)
     if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
     if (s->graph) (void)hipGraphDestroy(s->graph);
     if (s->c4_scratch) (void)hipFree(s->c4_scratch);
+    if (s->group_event) (void)hipEventDestroy(s->group_event);
     if (s->own_buf && s->buf) (void)hipFree(s->buf);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
@@ -473,6 +476,76 @@ ea_status ea_sweep(ea_sim *s, uint64_t n)
     if (st != EA_OK) return st;
     EA_HIP(hipGetLastError());
     s->t += n;
+    return EA_OK;
+}
+
+namespace {
+
+ea_status group_event(ea_sim *s)
+{
+    if (!s->group_event) EA_HIP(hipEventCreateWithFlags(&s->group_event, hipEventDisableTiming));
+    return EA_OK;
+}
+
+}  // namespace
+
+ea_status ea_sweep_group(ea_sim *const *sims, int32_t n_sims, uint64_t n)
+{
+    if (!sims || n_sims < 1) return fail(EA_ERR_ARG, "need at least one run");
+    for (int32_t i = 0; i < n_sims; ++i) {
+        if (!sims[i]) return fail(EA_ERR_ARG, "run %d is NULL", i);
+        if (sims[i]->lay.L != sims[0]->lay.L || sims[i]->lay.RW != sims[0]->lay.RW)
+            return fail(EA_ERR_ARG, "run %d: L=%d with %d words per row, run 0: L=%d with %d", i, sims[i]->lay.L,
+                        sims[i]->lay.RW, sims[0]->lay.L, sims[0]->lay.RW);
+        for (int32_t j = 0; j < i; ++j)
+            if (sims[j] == sims[i]) return fail(EA_ERR_ARG, "run %d appears twice", i);
+        if (sims[i]->t + n >= (1ull << 32) || n >= (1ull << 32))
+            return fail(EA_ERR_ARG, "run %d: t + n would reach 2^32", i);
+    }
+    if (n == 0) return EA_OK;
+    ea_sim *lead = sims[0];
+    // the work runs on the first run's stream, after everything queued on the others
+    for (int32_t i = 1; i < n_sims; ++i) {
+        if (sims[i]->stream == lead->stream) continue;
+        ea_status st = group_event(sims[i]);
+        if (st != EA_OK) return st;
+        EA_HIP(hipEventRecord(sims[i]->group_event, sims[i]->stream));
+        EA_HIP(hipStreamWaitEvent(lead->stream, sims[i]->group_event, 0));
+    }
+    ea::Geom g = lead->geom();
+    for (int32_t i = 0; i < n_sims; ++i)
+        hipLaunchKernelGGL(ea::set_u32_kernel, dim3(1), dim3(64), 0, lead->stream, sims[i]->t_dev,
+                           (uint32_t)sims[i]->t);
+    // member arguments, one block of at most kGroupMax runs per launch
+    std::vector<ea::GroupArgs> chunks((size_t)((n_sims + ea::kGroupMax - 1) / ea::kGroupMax));
+    for (int32_t i = 0; i < n_sims; ++i) {
+        const ea_sim *m = sims[i];
+        ea::GroupMember &gm = chunks[(size_t)(i / ea::kGroupMax)].m[i % ea::kGroupMax];
+        gm.lat = m->lat;
+        gm.t_base = m->t_dev;
+        gm.k0 = key_lo(m);
+        gm.k1 = key_hi(m);
+        gm.sample = m->sample;
+        gm.thr1 = m->thr[0];
+        gm.thr2 = m->thr[1];
+        gm.thr3 = m->thr[2];
+    }
+    // sweep by sweep, every chunk of runs for each half-step
+    for (uint64_t k = 0; k < n; ++k)
+        for (int half = 0; half < 2; ++half)
+            for (size_t c = 0; c < chunks.size(); ++c) {
+                const int32_t cnt = std::min<int32_t>(ea::kGroupMax, n_sims - (int32_t)c * ea::kGroupMax);
+                const dim3 grid(blocks_for(g.plane), 2, (unsigned)cnt);
+                EA_DISPATCH_W(lead->lay.W, hipLaunchKernelGGL((ea::group_half_step_kernel<WW>), grid, dim3(256), 0,
+                                                             lead->stream, chunks[c], g, half, (uint32_t)k));
+            }
+    EA_HIP(hipGetLastError());
+    ea_status st = group_event(lead);
+    if (st != EA_OK) return st;
+    EA_HIP(hipEventRecord(lead->group_event, lead->stream));
+    for (int32_t i = 1; i < n_sims; ++i)
+        if (sims[i]->stream != lead->stream) EA_HIP(hipStreamWaitEvent(sims[i]->stream, lead->group_event, 0));
+    for (int32_t i = 0; i < n_sims; ++i) sims[i]->t += n;
     return EA_OK;
 }
 

@@ -68,15 +68,10 @@ __global__ __launch_bounds__(256) void init_kernel(Lattice lat, Geom g, uint32_t
 // neighbours of a colour-c site have colour 1 - c, so every thread reads the
 // other colour and writes only its own word.  One thread per (row, word).
 template <int W>
-__global__ __launch_bounds__(256) void half_step_kernel(Lattice lat, Geom g, int half,
-                                                        const uint32_t *__restrict__ t_base, uint32_t t_off,
-                                                        uint32_t k0, uint32_t k1, uint32_t sample,
-                                                        uint32_t thr1, uint32_t thr2, uint32_t thr3)
+__device__ __forceinline__ void half_step_word(const Lattice &lat, const Geom &g, int half, uint32_t t, int r,
+                                               int tid, uint32_t k0, uint32_t k1, uint32_t sample, uint32_t thr1,
+                                               uint32_t thr2, uint32_t thr3)
 {
-    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-    if (tid >= g.plane) return;
-    const uint32_t t = *t_base + t_off;
-    const int r = blockIdx.y;
     const int c = r ^ half;
     const int row = tid / g.RW;
     const int w = tid - row * g.RW;
@@ -121,6 +116,42 @@ __global__ __launch_bounds__(256) void half_step_kernel(Lattice lat, Geom g, int
     const uint32_t flips = flip_mask<W>(d, t, quad0, counter_word2(TAG_METRO, (uint32_t)c, (uint32_t)r),
                                         sample, k0, k1, thr1, thr2, thr3);
     own[base + w] = S ^ flips;
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void half_step_kernel(Lattice lat, Geom g, int half,
+                                                        const uint32_t *__restrict__ t_base, uint32_t t_off,
+                                                        uint32_t k0, uint32_t k1, uint32_t sample,
+                                                        uint32_t thr1, uint32_t thr2, uint32_t thr3)
+{
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= g.plane) return;
+    half_step_word<W>(lat, g, half, *t_base + t_off, (int)blockIdx.y, tid, k0, k1, sample, thr1, thr2, thr3);
+}
+
+// Several runs of the same geometry in one launch: grid.z = member.  Each
+// member keeps its own couplings, key, thresholds and sweep counter, so the
+// launch is the members' own half-steps side by side.
+constexpr int kGroupMax = 16;
+
+struct GroupMember {
+    Lattice lat;
+    const uint32_t *t_base;
+    uint32_t k0, k1, sample, thr1, thr2, thr3;
+};
+
+struct GroupArgs {
+    GroupMember m[kGroupMax];
+};
+
+template <int W>
+__global__ __launch_bounds__(256) void group_half_step_kernel(GroupArgs a, Geom g, int half, uint32_t t_off)
+{
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= g.plane) return;
+    const GroupMember &M = a.m[blockIdx.z];
+    half_step_word<W>(M.lat, g, half, *M.t_base + t_off, (int)blockIdx.y, tid, M.k0, M.k1, M.sample, M.thr1,
+                      M.thr2, M.thr3);
 }
 
 // --------------------------------------------------------------------------

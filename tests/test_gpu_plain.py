@@ -275,3 +275,69 @@ def test_c4_shells_errors(ea_gpu):
     big = ea_gpu.Sim(136, 0.5, 0.8, seed=1)
     with pytest.raises(ea_gpu.EAError):
         big.c4_shells(10)
+
+
+def test_sweep_group_matches_oracle(ea_gpu, oracle_mod):
+    """Grouped launches give each member the oracle's own trajectory: mixed
+    p, T, seed, sample and start times, members on separate streams (one of
+    them library-owned), group and single sweeps interleaved."""
+    L = 24
+    params = [(0.5, 0.8, 3, 0), (0.2, 0.6, 3, 1), (0.5, 1.2, 91, 4), (0.0, 0.7, 5, 2)]
+    gs = [ea_gpu.Sim(L, p, T, seed=s, sample=k, n_slots=1, use_torch=(i != 2))
+          for i, (p, T, s, k) in enumerate(params)]
+    os_ = [oracle_mod.Sim(L, p, T, seed=s, sample=k, n_slots=1) for (p, T, s, k) in params]
+    for g, o in zip(gs, os_):
+        g.snapshot(0)
+        o.snapshot(0)
+    gs[1].sweep(2)
+    os_[1].sweep(2)
+    _say("group L=24: 4 runs x 5 sweeps")
+    ea_gpu.sweep_group(gs, 5)
+    for o in os_:
+        o.sweep(5)
+    gs[3].sweep(1)
+    os_[3].sweep(1)
+    ea_gpu.sweep_group(gs[1:], 3)
+    for o in os_[1:]:
+        o.sweep(3)
+    for i, (g, o) in enumerate(zip(gs, os_)):
+        _compare_state(g, o, f"group member {i}")
+        oo = o.measure()
+        assert g.time == oo.t
+        _compare_obs(g.measure(), oo, f"group member {i}")
+
+
+@pytest.mark.parametrize("L,n_runs,rw", [(16, 21, 0), (64, 3, 2), (128, 5, 0)])
+def test_sweep_group_equals_single_runs(ea_gpu, L, n_runs, rw):
+    """A group of n_runs (more than one launch's 16 members for n_runs = 21)
+    reaches bit for bit the spins of the same runs swept one by one."""
+    _say(f"group L={L} runs={n_runs} rw={rw}")
+    mk = lambda i: ea_gpu.Sim(L, 0.5 if i % 2 else 0.3, 0.7 + 0.05 * (i % 3), seed=11, sample=i,
+                              words_per_row=rw)
+    grp = [mk(i) for i in range(n_runs)]
+    one = [mk(i) for i in range(n_runs)]
+    ea_gpu.sweep_group(grp, 4)
+    ea_gpu.sweep_group(grp, 0)
+    for s in one:
+        s.sweep(4)
+    for i, (a, b) in enumerate(zip(grp, one)):
+        assert a.time == b.time == 4
+        for r in (0, 1):
+            assert np.array_equal(a.spins(r), b.spins(r)), (L, i, r)
+
+
+def test_sweep_group_errors(ea_gpu):
+    a = ea_gpu.Sim(16, 0.5, 0.8, seed=1)
+    b = ea_gpu.Sim(16, 0.5, 0.8, seed=2)
+    c = ea_gpu.Sim(24, 0.5, 0.8, seed=3)
+    d = ea_gpu.Sim(64, 0.5, 0.8, seed=3, words_per_row=1)
+    e = ea_gpu.Sim(64, 0.5, 0.8, seed=3, words_per_row=2)
+    for bad in ([], [a, c], [a, a], [a, b, a], [d, e]):
+        with pytest.raises(ea_gpu.EAError):
+            ea_gpu.sweep_group(bad, 1)
+    b.set_time((1 << 32) - 3)
+    with pytest.raises(ea_gpu.EAError):
+        ea_gpu.sweep_group([a, b], 3)
+    assert a.time == 0 and b.time == (1 << 32) - 3   # nothing advanced
+    ea_gpu.sweep_group([a, b], 2)
+    assert a.time == 2 and b.time == (1 << 32) - 1
