@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "ea_oracle.c")
 LIB = os.path.join(HERE, "libea_oracle.so")
 
-TAG_METRO, TAG_BOND, TAG_INIT = 0, 1, 2
+TAG_METRO, TAG_BOND, TAG_INIT, TAG_SHARED = 0, 1, 2, 3
 
 
 def build(force: bool = False) -> str:
@@ -79,6 +79,8 @@ def lib():
         L.eao_time.restype = ctypes.c_uint64
         L.eao_set_time.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
         L.eao_set_time.restype = None
+        L.eao_share_noise.argtypes = [ctypes.c_void_p, ctypes.c_uint32]
+        L.eao_share_noise.restype = None
         L.eao_sweep.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
         L.eao_sweep.restype = None
         L.eao_half_step.argtypes = [ctypes.c_void_p, ctypes.c_int]
@@ -162,6 +164,16 @@ class Obs:
                 tuple(map(tuple, self.autocorr)), tuple(map(tuple, self.c4)))
 
 
+def shared_batch(L, p, T, seed, sample0, n_samples, shared_id, n_slots=0):
+    """The samples sample0 .. sample0 + n_samples - 1 that one multispin word
+    holds (Sec. III): separate runs whose Metropolis words all come from the
+    shared stream shared_id."""
+    sims = [Sim(L, p, T, seed, sample0 + b, n_slots) for b in range(n_samples)]
+    for s in sims:
+        s.share_noise(shared_id)
+    return sims
+
+
 class Sim:
     """One disorder sample with two replicas, run by the oracle."""
 
@@ -169,6 +181,7 @@ class Sim:
         self.L, self.p, self.T = int(L), float(p), float(T)
         self.seed, self.sample, self.n_slots = int(seed), int(sample), int(n_slots)
         self.N = self.L ** 3
+        self.shared = None
         h = lib().eao_create(self.L, self.p, self.T, self.seed, self.sample, self.n_slots)
         if not h:
             raise ValueError(f"oracle rejected L={L} p={p} T={T} n_slots={n_slots}")
@@ -191,6 +204,12 @@ class Sim:
 
     def set_time(self, t: int):
         lib().eao_set_time(self._h, t)
+
+    def share_noise(self, shared_id: int):
+        """Draw Metropolis words from the shared stream shared_id (the
+        asynchronous multispin coding of Sec. III)."""
+        lib().eao_share_noise(self._h, int(shared_id))
+        self.shared = int(shared_id)
 
     def sweep(self, n: int = 1):
         lib().eao_sweep(self._h, n)

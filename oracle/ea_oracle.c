@@ -161,6 +161,8 @@ struct eao_sim {
     double T;
     uint64_t seed;
     uint32_t sample;
+    uint32_t metro_tag;    /* tag and counter word 3 of the Metropolis words */
+    uint32_t metro_id;
     uint32_t thr[3];
     uint64_t t;
     int n_slots;
@@ -173,6 +175,15 @@ struct eao_sim {
 int eao_L(const eao_sim *sim) { return sim->L; }
 uint64_t eao_time(const eao_sim *sim) { return sim->t; }
 void eao_set_time(eao_sim *sim, uint64_t t) { sim->t = t; }
+
+/* Sec. III: in asynchronous multispin coding one random number serves the
+ * same site of every sample packed in the word.  Only the Metropolis words
+ * change; each sample keeps its own couplings and start. */
+void eao_share_noise(eao_sim *sim, uint32_t id)
+{
+    sim->metro_tag = EAO_TAG_SHARED;
+    sim->metro_id = id;
+}
 
 /* Sec. II: couplings drawn i.i.d. per bond with P(J = -1) = p; both replicas
  * start from independent uniformly random spins (quench from T = infinity);
@@ -191,6 +202,8 @@ eao_sim *eao_create(int L, double p, double T, uint64_t seed, uint32_t sample, i
     sim->T = T;
     sim->seed = seed;
     sim->sample = sample;
+    sim->metro_tag = EAO_TAG_METRO;
+    sim->metro_id = sample;
     sim->t = 0;
     sim->n_slots = n_slots;
     eao_thresholds(T, sim->thr);
@@ -252,7 +265,7 @@ static void update_site(eao_sim *sim, int r, int colour, int64_t s)
         flip = 1;
     } else {
         int k = dE / 4;
-        uint32_t u = eao_site_word(sim->seed, sim->sample, EAO_TAG_METRO, (uint32_t)sim->t,
+        uint32_t u = eao_site_word(sim->seed, sim->metro_id, sim->metro_tag, (uint32_t)sim->t,
                                    colour, r, (uint64_t)eao_half_index(sim->L, s));
         flip = u < sim->thr[k - 1];
     }

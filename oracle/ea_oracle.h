@@ -22,6 +22,11 @@
  *   - random words: Philox4x32-10, key = (seed lo, seed hi), counter =
  *     (aux, h>>2, tag<<8 | colour<<1 | replica, sample), word h & 3, where aux
  *     is the sweep index (tag 0), the bond direction (tag 1) or 0 (tag 2).
+ *   - shared noise (asynchronous multispin coding, Sec. III): a run switched
+ *     by eao_share_noise draws its Metropolis words with tag 3 and counter
+ *     word 3 = the shared id instead of its sample, so every run with the same
+ *     seed and id uses the same word for the same (sweep, colour, replica,
+ *     site); its couplings and start keep the sample's own keys.
  *   - acceptance of dE = 4k > 0 iff u < thr_k, thr_k = floor(exp(-4k/T) 2^32)
  *     (clamped to 2^32-1; 0 at T = 0).  dE <= 0 is always accepted.
  */
@@ -35,7 +40,7 @@ extern "C" {
 #endif
 
 /* Random-word tags (third counter word, bits 8 and up). */
-enum { EAO_TAG_METRO = 0, EAO_TAG_BOND = 1, EAO_TAG_INIT = 2 };
+enum { EAO_TAG_METRO = 0, EAO_TAG_BOND = 1, EAO_TAG_INIT = 2, EAO_TAG_SHARED = 3 };
 
 /* Philox4x32-10 block: out = Philox(key, ctr).  Salmon, Moraes, Dror, Shaw,
  * "Parallel random numbers: as easy as 1, 2, 3", SC'11. */
@@ -86,6 +91,10 @@ void eao_destroy(eao_sim *sim);
 int eao_L(const eao_sim *sim);
 uint64_t eao_time(const eao_sim *sim);
 void eao_set_time(eao_sim *sim, uint64_t t);
+/* From now on draw the Metropolis words from the shared stream `id` (see the
+ * conventions above): the samples that one multispin word holds in the
+ * paper's Sec. III all follow one random number per site and sweep. */
+void eao_share_noise(eao_sim *sim, uint32_t id);
 
 /* Advance both replicas by n sweeps. */
 void eao_sweep(eao_sim *sim, uint64_t n);
