@@ -369,6 +369,78 @@ ea_status ea_server_release(ea_server *s, uint64_t id);
 
 ea_status ea_server_stats(ea_server *s, ea_server_report *out);
 
+/* ------------------------------------------------------------------------
+ * Multispin-coded batch: asynchronous multispin coding (Sec. III).  The same
+ * site of n_samples samples shares one word, and one random word per (sweep,
+ * colour, replica, site) decides the Metropolis move (eq. 9) of that site in
+ * every sample: Philox key (seed lo, seed hi), counter (t, h >> 2,
+ * 3 << 8 | colour << 1 | replica, shared), word h & 3, with h the site's half
+ * index as in the one-sample form.  Sample b (0 <= b < n_samples) gets the
+ * couplings and initial spins that ea_create gives sample sample0 + b, and
+ * then follows its own Metropolis chain, correlated with the others only
+ * through the shared words; two batches with the same seed and shared id use
+ * the same words.  All samples share L, p and T.
+ *
+ * Packing.  A 32-bit word holds M = min(n_samples, 32) samples; with fewer
+ * than 32 the lattice is cut along z into 32 / M slabs whose same-position
+ * sites share a word, a neighbour across a slab face being the word rotated
+ * by M bits (the slab split of Sec. III); n_samples = 64 uses two words per
+ * site that share the random words, as the paper's 64-bit words do.  The
+ * packing changes no result, only the work per random word.
+ *
+ * Device memory: (3 + 2 (1 + n_tw_slots)) n_samples L^3 / 8 bytes of words
+ * plus counters (ea_msc_footprint).  Calls follow the one-sample form:
+ * ea_msc_sweep and ea_msc_snapshot enqueue and return, calls that hand data
+ * to the host synchronise the stream, one host thread at a time. */
+typedef struct ea_msc ea_msc;
+
+typedef struct {
+    int32_t L;            /* multiple of 8 in 8..256, and of 64 / n_samples when n_samples < 32 */
+    int32_t n_samples;    /* 1, 2, 4, 8, 16, 32 or 64 */
+    double p;             /* P(J = -1), in [0, 1] */
+    double T;             /* temperature >= 0, finite */
+    uint64_t seed;        /* Philox key */
+    uint32_t sample0;     /* sample b draws couplings and start as sample sample0 + b */
+    uint32_t shared;      /* counter word 3 of the shared Metropolis words */
+    int32_t n_tw_slots;   /* reference configurations S(t_w), 0..64 */
+    void *stream;         /* hipStream_t to enqueue on, or NULL */
+    void *dev_buf;        /* optional caller-owned device buffer (256-byte aligned), or NULL */
+    size_t dev_buf_bytes; /* its size in bytes */
+} ea_msc_config;
+
+/* Device bytes of a batch; EA_ERR_ARG for an invalid L, n_samples or slot count. */
+ea_status ea_msc_footprint(const ea_msc_config *cfg, size_t *bytes);
+
+/* Create the batch and generate every sample's couplings and spins on the
+ * device (t = 0).  EA_ERR_ARG for an invalid config (see the fields),
+ * EA_ERR_NOMEM if the device allocation fails. */
+ea_status ea_msc_create(const ea_msc_config *cfg, ea_msc **out);
+void ea_msc_destroy(ea_msc *batch);
+
+/* n sweeps of every sample (t += n); asynchronous.  EA_ERR_ARG if t + n
+ * would reach 2^32. */
+ea_status ea_msc_sweep(ea_msc *batch, uint64_t n);
+
+/* Store every sample's spins as reference S(t_w) in slot k, t_w = t. */
+ea_status ea_msc_snapshot(ea_msc *batch, int32_t slot);
+
+/* Observables of every sample at the current time: out[b] for sample b,
+ * b < n_samples, each filled as ea_measure fills its ea_obs (tw/autocorr
+ * and c4 may be NULL per sample).  Synchronises. */
+ea_status ea_msc_measure(ea_msc *batch, ea_obs *out);
+
+/* Spins of sample b, replica r, as int8 +-1 [N] in canonical order; set
+ * rejects values other than +-1.  Couplings of sample b, [3N] as in
+ * ea_get_bonds.  Synchronise. */
+ea_status ea_msc_get_spins(ea_msc *batch, int32_t b, int32_t r, int8_t *pm1);
+ea_status ea_msc_set_spins(ea_msc *batch, int32_t b, int32_t r, const int8_t *pm1);
+ea_status ea_msc_get_bonds(ea_msc *batch, int32_t b, int8_t *pm1);
+
+ea_status ea_msc_time(const ea_msc *batch, uint64_t *t);
+/* Set the sweep counter (resume from a checkpoint taken at time t < 2^32). */
+ea_status ea_msc_set_time(ea_msc *batch, uint64_t t);
+ea_status ea_msc_sync(ea_msc *batch);
+
 #ifdef __cplusplus
 }
 #endif

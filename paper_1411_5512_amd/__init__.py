@@ -15,7 +15,7 @@ import numpy as np
 from . import abi
 from .abi import EAError
 
-__all__ = ["Sim", "Batch", "Server", "EAError", "thresholds", "footprint", "version", "tune", "sweep_group"]
+__all__ = ["Sim", "Batch", "Server", "EAError", "thresholds", "footprint", "version", "tune", "sweep_group", "Msc"]
 
 
 def version() -> str:
@@ -230,6 +230,103 @@ def sweep_group(sims, n: int = 1):
     sims = list(sims)
     arr = (ctypes.c_void_p * max(len(sims), 1))(*[s._h.value if s._h is not None else None for s in sims])
     abi.check(abi.lib().ea_sweep_group(arr, len(sims), int(n)))
+
+
+class Msc:
+    """Multispin-coded batch (asynchronous multispin coding, Sec. III): the
+    samples sample0 .. sample0 + n_samples - 1 of one L, p, T share one word per
+    site and one random word per site and sweep (see ea_msc_* in ea.h)."""
+
+    def __init__(self, L: int, n_samples: int, p: float, T: float, seed: int, sample0: int = 0,
+                 shared: int = 0, n_slots: int = 0, use_torch: bool = True):
+        self.L, self.n_samples, self.p, self.T = int(L), int(n_samples), float(p), float(T)
+        self.seed, self.sample0, self.shared, self.n_slots = int(seed), int(sample0), int(shared), int(n_slots)
+        self.N = self.L ** 3
+        self._h = None
+        cfg = abi.MscConfig()
+        cfg.L, cfg.n_samples, cfg.p, cfg.T = self.L, self.n_samples, self.p, self.T
+        cfg.seed, cfg.sample0, cfg.shared, cfg.n_tw_slots = self.seed, self.sample0, self.shared, self.n_slots
+        need = ctypes.c_size_t(0)
+        if abi.lib().ea_msc_footprint(ctypes.byref(cfg), ctypes.byref(need)) != 0:
+            need = ctypes.c_size_t(0)  # invalid arguments: ea_msc_create reports them
+        need = need.value
+        self._stream, self._buf = _torch_stream_and_buffer(need, use_torch and need > 0)
+        if self._stream is not None:
+            cfg.stream = ctypes.c_void_p(self._stream.cuda_stream)
+            cfg.dev_buf = ctypes.c_void_p((self._buf.data_ptr() + 255) & ~255)
+            cfg.dev_buf_bytes = need
+        h = ctypes.c_void_p()
+        abi.check(abi.lib().ea_msc_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+
+    @staticmethod
+    def footprint(L: int, n_samples: int, n_slots: int = 0) -> int:
+        cfg = abi.MscConfig()
+        cfg.L, cfg.n_samples, cfg.n_tw_slots = int(L), int(n_samples), int(n_slots)
+        out = ctypes.c_size_t(0)
+        abi.check(abi.lib().ea_msc_footprint(ctypes.byref(cfg), ctypes.byref(out)))
+        return int(out.value)
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            abi.lib().ea_msc_destroy(self._h)
+        self._h = None
+        self._buf = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def stream(self):
+        return self._stream
+
+    @property
+    def time(self) -> int:
+        t = ctypes.c_uint64(0)
+        abi.check(abi.lib().ea_msc_time(self._h, ctypes.byref(t)))
+        return int(t.value)
+
+    def set_time(self, t: int):
+        abi.check(abi.lib().ea_msc_set_time(self._h, int(t)))
+
+    def sweep(self, n: int = 1):
+        abi.check(abi.lib().ea_msc_sweep(self._h, int(n)))
+
+    def snapshot(self, slot: int):
+        abi.check(abi.lib().ea_msc_snapshot(self._h, int(slot)))
+
+    def sync(self):
+        abi.check(abi.lib().ea_msc_sync(self._h))
+
+    def measure(self, c4: bool = True, autocorr: bool = True) -> list:
+        B = self.n_samples
+        objs = (abi.Obs * B)()
+        bufs = [_obs_buffers(self.L, self.n_slots if autocorr else 0, c4, objs[b]) for b in range(B)]
+        abi.check(abi.lib().ea_msc_measure(self._h, objs))
+        ns = self.n_slots if autocorr else 0
+        return [Obs(int(objs[b].t), np.array(objs[b].unsat[:], dtype=np.int64),
+                    np.array(objs[b].mag[:], dtype=np.int64), int(objs[b].overlap),
+                    bufs[b][0][:ns].copy(), bufs[b][1][:, :ns].copy(), bufs[b][2] if c4 else None)
+                for b in range(B)]
+
+    def spins(self, b: int, r: int) -> np.ndarray:
+        out = np.zeros(self.N, dtype=np.int8)
+        abi.check(abi.lib().ea_msc_get_spins(self._h, int(b), int(r), abi.ptr(out, ctypes.c_int8)))
+        return out
+
+    def set_spins(self, b: int, r: int, S):
+        S = np.ascontiguousarray(S, dtype=np.int8)
+        if S.size != self.N:
+            raise ValueError(f"{S.size} spins given, {self.N} needed")
+        abi.check(abi.lib().ea_msc_set_spins(self._h, int(b), int(r), abi.ptr(S, ctypes.c_int8)))
+
+    def bonds(self, b: int) -> np.ndarray:
+        out = np.zeros(3 * self.N, dtype=np.int8)
+        abi.check(abi.lib().ea_msc_get_bonds(self._h, int(b), abi.ptr(out, ctypes.c_int8)))
+        return out
 
 
 def _job_struct(job, keep):

@@ -39,6 +39,22 @@ class Config(ctypes.Structure):
     ]
 
 
+class MscConfig(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_int32),
+        ("n_samples", ctypes.c_int32),
+        ("p", ctypes.c_double),
+        ("T", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("sample0", ctypes.c_uint32),
+        ("shared", ctypes.c_uint32),
+        ("n_tw_slots", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
+        ("dev_buf", ctypes.c_void_p),
+        ("dev_buf_bytes", ctypes.c_size_t),
+    ]
+
+
 class Obs(ctypes.Structure):
     _fields_ = [
         ("t", ctypes.c_uint64),
@@ -123,6 +139,20 @@ _SIGS = {
                                  ctypes.POINTER(ctypes.c_void_p)]),
     "ea_create_ex": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_void_p)]),
     "ea_destroy": (None, [ctypes.c_void_p]),
+    "ea_msc_footprint": (ctypes.c_int, [ctypes.POINTER(MscConfig), ctypes.POINTER(ctypes.c_size_t)]),
+    "ea_msc_create": (ctypes.c_int, [ctypes.POINTER(MscConfig), ctypes.POINTER(ctypes.c_void_p)]),
+    "ea_msc_destroy": (None, [ctypes.c_void_p]),
+    "ea_msc_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "ea_msc_snapshot": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "ea_msc_measure": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Obs)]),
+    "ea_msc_get_spins": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int8)]),
+    "ea_msc_set_spins": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int8)]),
+    "ea_msc_get_bonds": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int8)]),
+    "ea_msc_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
+    "ea_msc_set_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "ea_msc_sync": (ctypes.c_int, [ctypes.c_void_p]),
     "ea_reset": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32]),
     "ea_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
     "ea_sweep_group": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_uint64]),

@@ -821,3 +821,4 @@ ea_status ea_set_bonds(ea_sim *s, const int8_t *pm1)
 
 #include "ea_batch_api.h"
 #include "ea_server_api.h"
+#include "ea_msc_api.h"

@@ -1,0 +1,399 @@
+// ea_msc_kernels.h -- asynchronous multispin coding (Sec. III): the same site
+// of several samples sits in the bits of one 32-bit word, and one random word
+// per (sweep, colour, replica, site) serves every sample of the word.
+//
+// Multispin layout.  A batch holds B samples; one word carries M = min(B, 32)
+// of them and G = B / M word sets (G = 2 for B = 64) share the random words.
+// With M < 32 a word carries S = 32 / M sites of each sample: the lattice is
+// cut along z into S slabs of Lz = L / S planes (Lz even), and bit k M + m of
+// the word at reduced position (x, y, z') holds sample m at z = z' + k Lz
+// (the slab split of Sec. III).  A z-neighbour across a slab face sits in the
+// word at the other face of the reduced lattice, rotated by M bits.  Colours
+// follow the reduced coordinates, (x + y + z') & 1, equal to the full site's
+// colour because Lz is even.  Each (word set, replica, colour) plane holds
+// P = R L Lz words (R = L/2), word index xh + R (y + L z'), xh = x >> 1.
+// Spins and couplings carry 1 for -1, as in the one-sample layout; the
+// couplings to +x, +y, +z live in three planes per colour, like the spins.
+#pragma once
+
+#include "ea_device.h"
+
+namespace ea {
+
+constexpr uint32_t TAG_SHARED = 3u;  // counter tag of the shared Metropolis words
+
+struct MscGeom {
+    int L, R, Lz;
+    int P;   // words per plane
+    int q;   // threads per plane: four consecutive xh each
+};
+
+struct MscLattice {
+    uint32_t *spins;  // [G][replica 2][colour 2][P]
+    uint32_t *bonds;  // [G][direction 3][colour 2][P]
+};
+
+__device__ __forceinline__ size_t msc_spin_plane(const MscGeom &g, int gi, int r, int c)
+{
+    return (((size_t)gi * 2 + (size_t)r) * 2 + (size_t)c) * (size_t)g.P;
+}
+
+__device__ __forceinline__ size_t msc_bond_plane(const MscGeom &g, int gi, int d, int c)
+{
+    return (((size_t)gi * 3 + (size_t)d) * 2 + (size_t)c) * (size_t)g.P;
+}
+
+// The word of the slab above aligned to this one: bit k M + m takes bit
+// (k + 1) M + m, slab S - 1 takes slab 0 (the periodic face).
+template <int M>
+__device__ __forceinline__ uint32_t from_slab_above(uint32_t w)
+{
+    if constexpr (M == 32)
+        return w;
+    else
+        return (w >> M) | (w << (32 - M));
+}
+
+// The word of the slab below aligned to this one: bit k M + m takes bit
+// (k - 1) M + m.
+template <int M>
+__device__ __forceinline__ uint32_t from_slab_below(uint32_t w)
+{
+    if constexpr (M == 32)
+        return w;
+    else
+        return (w << M) | (w >> (32 - M));
+}
+
+// Shift by n slabs up (n >= 0): bit k M + m takes bit (k + n) M + m.
+template <int M>
+__device__ __forceinline__ uint32_t from_slabs_above(uint32_t w, int n)
+{
+    if constexpr (M == 32) {
+        return w;
+    } else {
+        const int s = (n * M) & 31;
+        return s ? (w >> s) | (w << (32 - s)) : w;
+    }
+}
+
+__device__ __forceinline__ uint4 load4(const uint32_t *p)
+{
+    return *reinterpret_cast<const uint4 *>(p);
+}
+
+// --------------------------------------------------------------------------
+// Couplings and initial spins (Sec. II), sample by sample with the keys of
+// the one-sample form: sample sample0 + gi M + m draws, for the full site h,
+// the words the one-sample form draws for it.  One thread per four
+// consecutive xh of a row; grid.y = what (0..2 coupling direction, 3..4
+// replica of the spins), grid.z = gi * 2 + colour.
+template <int M>
+__global__ __launch_bounds__(256) void msc_init_kernel(MscLattice lat, MscGeom g, uint32_t k0, uint32_t k1,
+                                                       uint32_t sample0, uint64_t pcut)
+{
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= g.q) return;
+    const int what = blockIdx.y;
+    const int gi = blockIdx.z >> 1, c = blockIdx.z & 1;
+    const int R4 = g.R >> 2;
+    const int row = tid / R4;
+    const int xh0 = (tid - row * R4) * 4;
+    const int y = row % g.L, z = row / g.L;
+    const bool bond = what < 3;
+    const uint32_t aux = bond ? (uint32_t)what : 0u;
+    const uint32_t w2 = bond ? counter_word2(TAG_BOND, (uint32_t)c, 0u)
+                             : counter_word2(TAG_INIT, (uint32_t)c, (uint32_t)(what - 3));
+    uint32_t out[4] = {0u, 0u, 0u, 0u};
+    for (int bit = 0; bit < 32; ++bit) {
+        const int m = bit % M, k = bit / M;
+        const uint32_t h = (uint32_t)xh0 + (uint32_t)g.R * ((uint32_t)y + (uint32_t)g.L * (uint32_t)(z + k * g.Lz));
+        const Words4 u = philox10(aux, h >> 2, w2, sample0 + (uint32_t)(gi * M + m), k0, k1);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t b = bond ? (uint32_t)((uint64_t)u.v[i] < pcut) : (u.v[i] >> 31);
+            out[i] |= b << bit;
+        }
+    }
+    uint32_t *dst = bond ? lat.bonds + msc_bond_plane(g, gi, what, c) : lat.spins + msc_spin_plane(g, gi, what - 3, c);
+    *reinterpret_cast<uint4 *>(dst + (size_t)row * g.R + xh0) = make_uint4(out[0], out[1], out[2], out[3]);
+}
+
+// --------------------------------------------------------------------------
+// One checkerboard half-step (Sec. III, eq. 9) of every sample of the batch.
+// grid.y = replica r, which updates colour c = r ^ half (the interlaced
+// order).  One thread per four consecutive xh of a row of one replica: for
+// each slab k it draws one Philox block whose four words are the shared
+// words of its four sites, turns them into per-bit threshold masks, and then
+// decides all M S bits of each of its G words with the bit-sliced count of
+// unsatisfied bonds.
+template <int M, int G>
+__global__ __launch_bounds__(256) void msc_half_step_kernel(MscLattice lat, MscGeom g, int half,
+                                                            const uint32_t *__restrict__ t_base, uint32_t t_off,
+                                                            uint32_t k0, uint32_t k1, uint32_t shared,
+                                                            uint32_t thr1, uint32_t thr2, uint32_t thr3)
+{
+    constexpr int S = 32 / M;
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= g.q) return;
+    const int r = blockIdx.y;
+    const int c = r ^ half;
+    const int R4 = g.R >> 2;
+    const int row = tid / R4;
+    const int xh0 = (tid - row * R4) * 4;
+    const int y = row % g.L, z = row / g.L;
+    const int par = (y + z + c) & 1;  // x = 2 xh + par on this row
+    const int R = g.R;
+    const int row_yp = wrap(y + 1, g.L) + g.L * z, row_ym = wrap(y - 1, g.L) + g.L * z;
+    const bool top = z == g.Lz - 1, bottom = z == 0;
+    const int row_zp = y + g.L * (top ? 0 : z + 1), row_zm = y + g.L * (bottom ? g.Lz - 1 : z - 1);
+    const uint32_t t = *t_base + t_off;
+
+    // threshold masks: bit b of mj[i] is set iff site i's shared word of
+    // b's slab is below thr_j
+    uint32_t m1[4] = {0u, 0u, 0u, 0u}, m2[4] = {0u, 0u, 0u, 0u}, m3[4] = {0u, 0u, 0u, 0u};
+    const uint32_t w2 = counter_word2(TAG_SHARED, (uint32_t)c, (uint32_t)r);
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+        const uint32_t h = (uint32_t)xh0 + (uint32_t)R * ((uint32_t)y + (uint32_t)g.L * (uint32_t)(z + k * g.Lz));
+        const Words4 u = philox10(t, h >> 2, w2, shared, k0, k1);
+        const uint32_t slab = M == 32 ? 0xffffffffu : (((1u << (M & 31)) - 1u) << (k * M));
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            m1[i] |= u.v[i] < thr1 ? slab : 0u;
+            m2[i] |= u.v[i] < thr2 ? slab : 0u;
+            m3[i] |= u.v[i] < thr3 ? slab : 0u;
+        }
+    }
+
+    const size_t at = (size_t)row * R + xh0;
+    const size_t edge = (size_t)row * R + (par ? (xh0 + 4 == R ? 0 : xh0 + 4) : (xh0 == 0 ? R - 1 : xh0 - 1));
+    const size_t left = (size_t)row * R + (xh0 == 0 ? R - 1 : xh0 - 1);
+#pragma unroll
+    for (int gi = 0; gi < G; ++gi) {
+        uint32_t *own = lat.spins + msc_spin_plane(g, gi, r, c);
+        const uint32_t *oth = lat.spins + msc_spin_plane(g, gi, r, c ^ 1);
+        const uint32_t *bx_own = lat.bonds + msc_bond_plane(g, gi, 0, c);
+        const uint32_t *by_own = lat.bonds + msc_bond_plane(g, gi, 1, c);
+        const uint32_t *bz_own = lat.bonds + msc_bond_plane(g, gi, 2, c);
+        const uint32_t *bx_oth = lat.bonds + msc_bond_plane(g, gi, 0, c ^ 1);
+        const uint32_t *by_oth = lat.bonds + msc_bond_plane(g, gi, 1, c ^ 1);
+        const uint32_t *bz_oth = lat.bonds + msc_bond_plane(g, gi, 2, c ^ 1);
+
+        const uint4 s4 = load4(own + at);
+        const uint4 o4 = load4(oth + at);
+        const uint32_t oe = oth[edge];
+        const uint4 xo4 = load4(bx_oth + at);
+        const uint32_t xe = bx_oth[left];
+        const uint4 bx4 = load4(bx_own + at), by4 = load4(by_own + at), bz4 = load4(bz_own + at);
+        const uint4 yp4 = load4(oth + (size_t)row_yp * R + xh0), ym4 = load4(oth + (size_t)row_ym * R + xh0);
+        const uint4 bym4 = load4(by_oth + (size_t)row_ym * R + xh0);
+        const uint4 zp4 = load4(oth + (size_t)row_zp * R + xh0), zm4 = load4(oth + (size_t)row_zm * R + xh0);
+        const uint4 bzm4 = load4(bz_oth + (size_t)row_zm * R + xh0);
+
+        const uint32_t Sv[4] = {s4.x, s4.y, s4.z, s4.w};
+        const uint32_t O[4] = {o4.x, o4.y, o4.z, o4.w};
+        const uint32_t Xo[4] = {xo4.x, xo4.y, xo4.z, xo4.w};
+        const uint32_t Bx[4] = {bx4.x, bx4.y, bx4.z, bx4.w}, By[4] = {by4.x, by4.y, by4.z, by4.w};
+        const uint32_t Bz[4] = {bz4.x, bz4.y, bz4.z, bz4.w};
+        const uint32_t Yp[4] = {yp4.x, yp4.y, yp4.z, yp4.w}, Ym[4] = {ym4.x, ym4.y, ym4.z, ym4.w};
+        const uint32_t Bym[4] = {bym4.x, bym4.y, bym4.z, bym4.w};
+        const uint32_t Zp[4] = {zp4.x, zp4.y, zp4.z, zp4.w}, Zm[4] = {zm4.x, zm4.y, zm4.z, zm4.w};
+        const uint32_t Bzm[4] = {bzm4.x, bzm4.y, bzm4.z, bzm4.w};
+
+        uint32_t out[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t s = Sv[i];
+            // x neighbours: on even rows (par = 0) +x shares xh and -x is xh - 1;
+            // on odd rows +x is xh + 1 and -x shares xh.  The -x coupling is
+            // stored at the -x site.
+            const uint32_t xp = par ? (i < 3 ? O[i + 1] : oe) : O[i];
+            const uint32_t xm = par ? O[i] : (i > 0 ? O[i - 1] : oe);
+            const uint32_t bxm = par ? Xo[i] : (i > 0 ? Xo[i - 1] : xe);
+            const uint32_t zp = top ? from_slab_above<M>(Zp[i]) : Zp[i];
+            const uint32_t zm = bottom ? from_slab_below<M>(Zm[i]) : Zm[i];
+            const uint32_t bzm = bottom ? from_slab_below<M>(Bzm[i]) : Bzm[i];
+            const Decision d = classify(xor3(s, xp, Bx[i]), xor3(s, xm, bxm), xor3(s, Yp[i], By[i]),
+                                        xor3(s, Ym[i], Bym[i]), xor3(s, zp, Bz[i]), xor3(s, zm, bzm));
+            // n >= 2 -> thr1 (n >= 3 is in "always"), n = 1 -> thr2, n = 0 -> thr3
+            const uint32_t low = __builtin_amdgcn_bitop3_b32(d.odd, m2[i], m3[i], kBitopSelect);
+            const uint32_t pick = __builtin_amdgcn_bitop3_b32(d.any, m1[i], low, kBitopSelect);
+            out[i] = s ^ (d.always | pick);
+        }
+        *reinterpret_cast<uint4 *>(own + at) = make_uint4(out[0], out[1], out[2], out[3]);
+    }
+}
+
+// --------------------------------------------------------------------------
+// Measurements (eqs. 1, 2, 3, 7) sample by sample.  Every bit of a word is a
+// different (sample, slab), so the sums are per-bit counts: each lane visits
+// words, and for each bit b a wave ballot of that bit, counted, goes to lane
+// b's accumulator.  The block adds its waves' counts in LDS and then to the
+// device counters, laid out [quantity][G][32 bits]; the host adds the S
+// bits k M + m of each sample m.
+enum { MSC_UNSAT = 0, MSC_DOWN = 2, MSC_QDIFF = 4, MSC_AUTO = 5 };
+
+// Adds to lane b of acc, for b < 32, the number of lanes whose x has bit b set.
+__device__ __forceinline__ void count_bits(uint32_t x, uint32_t &acc)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+#pragma unroll
+    for (uint32_t b = 0; b < 32; ++b) {
+        const uint32_t n = (uint32_t)__popcll(__ballot((x >> b) & 1u));
+        acc += lane == b ? n : 0u;
+    }
+}
+
+// Block sum of up to 5 per-bit accumulators, then one atomic per bit and
+// quantity: dst[k] receives quantity k's 32 counts.
+template <int NQ>
+__device__ __forceinline__ void block_flush(const uint32_t (&acc)[NQ], unsigned long long *const (&dst)[NQ])
+{
+    __shared__ uint32_t red[NQ][32];
+    for (int i = threadIdx.x; i < NQ * 32; i += blockDim.x) red[i / 32][i % 32] = 0u;
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
+    if (lane < 32)
+#pragma unroll
+        for (int k = 0; k < NQ; ++k)
+            if (acc[k]) atomicAdd(&red[k][lane], acc[k]);
+    __syncthreads();
+    for (int i = threadIdx.x; i < NQ * 32; i += blockDim.x)
+        if (red[i / 32][i % 32]) atomicAdd(dst[i / 32] + (i % 32), (unsigned long long)red[i / 32][i % 32]);
+}
+
+// Word idx of the 2P words of one word set and replica pair: colour, row and xh.
+struct MscSite {
+    int c, hw, row, xh, y, z, par;
+};
+
+__device__ __forceinline__ MscSite msc_site(const MscGeom &g, int idx)
+{
+    MscSite s;
+    s.c = idx >= g.P;
+    s.hw = idx - s.c * g.P;
+    s.row = s.hw / g.R;
+    s.xh = s.hw - s.row * g.R;
+    s.y = s.row % g.L;
+    s.z = s.row / g.L;
+    s.par = (s.y + s.z + s.c) & 1;
+    return s;
+}
+
+// grid.y = 0: unsatisfied bonds, down spins and the overlap; grid.y = 1 + k:
+// the autocorrelation with slot k.  grid.z = word set.
+template <int M>
+__global__ __launch_bounds__(256) void msc_measure_kernel(MscLattice lat, MscGeom g, const uint32_t *snaps,
+                                                          size_t snap_words, int n_sets,
+                                                          unsigned long long *acc)
+{
+    const int gi = blockIdx.z;
+    const int what = blockIdx.y;
+    const int R = g.R;
+    const size_t stride = (size_t)n_sets * 32;
+    unsigned long long *base = acc + (size_t)gi * 32;
+    if (what == 0) {
+        uint32_t cnt[5] = {0u, 0u, 0u, 0u, 0u};
+        for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx - (int)threadIdx.x < 2 * g.P;
+             idx += gridDim.x * blockDim.x) {
+            // every lane reaches the ballots; lanes past the end count zeros
+            uint32_t s0 = 0u, s1 = 0u, un0[3] = {0u, 0u, 0u}, un1[3] = {0u, 0u, 0u};
+            if (idx < 2 * g.P) {
+                const MscSite st = msc_site(g, idx);
+                s0 = lat.spins[msc_spin_plane(g, gi, 0, st.c) + st.hw];
+                s1 = lat.spins[msc_spin_plane(g, gi, 1, st.c) + st.hw];
+                // bonds to +x, +y, +z, each counted at the site that stores it
+                const int xn = st.par ? (st.xh + 1 == R ? 0 : st.xh + 1) : st.xh;
+                const bool top = st.z + 1 == g.Lz;
+                const size_t nb[3] = {(size_t)st.row * R + xn, (size_t)(wrap(st.y + 1, g.L) + g.L * st.z) * R + st.xh,
+                                      (size_t)(st.y + g.L * (top ? 0 : st.z + 1)) * R + st.xh};
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const uint32_t J = lat.bonds[msc_bond_plane(g, gi, d, st.c) + st.hw];
+                    uint32_t n0 = lat.spins[msc_spin_plane(g, gi, 0, st.c ^ 1) + nb[d]];
+                    uint32_t n1 = lat.spins[msc_spin_plane(g, gi, 1, st.c ^ 1) + nb[d]];
+                    if (d == 2 && top) {
+                        n0 = from_slab_above<M>(n0);
+                        n1 = from_slab_above<M>(n1);
+                    }
+                    un0[d] = xor3(s0, n0, J);
+                    un1[d] = xor3(s1, n1, J);
+                }
+            }
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                count_bits(un0[d], cnt[0]);
+                count_bits(un1[d], cnt[1]);
+            }
+            count_bits(s0, cnt[2]);
+            count_bits(s1, cnt[3]);
+            count_bits(s0 ^ s1, cnt[4]);
+        }
+        unsigned long long *const dst[5] = {base + MSC_UNSAT * stride, base + (MSC_UNSAT + 1) * stride,
+                                            base + MSC_DOWN * stride, base + (MSC_DOWN + 1) * stride,
+                                            base + MSC_QDIFF * stride};
+        block_flush<5>(cnt, dst);
+    } else {
+        const uint32_t *snap = snaps + (size_t)(what - 1) * snap_words;
+        uint32_t cnt[2] = {0u, 0u};
+        for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx - (int)threadIdx.x < 2 * g.P;
+             idx += gridDim.x * blockDim.x) {
+            uint32_t d0 = 0u, d1 = 0u;
+            if (idx < 2 * g.P) {
+                const MscSite st = msc_site(g, idx);
+                d0 = lat.spins[msc_spin_plane(g, gi, 0, st.c) + st.hw] ^ snap[msc_spin_plane(g, gi, 0, st.c) + st.hw];
+                d1 = lat.spins[msc_spin_plane(g, gi, 1, st.c) + st.hw] ^ snap[msc_spin_plane(g, gi, 1, st.c) + st.hw];
+            }
+            count_bits(d0, cnt[0]);
+            count_bits(d1, cnt[1]);
+        }
+        const int k = what - 1;
+        unsigned long long *const dst[2] = {base + (MSC_AUTO + 2 * k) * stride,
+                                            base + (MSC_AUTO + 2 * k + 1) * stride};
+        block_flush<2>(cnt, dst);
+    }
+}
+
+// C4 along the axes (eq. 3): sites whose overlap differs from the overlap
+// rho e_d away.  grid.y = d (R + 1) + rho, grid.z = word set; acc points at
+// the C4 block, laid out [d][rho][G][32].
+template <int M>
+__global__ __launch_bounds__(256) void msc_c4_kernel(MscLattice lat, MscGeom g, int n_sets,
+                                                     unsigned long long *acc)
+{
+    const int gi = blockIdx.z;
+    const int d = blockIdx.y / (g.R + 1), rho = blockIdx.y - d * (g.R + 1);
+    const int R = g.R;
+    uint32_t cnt[1] = {0u};
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx - (int)threadIdx.x < 2 * g.P;
+         idx += gridDim.x * blockDim.x) {
+        uint32_t diff = 0u;
+        if (idx < 2 * g.P) {
+            const MscSite st = msc_site(g, idx);
+            const int x = 2 * st.xh + st.par;
+            const int c2 = st.c ^ (rho & 1);
+            size_t w2;
+            int up = 0;  // slabs crossed along z
+            if (d == 0) {
+                const int x2 = (x + rho) % g.L;
+                w2 = (size_t)st.row * R + (x2 >> 1);
+            } else if (d == 1) {
+                w2 = (size_t)(((st.y + rho) % g.L) + g.L * st.z) * R + st.xh;
+            } else {
+                const int zz = st.z + rho;
+                up = zz / g.Lz;
+                w2 = (size_t)(st.y + g.L * (zz - up * g.Lz)) * R + st.xh;
+            }
+            const uint32_t q = lat.spins[msc_spin_plane(g, gi, 0, st.c) + st.hw] ^
+                               lat.spins[msc_spin_plane(g, gi, 1, st.c) + st.hw];
+            const uint32_t q2 = lat.spins[msc_spin_plane(g, gi, 0, c2) + w2] ^ lat.spins[msc_spin_plane(g, gi, 1, c2) + w2];
+            diff = q ^ from_slabs_above<M>(q2, up);
+        }
+        count_bits(diff, cnt[0]);
+    }
+    unsigned long long *const dst[1] = {acc + ((size_t)blockIdx.y * n_sets + gi) * 32};
+    block_flush<1>(cnt, dst);
+}
+
+}  // namespace ea

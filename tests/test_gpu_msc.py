@@ -1,0 +1,178 @@
+"""Parity of the multispin-coded batch (asynchronous multispin coding,
+Sec. III) against the oracle: each sample b of a GPU batch must follow, bit
+for bit, the oracle run of sample sample0 + b switched to the shared noise of
+the batch, in every packing (32 samples per word; fewer, with the lattice cut
+into z-slabs; 64 in two word sets)."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _compare_obs(go, oo, ctx):
+    assert go.t == oo.t, ctx
+    assert list(go.unsat) == list(oo.unsat), ctx
+    assert list(go.mag) == list(oo.mag), ctx
+    assert go.overlap == oo.overlap, ctx
+    if oo.autocorr.size:
+        assert np.array_equal(go.autocorr, oo.autocorr), ctx
+    if go.c4 is not None:
+        assert np.array_equal(go.c4, oo.c4), ctx
+
+
+def _check_samples(g, os_, bs, ctx):
+    for b in bs:
+        for r in (0, 1):
+            gs, ref = g.spins(b, r), os_[b].spins(r)
+            if not np.array_equal(gs, ref):
+                bad = np.flatnonzero(gs != ref)
+                raise AssertionError(f"{ctx}: sample {b} replica {r} differs at {bad.size} sites, first {bad[:8]}")
+
+
+# (L, n_samples): 32 per word; 16, 4 and 1 per word (2, 8 and 32 z-slabs);
+# 64 in two word sets
+PACKINGS = [(8, 32), (16, 32), (24, 16), (16, 4), (64, 1), (32, 2), (16, 64), (40, 8)]
+
+
+@pytest.mark.parametrize("L,B", PACKINGS)
+def test_initial_state_matches_oracle(ea_gpu, oracle_mod, L, B):
+    _say(f"msc init L={L} B={B}")
+    g = ea_gpu.Msc(L, B, 0.4, 0.8, seed=12, sample0=3, shared=9)
+    for b in sorted({b for b in (0, 1, B // 2, B - 1) if b < B}):
+        o = oracle_mod.Sim(L, 0.4, 0.8, seed=12, sample=3 + b)
+        assert np.array_equal(g.bonds(b), o.bonds()), (L, B, b)
+        for r in (0, 1):
+            assert np.array_equal(g.spins(b, r), o.spins(r)), (L, B, b, r)
+
+
+@pytest.mark.parametrize("L,B,p,T,sweeps", [
+    (8, 32, 0.5, 0.8, 12), (16, 32, 0.5, 0.8, 5), (24, 16, 0.3, 0.6, 4), (16, 4, 0.5, 1.2, 6),
+    (64, 1, 0.5, 0.7, 2), (32, 2, 0.2, 0.7, 3), (16, 64, 0.5, 0.8, 3), (40, 8, 0.5, 0.9, 2),
+    (8, 32, 0.0, 0.7, 10), (8, 32, 1.0, 0.7, 10), (8, 32, 0.5, 0.0, 10), (8, 8, 0.5, 3.0, 10),
+])
+def test_sweeps_match_oracle(ea_gpu, oracle_mod, L, B, p, T, sweeps):
+    _say(f"msc sweeps L={L} B={B} p={p} T={T} n={sweeps}")
+    g = ea_gpu.Msc(L, B, p, T, seed=5, sample0=10, shared=77, n_slots=2)
+    os_ = oracle_mod.shared_batch(L, p, T, seed=5, sample0=10, n_samples=B, shared_id=77, n_slots=2)
+    g.snapshot(0)
+    for o in os_:
+        o.snapshot(0)
+    g.sweep(sweeps)
+    for o in os_:
+        o.sweep(sweeps)
+    g.snapshot(1)
+    for o in os_:
+        o.snapshot(1)
+    g.sweep(1)
+    for o in os_:
+        o.sweep(1)
+    _check_samples(g, os_, range(B), f"L={L} B={B}")
+    gobs = g.measure()
+    for b in range(B):
+        _compare_obs(gobs[b], os_[b].measure(), f"L={L} B={B} sample {b}")
+
+
+def test_graph_replays_and_resume(ea_gpu, oracle_mod):
+    """Runs of 64 sweeps and more replay a captured graph; splitting a run,
+    or restoring spins and time into a fresh batch, changes nothing."""
+    L, B = 8, 32
+    g = ea_gpu.Msc(L, B, 0.5, 0.9, seed=2, sample0=0, shared=1)
+    h = ea_gpu.Msc(L, B, 0.5, 0.9, seed=2, sample0=0, shared=1)
+    os_ = oracle_mod.shared_batch(L, 0.5, 0.9, seed=2, sample0=0, n_samples=B, shared_id=1)
+    g.sweep(150)
+    h.sweep(70)
+    h.sweep(80)
+    for o in os_:
+        o.sweep(150)
+    _check_samples(g, os_, range(B), "150 sweeps")
+    for b in range(B):
+        for r in (0, 1):
+            assert np.array_equal(g.spins(b, r), h.spins(b, r))
+    k = ea_gpu.Msc(L, B, 0.5, 0.9, seed=2, sample0=0, shared=1)
+    for b in range(B):
+        for r in (0, 1):
+            k.set_spins(b, r, g.spins(b, r))
+    k.set_time(150)
+    g.sweep(9)
+    k.sweep(9)
+    for o in os_:
+        o.sweep(9)
+    _check_samples(k, os_, range(B), "resumed")
+    assert k.time == g.time == 159
+
+
+def test_partial_observables(ea_gpu, oracle_mod):
+    L, B = 16, 8
+    g = ea_gpu.Msc(L, B, 0.5, 0.8, seed=4, sample0=2, shared=3, n_slots=1)
+    os_ = oracle_mod.shared_batch(L, 0.5, 0.8, seed=4, sample0=2, n_samples=B, shared_id=3, n_slots=1)
+    g.snapshot(0)
+    for o in os_:
+        o.snapshot(0)
+    g.sweep(4)
+    for o in os_:
+        o.sweep(4)
+    no_c4 = g.measure(c4=False)
+    no_ac = g.measure(autocorr=False)
+    for b in range(B):
+        oo = os_[b].measure()
+        assert no_c4[b].c4 is None and list(no_c4[b].unsat) == list(oo.unsat)
+        assert np.array_equal(no_c4[b].autocorr, oo.autocorr)
+        assert np.array_equal(no_ac[b].c4, oo.c4) and no_ac[b].autocorr.size == 0
+
+
+def test_full_size_sampled(ea_gpu, oracle_mod):
+    """The 128^3 batch of 32 samples (the paper's system size): two samples
+    checked against the oracle after two sweeps, the rest by invariants."""
+    L, B = 128, 32
+    _say("msc L=128 B=32")
+    g = ea_gpu.Msc(L, B, 0.5, 0.8, seed=1, sample0=0, shared=5)
+    g.sweep(2)
+    for b in (0, 31):
+        o = oracle_mod.Sim(L, 0.5, 0.8, seed=1, sample=b)
+        o.share_noise(5)
+        o.sweep(2)
+        for r in (0, 1):
+            assert np.array_equal(g.spins(b, r), o.spins(r)), (b, r)
+    obs = g.measure()
+    N = L ** 3
+    for b, ob in enumerate(obs):
+        assert ob.t == 2
+        assert all(0 <= u <= 3 * N for u in ob.unsat)
+        assert ob.c4[0][0] == ob.c4[1][0] == ob.c4[2][0] == N
+        # two sweeps from a random start already lower the energy a lot
+        assert all(u < 1.2 * N for u in ob.unsat), (b, ob.unsat)
+
+
+def test_msc_errors(ea_gpu):
+    for L, B in [(16, 3), (16, 0), (16, 128), (24, 1), (40, 2), (8, 4), (12, 32)]:
+        with pytest.raises(ea_gpu.EAError):
+            ea_gpu.Msc(L, B, 0.5, 0.8, seed=1)
+    with pytest.raises(ea_gpu.EAError):
+        ea_gpu.Msc(16, 32, 1.5, 0.8, seed=1)
+    with pytest.raises(ea_gpu.EAError):
+        ea_gpu.Msc(16, 32, 0.5, -1.0, seed=1)
+    g = ea_gpu.Msc(16, 8, 0.5, 0.8, seed=1, n_slots=1)
+    with pytest.raises(ea_gpu.EAError):
+        g.spins(8, 0)
+    with pytest.raises(ea_gpu.EAError):
+        g.spins(-1, 0)
+    with pytest.raises(ea_gpu.EAError):
+        g.spins(0, 2)
+    with pytest.raises(ea_gpu.EAError):
+        g.snapshot(1)
+    bad = np.ones(16 ** 3, dtype=np.int8)
+    bad[5] = 0
+    with pytest.raises(ea_gpu.EAError):
+        g.set_spins(0, 0, bad)
+    g.set_time((1 << 32) - 3)
+    with pytest.raises(ea_gpu.EAError):
+        g.sweep(3)
+    g.sweep(2)
+    assert g.time == (1 << 32) - 1
