@@ -212,6 +212,57 @@ def plain_rate(ea, torch, L: int, sweeps: int = 256) -> float:
     return ms * 1e-3 / (sweeps * 2 * L ** 3) * 1e12
 
 
+def bench_msc(ea, torch, job, burst: int):
+    """The multispin-coded batch (asynchronous multispin coding, shared random
+    words) on the paper's production configuration: the whole schedule once
+    (sweeps, snapshots, measurements; wall clock), then a burst of sweeps
+    timed with events on the batch's stream for the half-step launch."""
+    warm = ea.Msc(job.L, job.n_samples, job.p, job.T, seed=job.seed, sample0=job.sample, shared=0)
+    warm.sweep(64)  # loads the kernels; each handle captures its own graph on its first long run
+    warm.close()
+    g = ea.Msc(job.L, job.n_samples, job.p, job.T, seed=job.seed, sample0=job.sample, shared=0,
+               n_slots=len(job.tw))
+    g.sync()
+    w0 = time.perf_counter()
+    t_now, n_meas = 0, 0
+    for t, slots, meas in job.events():
+        g.sweep(t - t_now)
+        t_now = t
+        for k in slots:
+            g.snapshot(k)
+        if meas:
+            g.measure()
+            n_meas += 1
+    g.sweep(job.n_sweeps - t_now)
+    g.sync()
+    run_s = time.perf_counter() - w0
+    b0 = torch.cuda.Event(enable_timing=True)
+    b1 = torch.cuda.Event(enable_timing=True)
+    b0.record(g.stream)
+    g.sweep(burst)
+    b1.record(g.stream)
+    torch.cuda.synchronize()
+    half_us = b0.elapsed_time(b1) * 1e3 / (2 * burst)
+    g.close()
+    L, B = job.L, job.n_samples
+    words = B // min(B, 32) * (L // 2) * L * L  # words per plane (P) times word sets
+    alg_bytes = 48 * words  # per half-step: 2 replicas x (read 2 planes, write 1) + 6 coupling planes, 4 B each
+    flips_half = L ** 3 * B  # both replicas, half the sites each
+    gbs = alg_bytes / (half_us * 1e-6) / 1e9
+    return {
+        "workload": f"multispin-coded batch: L={L}, {B} samples x 2 replicas sharing one random word per "
+                    f"site and sweep, p={job.p}, T={job.T}, {job.n_sweeps} sweeps, {n_meas} measurements, "
+                    f"tw={job.tw}; one launch per half-step",
+        "ps_per_flip": round(run_s / job.flips * 1e12, 4),
+        "ps_per_flip_sweeps": round(half_us * 1e-6 / flips_half * 1e12, 4),
+        "half_step_avg_us": round(half_us, 3),
+        "roofline": {"bound": "hbm", "kernel": "msc_half_step_kernel", "achieved": round(gbs, 1),
+                     "peak": 8000.0, "unit": "GB/s", "frac": round(gbs / 8000.0, 4),
+                     "alg_bytes_per_launch": alg_bytes, "traffic": None},
+        "vs_paper_8ps": round(8.0 / (run_s / job.flips * 1e12), 1),
+    }
+
+
 SERVE_SIZES = (16, 24, 32, 48, 64, 96, 128)
 
 
@@ -281,6 +332,11 @@ def main():
     ap.add_argument("--serve-load2", type=float, default=0.5,
                     help="a second, lighter offered load reported beside it (0 = skip)")
     ap.add_argument("--serve-sweeps", type=int, default=10_000, help="upper end of the serving sweep range")
+    ap.add_argument("--msc-sweeps", type=int, default=10_000,
+                    help="sweeps of the multispin-coded batch (0 = skip that leg)")
+    ap.add_argument("--msc-samples", type=int, default=64, help="samples of the multispin-coded batch")
+    ap.add_argument("--msc-burst", type=int, default=1024, help="sweeps in its kernel-timing burst")
+    ap.add_argument("--msc-only", action="store_true", help="run only the multispin-coded leg and print it")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (a known-size kernel "
                          "for calibrating hardware byte counters) and exit")
@@ -307,6 +363,11 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": n, "read": n, "written": n}), flush=True)
+        return
+
+    if args.msc_only:
+        print(json.dumps({"msc": bench_msc(ea, torch, wl.msc_job(args.msc_sweeps, args.msc_samples),
+                                           args.msc_burst)}), flush=True)
         return
 
     jobs = wl.batch_jobs(n_jobs=args.jobs, n_sweeps=args.sweeps)
@@ -412,6 +473,9 @@ def main():
             log(f"serving form at load {args.serve_load2} ...")
             out["serving_light"] = bench_serving(ea, torch, wl, args.serve_jobs, args.serve_load2,
                                                  args.serve_sweeps, ps_per_flip)
+    if args.msc_sweeps:
+        log("multispin-coded batch ...")
+        out["msc"] = bench_msc(ea, torch, wl.msc_job(args.msc_sweeps, args.msc_samples), args.msc_burst)
     if not args.no_plain:
         log("plain form ...")
         plain = bench_plain(ea, torch, wl.mid_job(args.sweeps), args.plain_steps, args.burst)

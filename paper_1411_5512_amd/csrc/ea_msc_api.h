@@ -91,16 +91,11 @@ ea_status msc_layout(const ea_msc_config *cfg, MscLayout &y)
 ea_status msc_half_step(ea_msc *s, int half, uint32_t t_off)
 {
     const ea::MscGeom g = s->geom;
-    const dim3 grid(blocks_for((size_t)g.q), 2, 1);
-    if (s->G == 2) {
-        hipLaunchKernelGGL((ea::msc_half_step_kernel<32, 2>), grid, dim3(256), 0, s->stream, s->lat, g, half,
-                           s->t_dev, t_off, key_lo_u64(s->seed), key_hi_u64(s->seed), s->shared, s->thr[0],
-                           s->thr[1], s->thr[2]);
-    } else {
-        EA_DISPATCH_M(s->M, hipLaunchKernelGGL((ea::msc_half_step_kernel<MM, 1>), grid, dim3(256), 0, s->stream,
-                                                s->lat, g, half, s->t_dev, t_off, key_lo_u64(s->seed),
-                                                key_hi_u64(s->seed), s->shared, s->thr[0], s->thr[1], s->thr[2]));
-    }
+    // two blocks (one per replica) per tile of 256 threads; grid.y = word set
+    const dim3 grid(2 * blocks_for((size_t)g.q), (unsigned)s->G, 1);
+    EA_DISPATCH_M(s->M, hipLaunchKernelGGL((ea::msc_half_step_kernel<MM>), grid, dim3(256), 0, s->stream, s->lat,
+                                            g, half, s->t_dev, t_off, key_lo_u64(s->seed), key_hi_u64(s->seed),
+                                            s->shared, s->thr[0], s->thr[1], s->thr[2]));
     return EA_OK;
 }
 
@@ -322,7 +317,7 @@ ea_status ea_msc_measure(ea_msc *s, ea_obs *out)
                                             s->snaps, s->spin_words, s->G, s->meas));
     unsigned long long *c4_acc = s->meas + (size_t)kMscQuantities * s->G * 32;
     if (any_c4) {
-        const unsigned nblk_c4 = (unsigned)std::min<size_t>(blocks_for(2 * (size_t)g.P), 128);
+        const unsigned nblk_c4 = (unsigned)std::min<size_t>(blocks_for(2 * (size_t)g.P), 64);
         const dim3 grid_c4(nblk_c4, 3 * (unsigned)(g.R + 1), (unsigned)s->G);
         EA_DISPATCH_M(s->M, hipLaunchKernelGGL((ea::msc_c4_kernel<MM>), grid_c4, dim3(256), 0, s->stream, s->lat,
                                                 g, s->G, c4_acc));

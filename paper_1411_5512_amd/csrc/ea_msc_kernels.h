@@ -121,22 +121,34 @@ __global__ __launch_bounds__(256) void msc_init_kernel(MscLattice lat, MscGeom g
 
 // --------------------------------------------------------------------------
 // One checkerboard half-step (Sec. III, eq. 9) of every sample of the batch.
-// grid.y = replica r, which updates colour c = r ^ half (the interlaced
-// order).  One thread per four consecutive xh of a row of one replica: for
-// each slab k it draws one Philox block whose four words are the shared
-// words of its four sites, turns them into per-bit threshold masks, and then
-// decides all M S bits of each of its G words with the bit-sliced count of
-// unsatisfied bonds.
-template <int M, int G>
+// Replica r updates colour c = r ^ half (the interlaced order).  One thread
+// per four consecutive xh of a row of one replica and word set: for each slab
+// k it draws one Philox block whose four words are the shared words of its
+// four sites, turns them into per-bit threshold masks, and then decides all
+// M S bits of each word with the bit-sliced count of unsatisfied bonds.
+//
+// Block order.  Blocks go to the 8 XCDs in turn (block b to XCD b mod 8), so
+// logical block (b mod 8) n/8 + b/8 gives each XCD a contiguous run of tiles
+// -- a z-slab, whose neighbour rows then sit in that XCD's L2 -- and logical
+// block 2 tile + r puts the two replicas of a tile side by side, so that their
+// reads of the shared couplings meet in L2.  grid.y = word set.
+__device__ __forceinline__ int xcd_block(int b, int n)
+{
+    return (n & 7) ? b : (b & 7) * (n >> 3) + (b >> 3);
+}
+
+template <int M>
 __global__ __launch_bounds__(256) void msc_half_step_kernel(MscLattice lat, MscGeom g, int half,
                                                             const uint32_t *__restrict__ t_base, uint32_t t_off,
                                                             uint32_t k0, uint32_t k1, uint32_t shared,
                                                             uint32_t thr1, uint32_t thr2, uint32_t thr3)
 {
     constexpr int S = 32 / M;
-    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int r = lb & 1;
+    const int tid = (lb >> 1) * (int)blockDim.x + (int)threadIdx.x;
     if (tid >= g.q) return;
-    const int r = blockIdx.y;
+    const int gi = blockIdx.y;
     const int c = r ^ half;
     const int R4 = g.R >> 2;
     const int row = tid / R4;
@@ -169,8 +181,7 @@ __global__ __launch_bounds__(256) void msc_half_step_kernel(MscLattice lat, MscG
     const size_t at = (size_t)row * R + xh0;
     const size_t edge = (size_t)row * R + (par ? (xh0 + 4 == R ? 0 : xh0 + 4) : (xh0 == 0 ? R - 1 : xh0 - 1));
     const size_t left = (size_t)row * R + (xh0 == 0 ? R - 1 : xh0 - 1);
-#pragma unroll
-    for (int gi = 0; gi < G; ++gi) {
+    {
         uint32_t *own = lat.spins + msc_spin_plane(g, gi, r, c);
         const uint32_t *oth = lat.spins + msc_spin_plane(g, gi, r, c ^ 1);
         const uint32_t *bx_own = lat.bonds + msc_bond_plane(g, gi, 0, c);
@@ -227,25 +238,56 @@ __global__ __launch_bounds__(256) void msc_half_step_kernel(MscLattice lat, MscG
 
 // --------------------------------------------------------------------------
 // Measurements (eqs. 1, 2, 3, 7) sample by sample.  Every bit of a word is a
-// different (sample, slab), so the sums are per-bit counts: each lane visits
-// words, and for each bit b a wave ballot of that bit, counted, goes to lane
-// b's accumulator.  The block adds its waves' counts in LDS and then to the
-// device counters, laid out [quantity][G][32 bits]; the host adds the S
-// bits k M + m of each sample m.
+// different (sample, slab), so the sums are per-bit counts.  Each lane visits
+// words and adds every per-bit quantity into a bit-sliced counter: eight
+// planes holding, bit by bit, the binary digits of a count up to 255.  Every
+// 255 words, and at the end, each plane is counted across the wave with one
+// ballot per bit, weighted 2^j for plane j, into lane b's accumulator of bit
+// b.  The block adds its waves' accumulators in LDS and then to the device
+// counters, laid out [quantity][G][32 bits]; the host adds the S bits k M + m
+// of each sample m.
 enum { MSC_UNSAT = 0, MSC_DOWN = 2, MSC_QDIFF = 4, MSC_AUTO = 5 };
 
-// Adds to lane b of acc, for b < 32, the number of lanes whose x has bit b set.
-__device__ __forceinline__ void count_bits(uint32_t x, uint32_t &acc)
+constexpr int kPlanes = 8;
+constexpr int kPlaneMax = (1 << kPlanes) - 1;
+
+struct BitCounter {
+    uint32_t c[kPlanes];
+};
+
+__device__ __forceinline__ void bc_zero(BitCounter &k)
 {
-    const uint32_t lane = threadIdx.x & 63u;
 #pragma unroll
-    for (uint32_t b = 0; b < 32; ++b) {
-        const uint32_t n = (uint32_t)__popcll(__ballot((x >> b) & 1u));
-        acc += lane == b ? n : 0u;
+    for (int j = 0; j < kPlanes; ++j) k.c[j] = 0u;
+}
+
+// Ripple-carry add of one bit per position.
+__device__ __forceinline__ void bc_add(BitCounter &k, uint32_t x)
+{
+#pragma unroll
+    for (int j = 0; j < kPlanes; ++j) {
+        const uint32_t carry = k.c[j] & x;
+        k.c[j] ^= x;
+        x = carry;
     }
 }
 
-// Block sum of up to 5 per-bit accumulators, then one atomic per bit and
+// Lane b (< 32) of acc gains the wave's total count of bit b; the counter is cleared.
+__device__ __forceinline__ void bc_flush(BitCounter &k, uint32_t &acc)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+#pragma unroll
+    for (int j = 0; j < kPlanes; ++j) {
+#pragma unroll
+        for (uint32_t b = 0; b < 32; ++b) {
+            const uint32_t n = (uint32_t)__popcll(__ballot((k.c[j] >> b) & 1u));
+            acc += lane == b ? (n << j) : 0u;
+        }
+        k.c[j] = 0u;
+    }
+}
+
+// Block sum of NQ per-bit accumulators, then one atomic per bit and
 // quantity: dst[k] receives quantity k's 32 counts.
 template <int NQ>
 __device__ __forceinline__ void block_flush(const uint32_t (&acc)[NQ], unsigned long long *const (&dst)[NQ])
@@ -263,23 +305,42 @@ __device__ __forceinline__ void block_flush(const uint32_t (&acc)[NQ], unsigned 
         if (red[i / 32][i % 32]) atomicAdd(dst[i / 32] + (i % 32), (unsigned long long)red[i / 32][i % 32]);
 }
 
-// Word idx of the 2P words of one word set and replica pair: colour, row and xh.
-struct MscSite {
-    int c, hw, row, xh, y, z, par;
-};
+// Walk over the 2P words of a word set (colour-major, then z, y, xh) with a
+// fixed stride, the coordinates kept by carries instead of divisions.
+struct MscWalk {
+    int xh, y, z, c;
+    int dxh, dy, dz, dc;
 
-__device__ __forceinline__ MscSite msc_site(const MscGeom &g, int idx)
-{
-    MscSite s;
-    s.c = idx >= g.P;
-    s.hw = idx - s.c * g.P;
-    s.row = s.hw / g.R;
-    s.xh = s.hw - s.row * g.R;
-    s.y = s.row % g.L;
-    s.z = s.row / g.L;
-    s.par = (s.y + s.z + s.c) & 1;
-    return s;
-}
+    __device__ __forceinline__ void init(const MscGeom &g, int start, int stride)
+    {
+        xh = start % g.R;
+        int rem = start / g.R;
+        y = rem % g.L;
+        rem /= g.L;
+        z = rem % g.Lz;
+        c = rem / g.Lz;
+        dxh = stride % g.R;
+        rem = stride / g.R;
+        dy = rem % g.L;
+        rem /= g.L;
+        dz = rem % g.Lz;
+        dc = rem / g.Lz;
+    }
+    __device__ __forceinline__ void next(const MscGeom &g)
+    {
+        xh += dxh;
+        int carry = xh >= g.R;
+        xh -= carry ? g.R : 0;
+        y += dy + carry;
+        carry = y >= g.L;
+        y -= carry ? g.L : 0;
+        z += dz + carry;
+        carry = z >= g.Lz;
+        z -= carry ? g.Lz : 0;
+        c += dc + carry;
+    }
+    __device__ __forceinline__ bool live() const { return c < 2; }
+};
 
 // grid.y = 0: unsatisfied bonds, down spins and the overlap; grid.y = 1 + k:
 // the autocorrelation with slot k.  grid.z = word set.
@@ -291,28 +352,38 @@ __global__ __launch_bounds__(256) void msc_measure_kernel(MscLattice lat, MscGeo
     const int gi = blockIdx.z;
     const int what = blockIdx.y;
     const int R = g.R;
-    const size_t stride = (size_t)n_sets * 32;
+    const int stride = gridDim.x * blockDim.x;
+    const int n_it = (2 * g.P + stride - 1) / stride;
+    MscWalk w;
+    w.init(g, blockIdx.x * blockDim.x + threadIdx.x, stride);
+    const size_t sstride = (size_t)n_sets * 32;
     unsigned long long *base = acc + (size_t)gi * 32;
     if (what == 0) {
+        BitCounter k[5];
         uint32_t cnt[5] = {0u, 0u, 0u, 0u, 0u};
-        for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx - (int)threadIdx.x < 2 * g.P;
-             idx += gridDim.x * blockDim.x) {
-            // every lane reaches the ballots; lanes past the end count zeros
+#pragma unroll
+        for (int q = 0; q < 5; ++q) bc_zero(k[q]);
+        for (int it = 0, run = 0; it < n_it; ++it) {
+            // every lane reaches the flushes; lanes past the end add zeros
             uint32_t s0 = 0u, s1 = 0u, un0[3] = {0u, 0u, 0u}, un1[3] = {0u, 0u, 0u};
-            if (idx < 2 * g.P) {
-                const MscSite st = msc_site(g, idx);
-                s0 = lat.spins[msc_spin_plane(g, gi, 0, st.c) + st.hw];
-                s1 = lat.spins[msc_spin_plane(g, gi, 1, st.c) + st.hw];
+            if (w.live()) {
+                const int c = w.c;
+                const int row = w.y + g.L * w.z;
+                const size_t hw = (size_t)row * R + w.xh;
+                const int par = (w.y + w.z + c) & 1;
+                s0 = lat.spins[msc_spin_plane(g, gi, 0, c) + hw];
+                s1 = lat.spins[msc_spin_plane(g, gi, 1, c) + hw];
                 // bonds to +x, +y, +z, each counted at the site that stores it
-                const int xn = st.par ? (st.xh + 1 == R ? 0 : st.xh + 1) : st.xh;
-                const bool top = st.z + 1 == g.Lz;
-                const size_t nb[3] = {(size_t)st.row * R + xn, (size_t)(wrap(st.y + 1, g.L) + g.L * st.z) * R + st.xh,
-                                      (size_t)(st.y + g.L * (top ? 0 : st.z + 1)) * R + st.xh};
+                const int xn = par ? (w.xh + 1 == R ? 0 : w.xh + 1) : w.xh;
+                const bool top = w.z + 1 == g.Lz;
+                const size_t nb[3] = {(size_t)row * R + xn,
+                                      (size_t)((w.y + 1 == g.L ? 0 : w.y + 1) + g.L * w.z) * R + w.xh,
+                                      (size_t)(w.y + g.L * (top ? 0 : w.z + 1)) * R + w.xh};
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    const uint32_t J = lat.bonds[msc_bond_plane(g, gi, d, st.c) + st.hw];
-                    uint32_t n0 = lat.spins[msc_spin_plane(g, gi, 0, st.c ^ 1) + nb[d]];
-                    uint32_t n1 = lat.spins[msc_spin_plane(g, gi, 1, st.c ^ 1) + nb[d]];
+                    const uint32_t J = lat.bonds[msc_bond_plane(g, gi, d, c) + hw];
+                    uint32_t n0 = lat.spins[msc_spin_plane(g, gi, 0, c ^ 1) + nb[d]];
+                    uint32_t n1 = lat.spins[msc_spin_plane(g, gi, 1, c ^ 1) + nb[d]];
                     if (d == 2 && top) {
                         n0 = from_slab_above<M>(n0);
                         n1 = from_slab_above<M>(n1);
@@ -321,36 +392,52 @@ __global__ __launch_bounds__(256) void msc_measure_kernel(MscLattice lat, MscGeo
                     un1[d] = xor3(s1, n1, J);
                 }
             }
+            w.next(g);
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                count_bits(un0[d], cnt[0]);
-                count_bits(un1[d], cnt[1]);
+                bc_add(k[0], un0[d]);
+                bc_add(k[1], un1[d]);
             }
-            count_bits(s0, cnt[2]);
-            count_bits(s1, cnt[3]);
-            count_bits(s0 ^ s1, cnt[4]);
+            bc_add(k[2], s0);
+            bc_add(k[3], s1);
+            bc_add(k[4], s0 ^ s1);
+            // three unsatisfied-bond words per site: flush before 255 can be passed
+            if (++run == kPlaneMax / 3 || it + 1 == n_it) {
+                run = 0;
+#pragma unroll
+                for (int q = 0; q < 5; ++q) bc_flush(k[q], cnt[q]);
+            }
         }
-        unsigned long long *const dst[5] = {base + MSC_UNSAT * stride, base + (MSC_UNSAT + 1) * stride,
-                                            base + MSC_DOWN * stride, base + (MSC_DOWN + 1) * stride,
-                                            base + MSC_QDIFF * stride};
+        unsigned long long *const dst[5] = {base + MSC_UNSAT * sstride, base + (MSC_UNSAT + 1) * sstride,
+                                            base + MSC_DOWN * sstride, base + (MSC_DOWN + 1) * sstride,
+                                            base + MSC_QDIFF * sstride};
         block_flush<5>(cnt, dst);
     } else {
         const uint32_t *snap = snaps + (size_t)(what - 1) * snap_words;
+        BitCounter k[2];
         uint32_t cnt[2] = {0u, 0u};
-        for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx - (int)threadIdx.x < 2 * g.P;
-             idx += gridDim.x * blockDim.x) {
+        bc_zero(k[0]);
+        bc_zero(k[1]);
+        for (int it = 0, run = 0; it < n_it; ++it) {
             uint32_t d0 = 0u, d1 = 0u;
-            if (idx < 2 * g.P) {
-                const MscSite st = msc_site(g, idx);
-                d0 = lat.spins[msc_spin_plane(g, gi, 0, st.c) + st.hw] ^ snap[msc_spin_plane(g, gi, 0, st.c) + st.hw];
-                d1 = lat.spins[msc_spin_plane(g, gi, 1, st.c) + st.hw] ^ snap[msc_spin_plane(g, gi, 1, st.c) + st.hw];
+            if (w.live()) {
+                const size_t hw = (size_t)(w.y + g.L * w.z) * R + w.xh;
+                const size_t p0 = msc_spin_plane(g, gi, 0, w.c) + hw, p1 = msc_spin_plane(g, gi, 1, w.c) + hw;
+                d0 = lat.spins[p0] ^ snap[p0];
+                d1 = lat.spins[p1] ^ snap[p1];
             }
-            count_bits(d0, cnt[0]);
-            count_bits(d1, cnt[1]);
+            w.next(g);
+            bc_add(k[0], d0);
+            bc_add(k[1], d1);
+            if (++run == kPlaneMax || it + 1 == n_it) {
+                run = 0;
+                bc_flush(k[0], cnt[0]);
+                bc_flush(k[1], cnt[1]);
+            }
         }
-        const int k = what - 1;
-        unsigned long long *const dst[2] = {base + (MSC_AUTO + 2 * k) * stride,
-                                            base + (MSC_AUTO + 2 * k + 1) * stride};
+        const int kk = what - 1;
+        unsigned long long *const dst[2] = {base + (MSC_AUTO + 2 * kk) * sstride,
+                                            base + (MSC_AUTO + 2 * kk + 1) * sstride};
         block_flush<2>(cnt, dst);
     }
 }
@@ -365,32 +452,50 @@ __global__ __launch_bounds__(256) void msc_c4_kernel(MscLattice lat, MscGeom g, 
     const int gi = blockIdx.z;
     const int d = blockIdx.y / (g.R + 1), rho = blockIdx.y - d * (g.R + 1);
     const int R = g.R;
+    const int stride = gridDim.x * blockDim.x;
+    const int n_it = (2 * g.P + stride - 1) / stride;
+    // a z displacement crosses up_base slab faces, plus one more when the
+    // reduced z passes Lz
+    const int up_base = rho / g.Lz, z_rem = rho - up_base * g.Lz;
+    MscWalk w;
+    w.init(g, blockIdx.x * blockDim.x + threadIdx.x, stride);
+    BitCounter k;
+    bc_zero(k);
     uint32_t cnt[1] = {0u};
-    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx - (int)threadIdx.x < 2 * g.P;
-         idx += gridDim.x * blockDim.x) {
+    for (int it = 0, run = 0; it < n_it; ++it) {
         uint32_t diff = 0u;
-        if (idx < 2 * g.P) {
-            const MscSite st = msc_site(g, idx);
-            const int x = 2 * st.xh + st.par;
-            const int c2 = st.c ^ (rho & 1);
+        if (w.live()) {
+            const int c = w.c;
+            const int row = w.y + g.L * w.z;
+            const int c2 = c ^ (rho & 1);
             size_t w2;
-            int up = 0;  // slabs crossed along z
+            int up = 0;
             if (d == 0) {
-                const int x2 = (x + rho) % g.L;
-                w2 = (size_t)st.row * R + (x2 >> 1);
+                int x2 = 2 * w.xh + ((w.y + w.z + c) & 1) + rho;
+                x2 -= x2 >= g.L ? g.L : 0;
+                w2 = (size_t)row * R + (x2 >> 1);
             } else if (d == 1) {
-                w2 = (size_t)(((st.y + rho) % g.L) + g.L * st.z) * R + st.xh;
+                int y2 = w.y + rho;
+                y2 -= y2 >= g.L ? g.L : 0;
+                w2 = (size_t)(y2 + g.L * w.z) * R + w.xh;
             } else {
-                const int zz = st.z + rho;
-                up = zz / g.Lz;
-                w2 = (size_t)(st.y + g.L * (zz - up * g.Lz)) * R + st.xh;
+                int z2 = w.z + z_rem;
+                const int wrap_z = z2 >= g.Lz;
+                z2 -= wrap_z ? g.Lz : 0;
+                up = up_base + wrap_z;
+                w2 = (size_t)(w.y + g.L * z2) * R + w.xh;
             }
-            const uint32_t q = lat.spins[msc_spin_plane(g, gi, 0, st.c) + st.hw] ^
-                               lat.spins[msc_spin_plane(g, gi, 1, st.c) + st.hw];
+            const size_t hw = (size_t)row * R + w.xh;
+            const uint32_t q = lat.spins[msc_spin_plane(g, gi, 0, c) + hw] ^ lat.spins[msc_spin_plane(g, gi, 1, c) + hw];
             const uint32_t q2 = lat.spins[msc_spin_plane(g, gi, 0, c2) + w2] ^ lat.spins[msc_spin_plane(g, gi, 1, c2) + w2];
             diff = q ^ from_slabs_above<M>(q2, up);
         }
-        count_bits(diff, cnt[0]);
+        w.next(g);
+        bc_add(k, diff);
+        if (++run == kPlaneMax || it + 1 == n_it) {
+            run = 0;
+            bc_flush(k, cnt[0]);
+        }
     }
     unsigned long long *const dst[1] = {acc + ((size_t)blockIdx.y * n_sets + gi) * 32};
     block_flush<1>(cnt, dst);

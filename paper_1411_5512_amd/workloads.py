@@ -44,11 +44,12 @@ class Job:
     n_sweeps: int = 0
     meas_t: list = field(default_factory=list)   # sorted measurement times
     tw: list = field(default_factory=list)       # sorted snapshot (waiting) times
+    n_samples: int = 1                           # samples run together (multispin batch)
 
     @property
     def flips(self) -> int:
-        """Attempted single-spin updates of the whole run (both replicas)."""
-        return 2 * self.L ** 3 * self.n_sweeps
+        """Attempted single-spin updates of the whole run (both replicas, every sample)."""
+        return 2 * self.L ** 3 * self.n_sweeps * self.n_samples
 
     def events(self):
         """Chronological (time, snapshot_slots, measure) events."""
@@ -79,6 +80,16 @@ def crossover_jobs(n_sweeps: int = 1_000_000) -> list[Job]:
     return [Job(128, p, 0.7, seed=1, sample=0, n_sweeps=n_sweeps,
                 meas_t=sorted(set(meas) | set(tw)), tw=tw)
             for p in (0.5, 0.3, 0.25, 0.2, 0.15)]
+
+
+def msc_job(n_sweeps: int = 10_000, n_samples: int = 64) -> Job:
+    """The paper's production batch (Sec. IV): L = 128, p = 0.5, T = 0.8, the
+    samples of one multispin word set (64 by default) sharing the random words,
+    20 log-spaced measurements and t_w in {10^2, 10^3}.  `sample` is the
+    first sample; the batch has n_samples of them."""
+    tw = [t for t in (100, 1000) if t <= n_sweeps]
+    meas = sorted(set(log_schedule(n_sweeps, 20)) | set(tw))
+    return Job(128, 0.5, 0.8, seed=1, sample=0, n_sweeps=n_sweeps, meas_t=meas, tw=tw, n_samples=n_samples)
 
 
 def batch_jobs(n_jobs: int = 256, n_sweeps: int = 100_000, gen_seed: int = 4) -> list[Job]:
