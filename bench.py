@@ -47,35 +47,38 @@ ALG_OPS_PER_FLIP = 40 / 4 + 1
 # on; reported only while the sources still hash the same.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batch_kernel_mixed256_traffic.txt")
 KERNEL_SOURCES = ("ea_device.h", "ea_kernels.h", "ea_batch_kernels.h", "ea_batch_api.h")
+# the same for the multispin half-step on the paper's production batch
+MSC_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "msc_half_step_L128_B64_traffic.txt")
+MSC_SOURCES = ("ea_device.h", "ea_msc_kernels.h", "ea_msc_api.h")
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(sources=None) -> str:
     import hashlib
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in sources or KERNEL_SOURCES:
         h.update(name.encode() + b"\0")
         with open(os.path.join(ROOT, "paper_1411_5512_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def measured_record():
+def measured_record(path=None, sources=None):
     """The recorded counters (dict) if they were taken on the current kernel
-    sources, else (None, reason)."""
+    sources, else (None, reason).  Defaults: the batched kernel's record."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path or TRAFFIC_FILE) as f:
             kv = dict(line.split(None, 1) for line in f if line.strip() and not line.startswith("#"))
     except OSError:
         return None, "no counter record"
     kv = {k: v.strip() for k, v in kv.items()}
-    if kv.get("source_sha256") != kernel_source_hash():
+    if kv.get("source_sha256") != kernel_source_hash(sources):
         return None, "kernel changed since the counters were taken"
     return kv, kv.get("workload", "")
 
 
-def measured_traffic():
+def measured_traffic(path=None, sources=None):
     """(HBM bytes per launch, provenance) from the record, or (None, reason)."""
-    kv, why = measured_record()
+    kv, why = measured_record(path, sources)
     if kv is None:
         return None, why
     return int(kv["fetch_bytes"]) + int(kv["write_bytes"]), why
@@ -249,6 +252,9 @@ def bench_msc(ea, torch, job, burst: int):
     alg_bytes = 48 * words  # per half-step: 2 replicas x (read 2 planes, write 1) + 6 coupling planes, 4 B each
     flips_half = L ** 3 * B  # both replicas, half the sites each
     gbs = alg_bytes / (half_us * 1e-6) / 1e9
+    # the record holds the counters of the 64-sample batch at L = 128
+    traffic, traffic_src = (measured_traffic(MSC_TRAFFIC_FILE, MSC_SOURCES) if (L, B) == (128, 64)
+                            else (None, "no counter record for this batch"))
     return {
         "workload": f"multispin-coded batch: L={L}, {B} samples x 2 replicas sharing one random word per "
                     f"site and sweep, p={job.p}, T={job.T}, {job.n_sweeps} sweeps, {n_meas} measurements, "
@@ -258,7 +264,9 @@ def bench_msc(ea, torch, job, burst: int):
         "half_step_avg_us": round(half_us, 3),
         "roofline": {"bound": "hbm", "kernel": "msc_half_step_kernel", "achieved": round(gbs, 1),
                      "peak": 8000.0, "unit": "GB/s", "frac": round(gbs / 8000.0, 4),
-                     "alg_bytes_per_launch": alg_bytes, "traffic": None},
+                     "alg_bytes_per_launch": alg_bytes, "traffic": traffic, "traffic_source": traffic_src,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "traffic_frac": (round(traffic / (half_us * 1e-6) / 1e9 / 8000.0, 4) if traffic else None)},
         "vs_paper_8ps": round(8.0 / (run_s / job.flips * 1e12), 1),
     }
 

@@ -384,9 +384,10 @@ ea_status ea_server_stats(ea_server *s, ea_server_report *out);
  * Packing.  A 32-bit word holds M = min(n_samples, 32) samples; with fewer
  * than 32 the lattice is cut along z into 32 / M slabs whose same-position
  * sites share a word, a neighbour across a slab face being the word rotated
- * by M bits (the slab split of Sec. III); n_samples = 64 uses two words per
- * site that share the random words, as the paper's 64-bit words do.  The
- * packing changes no result, only the work per random word.
+ * by M bits (the slab split of Sec. III); n_samples = 32 G (G up to 8) uses
+ * G words per site that share the random words, as the paper's 64-bit words
+ * do for G = 2.  The packing changes no result, only the work per random
+ * word.
  *
  * Device memory: (3 + 2 (1 + n_tw_slots)) n_samples L^3 / 8 bytes of words
  * plus counters (ea_msc_footprint).  Calls follow the one-sample form:
@@ -396,7 +397,7 @@ typedef struct ea_msc ea_msc;
 
 typedef struct {
     int32_t L;            /* multiple of 8 in 8..256, and of 64 / n_samples when n_samples < 32 */
-    int32_t n_samples;    /* 1, 2, 4, 8, 16, 32 or 64 */
+    int32_t n_samples;    /* 1, 2, 4, 8, 16, or a multiple of 32 up to 256 */
     double p;             /* P(J = -1), in [0, 1] */
     double T;             /* temperature >= 0, finite */
     uint64_t seed;        /* Philox key */

@@ -47,6 +47,7 @@ namespace {
 uint32_t key_lo_u64(uint64_t seed) { return (uint32_t)(seed & 0xffffffffu); }
 uint32_t key_hi_u64(uint64_t seed) { return (uint32_t)(seed >> 32); }
 
+constexpr int kMscMaxSamples = 256;  // eight word sets
 constexpr int kMscQuantities = ea::MSC_AUTO + 2 * kMaxSlots;  // counters before the C4 block
 
 struct MscLayout {
@@ -60,8 +61,9 @@ ea_status msc_layout(const ea_msc_config *cfg, MscLayout &y)
     if (!cfg) return fail(EA_ERR_ARG, "config is NULL");
     if (!valid_L(cfg->L)) return fail(EA_ERR_ARG, "L=%d must be a multiple of 8 in [8, %d]", cfg->L, kMaxL);
     const int B = cfg->n_samples;
-    if (B != 1 && B != 2 && B != 4 && B != 8 && B != 16 && B != 32 && B != 64)
-        return fail(EA_ERR_ARG, "n_samples=%d is not one of 1, 2, 4, 8, 16, 32, 64", B);
+    if (!(B == 1 || B == 2 || B == 4 || B == 8 || B == 16 || (B % 32 == 0 && B >= 32 && B <= kMscMaxSamples)))
+        return fail(EA_ERR_ARG, "n_samples=%d is not 1, 2, 4, 8, 16 or a multiple of 32 up to %d", B,
+                    kMscMaxSamples);
     y.L = cfg->L;
     y.B = B;
     y.M = B < 32 ? B : 32;
@@ -204,6 +206,8 @@ ea_status ea_msc_create(const ea_msc_config *cfg, ea_msc **out)
     s->geom.Lz = y.Lz;
     s->geom.P = y.P;
     s->geom.q = y.P / 4;
+    s->geom.by_r4.m = ((uint64_t)1 << 40) / (uint64_t)(y.R / 4) + 1;
+    s->geom.by_l.m = ((uint64_t)1 << 40) / (uint64_t)y.L + 1;
     s->p = cfg->p;
     s->T = cfg->T;
     s->seed = cfg->seed;

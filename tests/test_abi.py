@@ -70,3 +70,23 @@ def test_footprint_and_bad_arguments(ealib):
         st = ealib.lib().ea_create(args[0], args[1], args[2], 1, ctypes.byref(h))
         assert st == ealib.EA_ERR_ARG and not h.value
         assert ealib.lib().ea_last_error()
+
+
+def test_msc_footprint_and_bad_arguments(ealib):
+    """Host logic of the multispin-coded batch: device bytes (bits of every
+    sample's spins, couplings and snapshots, plus counters) and the packing
+    rules (32 / M slabs of even depth, word sets of 32 samples)."""
+    import paper_1411_5512_amd as ea
+    for L, B, slots in ((128, 64, 0), (128, 32, 2), (16, 8, 1), (64, 1, 0), (24, 16, 3), (8, 256, 0)):
+        fp = ea.Msc.footprint(L, B, slots)
+        # words per plane, all word sets: 32 samples per word; fewer samples fill
+        # the 32 bits with 32 / B slabs of L B / 32 planes each
+        words = (B // 32 if B >= 32 else 1) * (L // 2) * L * (L if B >= 32 else L * B // 32)
+        dense = 4 * words * (4 + 6 + 4 * slots)
+        counters = 8 * (5 + 2 * 64 + 3 * (L // 2 + 1)) * (max(B, 32) // 32) * 32
+        assert dense + counters <= fp < dense + counters + 5 * 256 + 256, (L, B, slots)
+    for L, B in ((16, 3), (16, 0), (16, 48), (16, 288), (24, 1), (40, 2), (8, 4), (12, 32), (264, 32)):
+        with pytest.raises(ea.EAError):
+            ea.Msc.footprint(L, B)
+    with pytest.raises(ea.EAError):
+        ea.Msc.footprint(16, 32, 65)

@@ -37,8 +37,8 @@ def _check_samples(g, os_, bs, ctx):
 
 
 # (L, n_samples): 32 per word; 16, 4 and 1 per word (2, 8 and 32 z-slabs);
-# 64 in two word sets
-PACKINGS = [(8, 32), (16, 32), (24, 16), (16, 4), (64, 1), (32, 2), (16, 64), (40, 8)]
+# 64, 96 and 256 in two, three and eight word sets
+PACKINGS = [(8, 32), (16, 32), (24, 16), (16, 4), (64, 1), (32, 2), (16, 64), (40, 8), (8, 96), (8, 256)]
 
 
 @pytest.mark.parametrize("L,B", PACKINGS)
@@ -56,6 +56,7 @@ def test_initial_state_matches_oracle(ea_gpu, oracle_mod, L, B):
     (8, 32, 0.5, 0.8, 12), (16, 32, 0.5, 0.8, 5), (24, 16, 0.3, 0.6, 4), (16, 4, 0.5, 1.2, 6),
     (64, 1, 0.5, 0.7, 2), (32, 2, 0.2, 0.7, 3), (16, 64, 0.5, 0.8, 3), (40, 8, 0.5, 0.9, 2),
     (8, 32, 0.0, 0.7, 10), (8, 32, 1.0, 0.7, 10), (8, 32, 0.5, 0.0, 10), (8, 8, 0.5, 3.0, 10),
+    (8, 96, 0.5, 0.8, 4),
 ])
 def test_sweeps_match_oracle(ea_gpu, oracle_mod, L, B, p, T, sweeps):
     _say(f"msc sweeps L={L} B={B} p={p} T={T} n={sweeps}")
@@ -151,7 +152,7 @@ def test_full_size_sampled(ea_gpu, oracle_mod):
 
 
 def test_msc_errors(ea_gpu):
-    for L, B in [(16, 3), (16, 0), (16, 128), (24, 1), (40, 2), (8, 4), (12, 32)]:
+    for L, B in [(16, 3), (16, 0), (16, 48), (16, 288), (24, 1), (40, 2), (8, 4), (12, 32)]:
         with pytest.raises(ea_gpu.EAError):
             ea_gpu.Msc(L, B, 0.5, 0.8, seed=1)
     with pytest.raises(ea_gpu.EAError):
