@@ -65,3 +65,62 @@ def test_samples_cutoff_and_tail():
     # without the tail the estimate is biased low but stays close for a cut far out
     est_no_tail, _, _ = an.xi_k_samples(r, curves, k=1, tail=False)
     assert est_no_tail <= est * 1.001
+
+
+# ---------------------------------------------------------------------------
+# The fitted-exponent analysis: each fit recovers the parameters of data made
+# from its own functional form (noise-free and with noise), on the grids the
+# measured series use.
+
+def test_multifit_recovers_shared_exponents():
+    r = np.arange(0, 65, dtype=np.float64)
+    alpha, beta = 0.45, 1.42
+    xis = np.array([2.0, 3.1, 4.5, 6.2])
+    amps = np.array([0.9, 0.8, 0.85, 0.7])
+    curves = np.array([an.c4_form(np.maximum(r, 1e-9), a, alpha, x, beta) for a, x in zip(amps, xis)])
+    fit = an.multifit_c4(r, curves, r_min=3.0)
+    assert abs(fit["alpha"] - alpha) < 1e-4 and abs(fit["beta"] - beta) < 1e-4
+    assert np.allclose(fit["xi"], xis, rtol=1e-4) and np.allclose(fit["amp"], amps, rtol=1e-4)
+    # 1% multiplicative noise, weighted fit: still close
+    rng = np.random.default_rng(3)
+    noisy = curves * (1 + 0.01 * rng.standard_normal(curves.shape))
+    fit = an.multifit_c4(r, noisy, r_min=3.0, errors=0.01 * np.abs(curves) + 1e-12)
+    assert abs(fit["alpha"] - alpha) < 0.05 and abs(fit["beta"] - beta) < 0.05
+    assert np.allclose(fit["xi"], xis, rtol=0.05)
+
+
+def test_growth_fits_recover_z_and_log_form():
+    tw = np.logspace(1, 6, 25)
+    xi = 1.7 * tw ** (1 / 10.5) - 0.8
+    g = an.fit_growth(tw, xi)
+    assert abs(g["z"] - 10.5) < 1e-3 and abs(g["a"] - 1.7) < 1e-4 and abs(g["c"] + 0.8) < 1e-3
+    g0 = an.fit_growth(tw, 2.0 * tw ** 0.25, const=False)
+    assert abs(g0["z"] - 4.0) < 1e-6
+    xl = 0.9 * np.log(tw / 0.3) ** 1.6
+    lg = an.fit_log_growth(tw, xl)
+    assert abs(lg["zt"] - 1.6) < 1e-3 and abs(lg["t0"] - 0.3) < 1e-3 and abs(lg["a"] - 0.9) < 1e-3
+
+
+def test_fit_x_power_law_window():
+    t = np.unique(np.round(np.logspace(0, 6, 80)))
+    C = 0.8 * t ** -0.019
+    # outside the window the curve bends away (the ageing regime): ignored
+    Cb = np.where(t > 1e3, C * np.exp(-(t / 1e4)), C)
+    assert abs(an.fit_x(t, Cb, tw=1e6) - 0.019) < 1e-9
+    assert abs(an.fit_x(t, Cb, t_lo=10, t_hi=500) - 0.019) < 1e-9
+    with pytest.raises(ValueError):
+        an.fit_x(t, C, t_lo=100, t_hi=101)
+
+
+def test_collapse_finds_the_equilibrium_exponent():
+    x_true = 0.016
+    xi_of = lambda t: 1.3 * np.asarray(t, dtype=np.float64) ** (1 / 8.0)
+    f = lambda u: np.exp(-1.5 * u)
+    curves = []
+    for tw in (1e2, 1e3, 1e4, 1e5):
+        t = np.logspace(0, 6, 60)
+        C = t ** -x_true * f(xi_of(tw + t) / xi_of(np.array([tw]))[0] - 1.0)
+        curves.append((tw, t, C))
+    assert an.collapse_spread(x_true, curves, xi_of) < 1e-20
+    assert an.collapse_spread(0.05, curves, xi_of) > 1e-4
+    assert abs(an.best_collapse_x(curves, xi_of, (0.0, 0.05), 501) - x_true) < 1e-3
