@@ -389,8 +389,9 @@ ea_status ea_server_stats(ea_server *s, ea_server_report *out);
  * do for G = 2.  The packing changes no result, only the work per random
  * word.
  *
- * Device memory: (3 + 2 (1 + n_tw_slots)) n_samples L^3 / 8 bytes of words
- * plus counters (ea_msc_footprint).  Calls follow the one-sample form:
+ * Device memory: (4 + 2 (1 + n_tw_slots)) n_samples L^3 / 8 bytes of words
+ * (couplings, spins, snapshots and the overlap words of the C4 pass) plus
+ * counters (ea_msc_footprint).  Calls follow the one-sample form:
  * ea_msc_sweep and ea_msc_snapshot enqueue and return, calls that hand data
  * to the host synchronise the stream, one host thread at a time. */
 typedef struct ea_msc ea_msc;

@@ -24,6 +24,7 @@ struct ea_msc {
     uint32_t *snaps = nullptr;
     unsigned long long *meas = nullptr;
     uint32_t *t_dev = nullptr;
+    uint32_t *q = nullptr;  // overlap words for the C4 passes
     size_t spin_words = 0, bond_words = 0, n_count = 0;
     std::vector<unsigned long long> host_meas;
     hipGraph_t graph = nullptr;
@@ -53,7 +54,7 @@ constexpr int kMscQuantities = ea::MSC_AUTO + 2 * kMaxSlots;  // counters before
 struct MscLayout {
     int L, B, M, S, G, Lz, R, P;
     size_t spin_words, bond_words, snap_words, n_count;
-    size_t off_spins, off_bonds, off_snaps, off_meas, off_ctl, total;
+    size_t off_spins, off_bonds, off_snaps, off_q, off_meas, off_ctl, total;
 };
 
 ea_status msc_layout(const ea_msc_config *cfg, MscLayout &y)
@@ -84,7 +85,8 @@ ea_status msc_layout(const ea_msc_config *cfg, MscLayout &y)
     y.off_spins = 0;
     y.off_bonds = align256(y.off_spins + 4 * y.spin_words);
     y.off_snaps = align256(y.off_bonds + 4 * y.bond_words);
-    y.off_meas = align256(y.off_snaps + 4 * y.snap_words);
+    y.off_q = align256(y.off_snaps + 4 * y.snap_words);
+    y.off_meas = align256(y.off_q + 4 * (y.spin_words / 2));
     y.off_ctl = align256(y.off_meas + 8 * y.n_count);
     y.total = align256(y.off_ctl + 256);
     return EA_OK;
@@ -248,6 +250,7 @@ ea_status ea_msc_create(const ea_msc_config *cfg, ea_msc **out)
     s->lat.bonds = (uint32_t *)(s->buf + y.off_bonds);
     s->snaps = (uint32_t *)(s->buf + y.off_snaps);
     s->meas = (unsigned long long *)(s->buf + y.off_meas);
+    s->q = (uint32_t *)(s->buf + y.off_q);
     s->t_dev = (uint32_t *)(s->buf + y.off_ctl);
 
     const dim3 grid(blocks_for((size_t)s->geom.q), 5, 2 * (unsigned)s->G);
@@ -321,10 +324,17 @@ ea_status ea_msc_measure(ea_msc *s, ea_obs *out)
                                             s->snaps, s->spin_words, s->G, s->meas));
     unsigned long long *c4_acc = s->meas + (size_t)kMscQuantities * s->G * 32;
     if (any_c4) {
+        hipLaunchKernelGGL(ea::msc_q_kernel, dim3(blocks_for(s->spin_words / 2)), dim3(256), 0, s->stream, s->lat, g,
+                           s->G, s->q);
         const unsigned nblk_c4 = (unsigned)std::min<size_t>(blocks_for(2 * (size_t)g.P), 64);
-        const dim3 grid_c4(nblk_c4, 3 * (unsigned)(g.R + 1), (unsigned)s->G);
-        EA_DISPATCH_M(s->M, hipLaunchKernelGGL((ea::msc_c4_kernel<MM>), grid_c4, dim3(256), 0, s->stream, s->lat,
+        const dim3 grid_c4(nblk_c4, (unsigned)(g.R + 1), (unsigned)s->G);
+        const size_t axis = (size_t)(g.R + 1) * s->G * 32;  // counters of one axis
+        EA_DISPATCH_M(s->M, hipLaunchKernelGGL((ea::msc_c4_kernel<MM, 0>), grid_c4, dim3(256), 0, s->stream, s->q,
                                                 g, s->G, c4_acc));
+        EA_DISPATCH_M(s->M, hipLaunchKernelGGL((ea::msc_c4_kernel<MM, 1>), grid_c4, dim3(256), 0, s->stream, s->q,
+                                                g, s->G, c4_acc + axis));
+        EA_DISPATCH_M(s->M, hipLaunchKernelGGL((ea::msc_c4_kernel<MM, 2>), grid_c4, dim3(256), 0, s->stream, s->q,
+                                                g, s->G, c4_acc + 2 * axis));
     }
     EA_HIP(hipGetLastError());
     EA_HIP(hipMemcpyAsync(s->host_meas.data(), s->meas, s->n_count * sizeof(unsigned long long),

@@ -473,21 +473,35 @@ __global__ __launch_bounds__(256) void msc_measure_kernel(MscLattice lat, MscGeo
     }
 }
 
-// C4 along the axes (eq. 3): sites whose overlap differs from the overlap
-// rho e_d away.  grid.y = d (R + 1) + rho, grid.z = word set; acc points at
-// the C4 block, laid out [d][rho][G][32].
-template <int M>
-__global__ __launch_bounds__(256) void msc_c4_kernel(MscLattice lat, MscGeom g, int n_sets,
+// The overlap word q = S_0 ^ S_1 of every site word, [G][colour][P], for the
+// C4 passes (one word read per site instead of two).
+__global__ __launch_bounds__(256) void msc_q_kernel(MscLattice lat, MscGeom g, int n_sets, uint32_t *q)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t per_set = 2 * (size_t)g.P;
+    if (i >= per_set * (size_t)n_sets) return;
+    const size_t gi = i / per_set, k = i - gi * per_set;
+    const uint32_t *s = lat.spins + gi * 4 * (size_t)g.P;
+    q[i] = s[k] ^ s[per_set + k];  // replica 0's two colour planes, then replica 1's
+}
+
+// C4 along axis D (eq. 3): sites whose overlap differs from the overlap
+// rho e_D away.  grid.y = rho, grid.z = word set; acc points at axis D's
+// block, laid out [rho][G][32].
+template <int M, int D>
+__global__ __launch_bounds__(256) void msc_c4_kernel(const uint32_t *__restrict__ q, MscGeom g, int n_sets,
                                                      unsigned long long *acc)
 {
     const int gi = blockIdx.z;
-    const int d = blockIdx.y / (g.R + 1), rho = blockIdx.y - d * (g.R + 1);
+    const int rho = blockIdx.y;
     const int R = g.R;
     const int stride = gridDim.x * blockDim.x;
     const int n_it = (2 * g.P + stride - 1) / stride;
+    const uint32_t *qs = q + (size_t)gi * 2 * (size_t)g.P;
     // a z displacement crosses up_base slab faces, plus one more when the
     // reduced z passes Lz
     const int up_base = rho / g.Lz, z_rem = rho - up_base * g.Lz;
+    const int flip = rho & 1;  // an odd displacement lands on the other colour
     MscWalk w;
     w.init(g, blockIdx.x * blockDim.x + threadIdx.x, stride);
     BitCounter k;
@@ -496,30 +510,26 @@ __global__ __launch_bounds__(256) void msc_c4_kernel(MscLattice lat, MscGeom g, 
     for (int it = 0, run = 0; it < n_it; ++it) {
         uint32_t diff = 0u;
         if (w.live()) {
-            const int c = w.c;
             const int row = w.y + g.L * w.z;
-            const int c2 = c ^ (rho & 1);
-            size_t w2;
-            int up = 0;
-            if (d == 0) {
-                int x2 = 2 * w.xh + ((w.y + w.z + c) & 1) + rho;
+            const int base2 = (w.c ^ flip) * g.P;
+            int w2, up = 0;
+            if constexpr (D == 0) {
+                int x2 = 2 * w.xh + ((w.y + w.z + w.c) & 1) + rho;
                 x2 -= x2 >= g.L ? g.L : 0;
-                w2 = (size_t)row * R + (x2 >> 1);
-            } else if (d == 1) {
+                w2 = base2 + row * R + (x2 >> 1);
+            } else if constexpr (D == 1) {
                 int y2 = w.y + rho;
                 y2 -= y2 >= g.L ? g.L : 0;
-                w2 = (size_t)(y2 + g.L * w.z) * R + w.xh;
+                w2 = base2 + (y2 + g.L * w.z) * R + w.xh;
             } else {
                 int z2 = w.z + z_rem;
                 const int wrap_z = z2 >= g.Lz;
                 z2 -= wrap_z ? g.Lz : 0;
                 up = up_base + wrap_z;
-                w2 = (size_t)(w.y + g.L * z2) * R + w.xh;
+                w2 = base2 + (w.y + g.L * z2) * R + w.xh;
             }
-            const size_t hw = (size_t)row * R + w.xh;
-            const uint32_t q = lat.spins[msc_spin_plane(g, gi, 0, c) + hw] ^ lat.spins[msc_spin_plane(g, gi, 1, c) + hw];
-            const uint32_t q2 = lat.spins[msc_spin_plane(g, gi, 0, c2) + w2] ^ lat.spins[msc_spin_plane(g, gi, 1, c2) + w2];
-            diff = q ^ from_slabs_above<M>(q2, up);
+            const uint32_t q1 = qs[w.c * g.P + row * R + w.xh];
+            diff = q1 ^ from_slabs_above<M>(qs[w2], up);
         }
         w.next(g);
         bc_add(k, diff);
@@ -528,7 +538,7 @@ __global__ __launch_bounds__(256) void msc_c4_kernel(MscLattice lat, MscGeom g, 
             bc_flush(k, cnt[0]);
         }
     }
-    unsigned long long *const dst[1] = {acc + ((size_t)blockIdx.y * n_sets + gi) * 32};
+    unsigned long long *const dst[1] = {acc + ((size_t)rho * n_sets + gi) * 32};
     block_flush<1>(cnt, dst);
 }
 

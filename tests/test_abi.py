@@ -82,7 +82,7 @@ def test_msc_footprint_and_bad_arguments(ealib):
         # words per plane, all word sets: 32 samples per word; fewer samples fill
         # the 32 bits with 32 / B slabs of L B / 32 planes each
         words = (B // 32 if B >= 32 else 1) * (L // 2) * L * (L if B >= 32 else L * B // 32)
-        dense = 4 * words * (4 + 6 + 4 * slots)
+        dense = 4 * words * (4 + 6 + 4 * slots + 2)   # spins, couplings, snapshots, overlap words
         counters = 8 * (5 + 2 * 64 + 3 * (L // 2 + 1)) * (max(B, 32) // 32) * 32
         assert dense + counters <= fp < dense + counters + 5 * 256 + 256, (L, B, slots)
     for L, B in ((16, 3), (16, 0), (16, 48), (16, 288), (24, 1), (40, 2), (8, 4), (12, 32), (264, 32)):
