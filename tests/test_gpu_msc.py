@@ -151,6 +151,26 @@ def test_full_size_sampled(ea_gpu, oracle_mod):
         assert all(u < 1.2 * N for u in ob.unsat), (b, ob.unsat)
 
 
+def test_full_size_two_word_sets(ea_gpu, oracle_mod):
+    """The benchmark's batch: 128^3 x 64 samples in two word sets sharing the
+    random words; the first and last sample against the oracle after two
+    sweeps, with a library-owned stream and buffer."""
+    L, B = 128, 64
+    _say("msc L=128 B=64 (library-owned memory)")
+    g = ea_gpu.Msc(L, B, 0.5, 0.8, seed=1, sample0=0, shared=0, use_torch=False)
+    g.sweep(2)
+    for b in (0, 63):
+        o = oracle_mod.Sim(L, 0.5, 0.8, seed=1, sample=b)
+        o.share_noise(0)
+        o.sweep(2)
+        for r in (0, 1):
+            assert np.array_equal(g.spins(b, r), o.spins(r)), (b, r)
+        ob = g.measure(autocorr=False)[b]
+        oo = o.measure()
+        assert list(ob.unsat) == list(oo.unsat) and ob.overlap == oo.overlap
+        assert np.array_equal(ob.c4, oo.c4)
+
+
 def test_msc_errors(ea_gpu):
     for L, B in [(16, 3), (16, 0), (16, 48), (16, 288), (24, 1), (40, 2), (8, 4), (12, 32)]:
         with pytest.raises(ea_gpu.EAError):
