@@ -271,6 +271,30 @@ def bench_msc(ea, torch, job, burst: int):
     }
 
 
+def bench_crossover(ea, torch, jobs):
+    """The crossover runs (five L = 128 samples, one per p) with their own
+    schedules: grouped (shared launches between events) and one after the
+    other, wall clock with the measurements."""
+    flips = sum(j.flips for j in jobs)
+    ea.run_group(jobs[:1])  # warm-up: kernels and the plain packing
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ea.run_group(jobs)
+    torch.cuda.synchronize()
+    grouped = time.perf_counter() - w0
+    w0 = time.perf_counter()
+    for j in jobs:
+        ea.run_group([j])
+    torch.cuda.synchronize()
+    separate = time.perf_counter() - w0
+    return {
+        "workload": f"{len(jobs)} plain runs, L={jobs[0].L}, p in {[j.p for j in jobs]}, T={jobs[0].T}, "
+                    f"{jobs[0].n_sweeps} sweeps, {len(jobs[0].meas_t)} measurements each",
+        "ps_per_flip_grouped": round(grouped / flips * 1e12, 4),
+        "ps_per_flip_one_by_one": round(separate / flips * 1e12, 4),
+    }
+
+
 SERVE_SIZES = (16, 24, 32, 48, 64, 96, 128)
 
 
@@ -345,6 +369,8 @@ def main():
     ap.add_argument("--msc-samples", type=int, default=64, help="samples of the multispin-coded batch")
     ap.add_argument("--msc-burst", type=int, default=1024, help="sweeps in its kernel-timing burst")
     ap.add_argument("--msc-only", action="store_true", help="run only the multispin-coded leg and print it")
+    ap.add_argument("--crossover-sweeps", type=int, default=10_000,
+                    help="sweeps of each crossover run in the grouped-plain leg (0 = skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (a known-size kernel "
                          "for calibrating hardware byte counters) and exit")
@@ -484,6 +510,9 @@ def main():
     if args.msc_sweeps:
         log("multispin-coded batch ...")
         out["msc"] = bench_msc(ea, torch, wl.msc_job(args.msc_sweeps, args.msc_samples), args.msc_burst)
+    if args.crossover_sweeps:
+        log("crossover runs, grouped ...")
+        out["crossover"] = bench_crossover(ea, torch, wl.crossover_jobs(args.crossover_sweeps))
     if not args.no_plain:
         log("plain form ...")
         plain = bench_plain(ea, torch, wl.mid_job(args.sweeps), args.plain_steps, args.burst)

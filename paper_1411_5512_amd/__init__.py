@@ -15,7 +15,7 @@ import numpy as np
 from . import abi
 from .abi import EAError
 
-__all__ = ["Sim", "Batch", "Server", "EAError", "thresholds", "footprint", "version", "tune", "sweep_group", "Msc"]
+__all__ = ["Sim", "Batch", "Server", "EAError", "thresholds", "footprint", "version", "tune", "sweep_group", "run_group", "Msc"]
 
 
 def version() -> str:
@@ -327,6 +327,42 @@ class Msc:
         out = np.zeros(3 * self.N, dtype=np.int8)
         abi.check(abi.lib().ea_msc_get_bonds(self._h, int(b), abi.ptr(out, ctypes.c_int8)))
         return out
+
+
+def run_group(jobs, words_per_row: int = 0, use_torch: bool = True):
+    """Run several plain jobs of one L together (see ea_sweep_group): every
+    run follows its own schedule of snapshots and measurements, and between
+    events all runs advance in shared launches.  `jobs` are workloads.Job-like
+    (L, p, T, seed, sample, n_sweeps, meas_t, tw, events()).  Returns, per job,
+    the list of Obs at its measurement times.  Same results as running each
+    job alone."""
+    jobs = list(jobs)
+    if not jobs:
+        return []
+    sims = [Sim(j.L, j.p, j.T, seed=j.seed, sample=j.sample, n_slots=len(j.tw), use_torch=use_torch,
+                words_per_row=words_per_row) for j in jobs]
+    events = {}
+    for i, j in enumerate(jobs):
+        for te, slots, meas in j.events():
+            events.setdefault(int(te), []).append((i, slots, meas))
+        events.setdefault(int(j.n_sweeps), [])
+    out = [[] for _ in jobs]
+    t = 0
+    for te in sorted(events):
+        # the runs still going at te advance together
+        live = [s for s, j in zip(sims, jobs) if j.n_sweeps >= te]
+        if te > t:
+            sweep_group(live, te - t)
+            t = te
+        for i, slots, meas in events[te]:
+            for k in slots:
+                sims[i].snapshot(k)
+            if meas:
+                out[i].append(sims[i].measure())
+    for s in sims:
+        s.sync()
+        s.close()
+    return out
 
 
 def _job_struct(job, keep):

@@ -341,3 +341,27 @@ def test_sweep_group_errors(ea_gpu):
     assert a.time == 0 and b.time == (1 << 32) - 3   # nothing advanced
     ea_gpu.sweep_group([a, b], 2)
     assert a.time == 2 and b.time == (1 << 32) - 1
+
+
+def test_run_group_schedules_match_oracle(ea_gpu, oracle_mod):
+    """run_group: runs of one L with different p, T, seeds, lengths and
+    schedules advance together and each gives its oracle run's observables
+    at its own measurement times."""
+    from paper_1411_5512_amd.workloads import Job
+    jobs = [Job(24, 0.5, 0.8, seed=3, sample=0, n_sweeps=40, meas_t=[5, 17, 40], tw=[5]),
+            Job(24, 0.2, 0.6, seed=4, sample=2, n_sweeps=25, meas_t=[1, 25], tw=[1, 12]),
+            Job(24, 0.4, 1.1, seed=5, sample=1, n_sweeps=33, meas_t=[33], tw=[])]
+    _say("run_group L=24 x 3")
+    res = ea_gpu.run_group(jobs)
+    for i, job in enumerate(jobs):
+        o = oracle_mod.Sim(job.L, job.p, job.T, seed=job.seed, sample=job.sample, n_slots=len(job.tw))
+        t, k = 0, 0
+        for te, slots, meas in job.events():
+            o.sweep(te - t)
+            t = te
+            for slot in slots:
+                o.snapshot(slot)
+            if meas:
+                _compare_obs(res[i][k], o.measure(), f"job {i} t={te}")
+                k += 1
+        assert k == len(res[i]) == len(job.meas_t)
