@@ -253,6 +253,43 @@ __device__ __forceinline__ uint32_t flip_mask(const Decision &d, uint32_t c0, ui
     return d.always | accept_blocks<W / 4 - 1>(0u, d, c0, quad0, c2, c3, k0, k1, thr1, thr2, thr3);
 }
 
+// The same flip mask in two steps, for kernels that wait on global loads:
+// first the W random words (they depend only on the counter, so they can be
+// computed while the neighbour words are in flight), then the decisions.
+template <int J, int W>
+__device__ __forceinline__ void random_words(uint32_t c0, uint32_t quad0, uint32_t c2, uint32_t c3, uint32_t k0,
+                                             uint32_t k1, uint32_t (&u)[W])
+{
+    if constexpr (J > 0) {
+        Words4 a, b;
+        philox10_pair(c0, quad0 + (uint32_t)J, quad0 + (uint32_t)(J - 1), c2, c3, k0, k1, a, b);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            u[4 * J + i] = a.v[i];
+            u[4 * J - 4 + i] = b.v[i];
+        }
+        if constexpr (J > 1) random_words<J - 2, W>(c0, quad0, c2, c3, k0, k1, u);
+    } else {
+        const Words4 a = philox10(c0, quad0, c2, c3, k0, k1);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) u[i] = a.v[i];
+    }
+}
+
+template <int J, int W>
+__device__ __forceinline__ uint32_t accept_words(uint32_t accept, const Decision &d, const uint32_t (&u)[W],
+                                                 uint32_t thr1, uint32_t thr2, uint32_t thr3)
+{
+    accept = append_below4(accept, u[4 * J + 3], site_threshold<4 * J + 3>(d, thr1, thr2, thr3), u[4 * J + 2],
+                           site_threshold<4 * J + 2>(d, thr1, thr2, thr3), u[4 * J + 1],
+                           site_threshold<4 * J + 1>(d, thr1, thr2, thr3), u[4 * J],
+                           site_threshold<4 * J>(d, thr1, thr2, thr3));
+    if constexpr (J > 0)
+        return accept_words<J - 1, W>(accept, d, u, thr1, thr2, thr3);
+    else
+        return accept;
+}
+
 // ---------------------------------------------------------------------------
 // Threshold select through LDS tables, four sites per read.  A 4-site block
 // q = 0..3 has class bits any_q (n >= 2) and odd_q (n odd); the 8-bit index

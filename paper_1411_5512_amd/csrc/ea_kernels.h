@@ -96,25 +96,37 @@ __device__ __forceinline__ void half_step_word(const Lattice &lat, const Geom &g
     const uint32_t S = own[base + w];
     const uint32_t O = oth[base + w], Om = oth[base + wm], Op = oth[base + wp];
     const uint32_t Xo = bx_oth[base + w], Xom = bx_oth[base + wm];
+    const uint32_t Bx = bx_own[base + w], By = by_own[base + w], Bz = bz_own[base + w];
+    const uint32_t Yp = oth[row_yp * g.RW + w], Ym = oth[row_ym * g.RW + w], Bym = by_oth[row_ym * g.RW + w];
+    const uint32_t Zp = oth[row_zp * g.RW + w], Zm = oth[row_zm * g.RW + w], Bzm = bz_oth[row_zm * g.RW + w];
+
+    // the random words do not depend on the lattice: computed here, they
+    // overlap the latency of the loads above (the scheduling barrier keeps
+    // every load issued before them)
+    __builtin_amdgcn_sched_barrier(0);
+    uint32_t u[W];
+    random_words<W / 4 - 1, W>(t, (uint32_t)((row * g.R + w * W) >> 2),
+                               counter_word2(TAG_METRO, (uint32_t)c, (uint32_t)r), sample, k0, k1, u);
 
     // x neighbours: on even rows (par = 0) the +x neighbour shares xh and the
     // -x neighbour sits at xh - 1; on odd rows the +x neighbour is at xh + 1
     // and the -x neighbour shares xh.  The -x bond is stored at the -x site.
-    const uint32_t xp = par ? take_plus1<W>(O, Op) : O;
-    const uint32_t xm = par ? (O ^ Xo) : take_minus1<W>(O ^ Xo, Om ^ Xom);
-    const uint32_t a1 = S ^ xp ^ bx_own[base + w];
+    // (selected with a mask rather than a branch, so that no load waits
+    // inside a divergent branch before the random words are computed)
+    const uint32_t pm = 0u - (uint32_t)par;
+    const uint32_t xp = __builtin_amdgcn_bitop3_b32(pm, take_plus1<W>(O, Op), O, kBitopSelect);
+    const uint32_t xm = __builtin_amdgcn_bitop3_b32(pm, O ^ Xo, take_minus1<W>(O ^ Xo, Om ^ Xom), kBitopSelect);
+    const uint32_t a1 = S ^ xp ^ Bx;
     const uint32_t a2 = S ^ xm;
-    const uint32_t a3 = xor3(S, oth[row_yp * g.RW + w], by_own[base + w]);
-    const uint32_t a4 = xor3(S, oth[row_ym * g.RW + w], by_oth[row_ym * g.RW + w]);
-    const uint32_t a5 = xor3(S, oth[row_zp * g.RW + w], bz_own[base + w]);
-    const uint32_t a6 = xor3(S, oth[row_zm * g.RW + w], bz_oth[row_zm * g.RW + w]);
+    const uint32_t a3 = xor3(S, Yp, By);
+    const uint32_t a4 = xor3(S, Ym, Bym);
+    const uint32_t a5 = xor3(S, Zp, Bz);
+    const uint32_t a6 = xor3(S, Zm, Bzm);
 
     const Decision d = classify(a1, a2, a3, a4, a5, a6);
-    const uint32_t quad0 = (uint32_t)((row * g.R + w * W) >> 2);
     // the register select: this launch is latency-bound, an LDS table would
     // add a fill and a barrier to every block
-    const uint32_t flips = flip_mask<W>(d, t, quad0, counter_word2(TAG_METRO, (uint32_t)c, (uint32_t)r),
-                                        sample, k0, k1, thr1, thr2, thr3);
+    const uint32_t flips = d.always | accept_words<W / 4 - 1, W>(0u, d, u, thr1, thr2, thr3);
     own[base + w] = S ^ flips;
 }
 
