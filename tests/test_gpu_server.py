@@ -161,6 +161,32 @@ def test_server_streams_large_lattices(ea_gpu):
             _same_obs(srv.result(jid, k), want, f"L={job.L} meas {k}")
 
 
+def test_server_groups_streamed_jobs_of_one_size(ea_gpu):
+    """Several streamed jobs of the same L with different lengths and
+    schedules, beside another size and an LDS job, through many epochs:
+    every job equals its run alone."""
+    from paper_1411_5512_amd.workloads import Job
+    jobs = [
+        Job(96, 0.5, 0.7, seed=51, sample=0, n_sweeps=37, meas_t=[0, 4, 21, 37], tw=[4]),
+        Job(96, 0.3, 0.9, seed=52, sample=1, n_sweeps=12, meas_t=[12], tw=[3]),
+        Job(96, 0.2, 0.6, seed=53, sample=0, n_sweeps=50, meas_t=[1, 7, 50], tw=[7, 30]),
+        Job(72, 0.5, 0.8, seed=54, sample=0, n_sweeps=29, meas_t=[9, 29], tw=[9]),
+        Job(72, 0.4, 1.0, seed=55, sample=2, n_sweeps=18, meas_t=[2, 18], tw=[]),
+        Job(24, 0.5, 0.8, seed=56, sample=0, n_sweeps=90, meas_t=[30, 90], tw=[30]),
+    ]
+    srv = ea_gpu.Server(hbm_budget=1 << 28, max_resident=8, epoch_site_sweeps=24 ** 3 * 5)
+    ids = [srv.submit(j) for j in jobs]
+    n = 0
+    while srv.step():
+        n += 1
+        assert n < 10000
+    for jid, job in zip(ids, jobs):
+        _say(f"grouped streamed job L={job.L} sweeps={job.n_sweeps}")
+        ref = _alone_plain(ea_gpu, job)
+        for k, want in enumerate(ref):
+            _same_obs(srv.result(jid, k), want, f"L={job.L} seed={job.seed} meas {k}")
+
+
 def test_server_streamed_job_matches_oracle(ea_gpu, oracle_mod):
     """One streamed job, split over many epochs, against the oracle."""
     from paper_1411_5512_amd.workloads import Job
