@@ -248,3 +248,23 @@ def best_collapse_x(curves, xi_of, x_range=(0.0, 0.1), n: int = 201):
     xs = np.linspace(x_range[0], x_range[1], n)
     s = [collapse_spread(x, curves, xi_of) for x in xs]
     return float(xs[int(np.argmin(s))])
+
+
+def fit_peak(p, z, offset: bool = True):
+    """The transition estimate of Sec. IV: a Gaussian a exp(-(p - p_c)^2 /
+    (2 w^2)) (+ b) fitted to the peak of the growth exponent z(p).  Returns
+    dict(p_c, width, amp, offset)."""
+    from scipy import optimize
+
+    p = np.asarray(p, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    i = int(np.argmax(z))
+    base = float(np.min(z)) if offset else 0.0
+    w0 = max((p.max() - p.min()) / 6.0, 1e-3)
+    if offset:
+        f = lambda x, a, pc, w, b: a * np.exp(-(x - pc) ** 2 / (2 * w * w)) + b
+        q, _ = optimize.curve_fit(f, p, z, p0=(z[i] - base, p[i], w0, base), maxfev=50000)
+        return {"p_c": float(q[1]), "width": float(abs(q[2])), "amp": float(q[0]), "offset": float(q[3])}
+    f = lambda x, a, pc, w: a * np.exp(-(x - pc) ** 2 / (2 * w * w))
+    q, _ = optimize.curve_fit(f, p, z, p0=(z[i], p[i], w0), maxfev=50000)
+    return {"p_c": float(q[1]), "width": float(abs(q[2])), "amp": float(q[0]), "offset": 0.0}

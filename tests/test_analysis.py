@@ -124,3 +124,15 @@ def test_collapse_finds_the_equilibrium_exponent():
     assert an.collapse_spread(x_true, curves, xi_of) < 1e-20
     assert an.collapse_spread(0.05, curves, xi_of) > 1e-4
     assert abs(an.best_collapse_x(curves, xi_of, (0.0, 0.05), 501) - x_true) < 1e-3
+
+
+def test_fit_peak_locates_the_transition():
+    p = np.linspace(0.1, 0.45, 36)
+    z = 6.0 * np.exp(-(p - 0.23) ** 2 / (2 * 0.03 ** 2)) + 10.5
+    f = an.fit_peak(p, z)
+    assert abs(f["p_c"] - 0.23) < 1e-6 and abs(f["width"] - 0.03) < 1e-6 and abs(f["offset"] - 10.5) < 1e-6
+    rng = np.random.default_rng(5)
+    f = an.fit_peak(p, z + 0.1 * rng.standard_normal(p.size))
+    assert abs(f["p_c"] - 0.23) < 0.005
+    f0 = an.fit_peak(p, z - 10.5, offset=False)
+    assert abs(f0["p_c"] - 0.23) < 1e-6
