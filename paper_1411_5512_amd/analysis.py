@@ -58,7 +58,9 @@ def c4_form(r, amp, alpha, xi, beta):
     """The functional form of eq. 4 with a stretched exponential g:
     amp r^-alpha exp(-(r/xi)^beta)."""
     r = np.asarray(r, dtype=np.float64)
-    return amp * r ** (-alpha) * np.exp(-(r / xi) ** beta)
+    # a fit may probe parameters where the form is undefined (xi <= 0): NaN there
+    with np.errstate(invalid="ignore", divide="ignore", over="ignore"):
+        return amp * r ** (-alpha) * np.exp(-(r / xi) ** beta)
 
 
 def xi_k_samples(r, curves, k: int = 1, n_sigma: float = 3.0, tail: bool = True,

@@ -236,6 +236,29 @@ def test_ageing_analysis_pipeline(ea_gpu):
     assert fit["xi"][-1] > fit["xi"][0]
 
 
+def _exponents(ea_gpu, an, p, seed=2024, n_sweeps=100_000):
+    """alpha, beta and z (from the fitted xi and from xi_1) of a 128^3 x 64
+    multispin batch at T = 0.8 over n_sweeps, C4 at four t_w per decade."""
+    L, B = 128, 64
+    g = ea_gpu.Msc(L, B, p, 0.8, seed=seed, sample0=0, shared=7)
+    r = np.arange(L // 2 + 1, dtype=np.float64)
+    tws = sorted({int(round(10 ** (k / 4))) for k in range(4, 4 * int(round(np.log10(n_sweeps))) + 1)})
+    means, errs, xi1 = [], [], []
+    t = 0
+    for tw in tws:
+        g.sweep(tw - t)
+        t = tw
+        per = np.array([o.c4.mean(axis=0) / L ** 3 for o in g.measure(autocorr=False)])
+        means.append(per.mean(axis=0))
+        errs.append(per.std(axis=0, ddof=1) / np.sqrt(B))
+        xi1.append(an.xi_k_samples(r, per, k=1, tail=True)[0])
+    g.close()
+    fit = an.multifit_c4(r, np.array(means), r_min=3.0, errors=np.array(errs), n_sigma=3.0)
+    tw_a = np.array(tws, dtype=float)
+    return (fit["alpha"], fit["beta"], an.fit_growth(tw_a, fit["xi"])["z"],
+            an.fit_growth(tw_a, np.array(xi1))["z"], xi1)
+
+
 def test_paper_batch_reproduces_spin_glass_exponents(ea_gpu):
     """The paper's production batch (128^3, 64 samples sharing the random
     words, p = 0.5, T = 0.8), 10^5 sweeps with C4 at log-spaced t_w from 10:
@@ -246,25 +269,36 @@ def test_paper_batch_reproduces_spin_glass_exponents(ea_gpu):
     0.505, beta 1.419, z 10.6 from the fitted xi, 9.2 from xi_1); the bounds
     only allow for the paper's own spread."""
     from paper_1411_5512_amd import analysis as an
-    L, B = 128, 64
-    g = ea_gpu.Msc(L, B, 0.5, 0.8, seed=2024, sample0=0, shared=7)
-    r = np.arange(L // 2 + 1, dtype=np.float64)
-    tws = sorted({int(round(10 ** (k / 4))) for k in range(4, 21)})
-    means, errs, xi1 = [], [], []
-    t = 0
-    for tw in tws:
-        g.sweep(tw - t)
-        t = tw
-        per = np.array([o.c4.mean(axis=0) / L ** 3 for o in g.measure(autocorr=False)])
-        means.append(per.mean(axis=0))
-        errs.append(per.std(axis=0, ddof=1) / np.sqrt(B))
-        xi1.append(an.xi_k_samples(r, per, k=1, tail=True)[0])
-    fit = an.multifit_c4(r, np.array(means), r_min=3.0, errors=np.array(errs), n_sigma=3.0)
-    z_fit = an.fit_growth(np.array(tws, dtype=float), fit["xi"])["z"]
-    z_int = an.fit_growth(np.array(tws, dtype=float), np.array(xi1))["z"]
-    _say(f"alpha={fit['alpha']:.3f} beta={fit['beta']:.3f} z(fit xi)={z_fit:.2f} z(xi_1)={z_int:.2f} "
-         f"xi_1(1e5)={xi1[-1]:.3f}")
-    assert 0.4 <= fit["alpha"] <= 0.6
-    assert 1.3 <= fit["beta"] <= 1.55
+    alpha, beta, z_fit, z_int, xi1 = _exponents(ea_gpu, an, 0.5)
+    _say(f"alpha={alpha:.3f} beta={beta:.3f} z(fit xi)={z_fit:.2f} z(xi_1)={z_int:.2f} xi_1(1e5)={xi1[-1]:.3f}")
+    assert 0.4 <= alpha <= 0.6
+    assert 1.3 <= beta <= 1.55
     assert 9.0 <= z_fit <= 12.0 and 8.0 <= z_int <= 12.0
     assert all(b > a for a, b in zip(xi1, xi1[1:]))
+
+
+def test_crossover_z_peak_locates_the_transition(ea_gpu):
+    """Sec. IV's crossover analysis on multispin batches (128^3 x 64, T = 0.8,
+    10^5 sweeps each) across p: z(p) peaks at the spin-glass/ferromagnet
+    transition, and a Gaussian fitted to the peak puts it at p ~ 0.225 (in the
+    paper's convention, where p counts ferromagnetic bonds, 0.775; the paper
+    finds 0.772 at L = 128 and 0.777 at L = 64).  alpha falls from its
+    spin-glass value towards zero on the ferromagnetic side.  Deterministic:
+    the bounds leave room only for the fit, not for the dynamics."""
+    from paper_1411_5512_amd import analysis as an
+    ps = [0.5, 0.3, 0.27, 0.25, 0.23, 0.21, 0.19, 0.17, 0.15]
+    rows = []
+    for p in ps:
+        alpha, beta, z_fit, z_int, xi1 = _exponents(ea_gpu, an, p)
+        rows.append((p, alpha, beta, z_fit, z_int))
+        _say(f"p={p:.2f} alpha={alpha:.3f} beta={beta:.3f} z(fit xi)={z_fit:.2f} z(xi_1)={z_int:.2f}")
+    p = np.array([r[0] for r in rows])
+    z_fit = np.array([r[3] for r in rows])
+    z_int = np.array([r[4] for r in rows])
+    near = p <= 0.35
+    pc_fit = an.fit_peak(p[near], z_fit[near])["p_c"]
+    pc_int = an.fit_peak(p[near], z_int[near])["p_c"]
+    _say(f"p_c from the z peak: {pc_fit:.4f} (fitted xi), {pc_int:.4f} (xi_1)")
+    assert 0.21 <= pc_fit <= 0.24 and 0.21 <= pc_int <= 0.24
+    assert z_fit.max() > 1.8 * z_fit[0]           # a pronounced peak over the spin-glass value
+    assert rows[0][1] > 0.4 and rows[-1][1] < 0.25  # alpha: spin glass vs ferromagnetic side
