@@ -122,6 +122,15 @@ __device__ __forceinline__ uint32_t take_plus1(uint32_t cur, uint32_t next)
     return (cur >> 1) | ((next & 1u) << (W - 1));
 }
 
+// Workgroups are handed to the 8 XCDs in turn (block b to XCD b mod 8), each
+// XCD with its own L2.  Renumbering block b as (b mod 8) n/8 + b/8 gives each
+// XCD a contiguous run of logical blocks, so that neighbouring rows of the
+// lattice are read through the same L2 (n a multiple of 8; else unchanged).
+__device__ __forceinline__ int xcd_block(int b, int n)
+{
+    return (n & 7) ? b : (b & 7) * (n >> 3) + (b >> 3);
+}
+
 __device__ __forceinline__ int wrap(int v, int L)
 {
     return v < 0 ? v + L : (v >= L ? v - L : v);

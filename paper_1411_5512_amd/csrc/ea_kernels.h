@@ -136,7 +136,7 @@ __global__ __launch_bounds__(256) void half_step_kernel(Lattice lat, Geom g, int
                                                         uint32_t k0, uint32_t k1, uint32_t sample,
                                                         uint32_t thr1, uint32_t thr2, uint32_t thr3)
 {
-    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int tid = xcd_block((int)blockIdx.x, (int)gridDim.x) * (int)blockDim.x + (int)threadIdx.x;
     if (tid >= g.plane) return;
     half_step_word<W>(lat, g, half, *t_base + t_off, (int)blockIdx.y, tid, k0, k1, sample, thr1, thr2, thr3);
 }
@@ -159,7 +159,7 @@ struct GroupArgs {
 template <int W>
 __global__ __launch_bounds__(256) void group_half_step_kernel(GroupArgs a, Geom g, int half, uint32_t t_off)
 {
-    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int tid = xcd_block((int)blockIdx.x, (int)gridDim.x) * (int)blockDim.x + (int)threadIdx.x;
     if (tid >= g.plane) return;
     const GroupMember &M = a.m[blockIdx.z];
     half_step_word<W>(M.lat, g, half, *M.t_base + t_off, (int)blockIdx.y, tid, M.k0, M.k1, M.sample, M.thr1,

@@ -153,11 +153,7 @@ __global__ __launch_bounds__(256) void msc_init_kernel(MscLattice lat, MscGeom g
 // logical block (b mod 8) n/8 + b/8 gives each XCD a contiguous run of tiles
 // -- a z-slab, whose neighbour rows then sit in that XCD's L2 -- and logical
 // block 2 tile + r puts the two replicas of a tile side by side, so that their
-// reads of the shared couplings meet in L2.  grid.y = word set.
-__device__ __forceinline__ int xcd_block(int b, int n)
-{
-    return (n & 7) ? b : (b & 7) * (n >> 3) + (b >> 3);
-}
+// reads of the shared couplings meet in L2 (xcd_block).  grid.y = word set.
 
 template <int M>
 __global__ __launch_bounds__(256) void msc_half_step_kernel(MscLattice lat, MscGeom g, int half,
