@@ -341,18 +341,22 @@ void order_units(const std::vector<BatchJobHost *> &jobs, const std::vector<uint
 // every pair are dispatched at the start), the in-order dispatch of the
 // resulting unit list onto n_cu one-unit CUs is simulated and the threshold
 // with the shortest estimated makespan is kept.  Time model per half-step
-// (measured on MI355X): a whole replica takes kHalfStepL64 x (L/64)^3; a
-// slab takes 0.55 of that, but at least kSlabFloor, the latency of the
-// boundary exchange (wait, remote reads, release).  Only jobs in their
-// default launch configuration (the slab kernel exists for that one) split.
-constexpr double kHalfStepL64 = 13.5e-6;
-constexpr double kSlabFloor = 9.9e-6;
+// (measured on MI355X): a whole replica takes kHalfStepL64 (L/64)^kSizeExp
+// (smaller lattices use a CU less fully than the site count alone says); a
+// slab takes half of that plus kSlabExchange, but at least kSlabFloor, the
+// latency of the boundary exchange (wait, remote reads, publication).  Only
+// jobs in their default launch configuration (the slab kernel exists for
+// that one) split.
+constexpr double kHalfStepL64 = 12.6e-6;
+constexpr double kSizeExp = 2.57;  // L = 48 measured at 0.478 of L = 64
+constexpr double kSlabExchange = 0.4e-6;
+constexpr double kSlabFloor = 4.5e-6;
 
 double unit_seconds(const BatchJobHost &h, bool slab)
 {
     const double x = (double)h.job.L / 64.0;
-    const double whole = kHalfStepL64 * x * x * x;
-    const double per_half = slab ? std::max(0.55 * whole, kSlabFloor) : whole;
+    const double whole = kHalfStepL64 * std::pow(x, kSizeExp);
+    const double per_half = slab ? std::max(0.5 * whole + kSlabExchange, kSlabFloor) : whole;
     return 2.0 * (double)std::max<uint64_t>(1, h.job.n_sweeps) * per_half;
 }
 

@@ -432,6 +432,41 @@ __device__ __forceinline__ void slab_publish(unsigned long long *pub, unsigned l
     if (threadIdx.x == 0) __hip_atomic_store(pub, value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The half-step exchange without cache maintenance.  The boundary words go
+// out with agent-scope stores, which are written through to the level shared
+// by all XCDs, and the partner reads them with agent-scope loads, which do
+// not hit a stale L2 line; so publishing only has to wait for this wave's
+// stores to complete before the counter is set, and waiting only has to see
+// the counter -- no L2 write-back or invalidation per half-step.
+__device__ __forceinline__ void store_agent(uint32_t *p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void slab_publish_words(unsigned long long *pub, unsigned long long value)
+{
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    if (threadIdx.x == 0) __hip_atomic_store(pub, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ bool slab_wait_words(unsigned long long *pub, unsigned long long want)
+{
+    int ok = 1;
+    if (threadIdx.x == 0) {
+        const unsigned long long start = __builtin_amdgcn_s_memrealtime();
+        while (__hip_atomic_load(pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want) {
+            __builtin_amdgcn_s_sleep(1);
+            if (__builtin_amdgcn_s_memrealtime() - start > kSplitSpinTicks) {
+                ok = 0;
+                break;
+            }
+        }
+    }
+    ok = __shfl(ok, 0, 64);
+    asm volatile("" ::: "memory");
+    return ok != 0;
+}
+
 // New value of slab word p (colour c, sweep t), given its z-1 and z+1
 // neighbour words of the other colour and the coupling to the z-1 neighbour.
 template <int L, int RW, int SEL>
@@ -495,7 +530,7 @@ __device__ __forceinline__ bool slab_half_step(const BatchJobDev &J, int r, int 
             own[p] = slab_new_word<L, RW, SEL>(J, r, c, t, z0, p, oth[p - S::PL], oth[p + S::PL], bz_oth[p - S::PL]);
         return true;
     }
-    if (!slab_wait(J.pub + 2 * r + (slab ^ 1), want)) return false;
+    if (!slab_wait_words(J.pub + 2 * r + (slab ^ 1), want)) return false;
     // colour c ^ 1 was last written in the previous half-step: this sweep's
     // first half-step, or the previous sweep's second
     const int rslot = (int)((c == r ? t + 1 : t) & 1u);
@@ -515,9 +550,9 @@ __device__ __forceinline__ bool slab_half_step(const BatchJobDev &J, int r, int 
             v = slab_new_word<L, RW, SEL>(J, r, c, t, z0, p, oth[p - S::PL], load_agent(part_first + j),
                                           bz_oth[p - S::PL]);
         own[p] = v;
-        slab_xbuf<S>(J, r, slab, wslot, c, k)[j] = v;
+        store_agent(slab_xbuf<S>(J, r, slab, wslot, c, k) + j, v);
     }
-    slab_publish(J.pub + 2 * r + slab, done);
+    slab_publish_words(J.pub + 2 * r + slab, done);
     return true;
 }
 
