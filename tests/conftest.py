@@ -36,3 +36,24 @@ def ea_gpu():
     import paper_1411_5512_amd as ea
     ea.abi.lib()  # raises if libea.so is missing: there is no fallback
     return ea
+
+
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def golden_values(name: str) -> dict:
+    """A tests/golden fixture of "name value  # citation" lines as a dict."""
+    out = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                key, value = line.split()
+                out[key] = float(value)
+    return out
+
+
+@pytest.fixture(scope="session")
+def paper():
+    """The results the paper prints (tests/golden/paper_values.txt)."""
+    return golden_values("paper_values.txt")

@@ -136,3 +136,12 @@ def test_fit_peak_locates_the_transition():
     assert abs(f["p_c"] - 0.23) < 0.005
     f0 = an.fit_peak(p, z - 10.5, offset=False)
     assert abs(f0["p_c"] - 0.23) < 1e-6
+
+
+def test_paper_values_fixture(paper):
+    """The printed results the GPU physics tests compare with (tests/golden)
+    are read whole and are the ordered ranges the paper states."""
+    assert paper["alpha_sg_lo"] < paper["alpha_sg_hi"] and paper["beta_sg_lo"] < paper["beta_sg_hi"]
+    assert paper["z_sg_lo"] < paper["z_sg_hi"]
+    assert paper["x_collapse"] < paper["x_sg"]  # Sec. IV: the collapse value is a bit smaller
+    assert 0.5 < paper["p_c_paper_L128"] < 1.0 and abs(paper["p_c_paper_L64"] - paper["p_c_paper_L128"]) < 0.01
