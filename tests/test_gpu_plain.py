@@ -267,6 +267,58 @@ def test_c4_shells_full_size(ea_gpu, L):
     assert np.array_equal(g.c4_shells(), got[:(L // 2) ** 2 + 1])
 
 
+def _unsat_count(S, J, L):
+    """Unsatisfied bonds of one replica, from the definition (J[3 s + d]
+    couples s = x + L (y + L z) with its + x, + y, + z neighbour)."""
+    s = S.reshape(L, L, L).astype(np.int32)  # [z][y][x]
+    j = J.reshape(L, L, L, 3).astype(np.int32)
+    return sum(int(np.count_nonzero(j[..., d] * s * np.roll(s, -1, axis=ax) < 0))
+               for d, ax in enumerate((2, 1, 0)))
+
+
+def _axis_c4(q, L):
+    """sum_x q(x) q(x + r e_d) for r = 0..L/2 along x, y, z, by FFT."""
+    g = q.reshape(L, L, L).astype(np.float64)
+    out = np.zeros((3, L // 2 + 1), dtype=np.int64)
+    for d, ax in enumerate((2, 1, 0)):
+        c = np.fft.irfft(np.abs(np.fft.rfft(g, axis=ax)) ** 2, n=L, axis=ax)
+        other = tuple(a for a in range(3) if a != ax)
+        out[d] = np.rint(c.sum(axis=other)[: L // 2 + 1]).astype(np.int64)
+    return out
+
+
+@pytest.mark.parametrize("L", [200, 256])
+def test_largest_lattices(ea_gpu, oracle_mod, L):
+    """The largest plain-form lattices (L = 256, the maximum, and L = 200,
+    not a power of two): couplings, the initial state and the state after
+    two sweeps equal the oracle's bit for bit.  The oracle's full measurement
+    takes minutes at this size, so the GPU's observables are checked against
+    their definitions (unsatisfied bonds of the Hamiltonian, magnetisation,
+    overlap, C(t, t_w) of eq. 7, C4 along the axes of eq. 3) evaluated on
+    that oracle-checked state."""
+    g = ea_gpu.Sim(L, 0.5, 0.7, seed=3, n_slots=1)
+    o = oracle_mod.Sim(L, 0.5, 0.7, seed=3)
+    _say(f"largest lattices L={L} rw={g.words_per_row}: initial state")
+    J = g.bonds()
+    assert np.array_equal(J, o.bonds())
+    _compare_state(g, o, f"L={L} t=0")
+    g.snapshot(0)
+    S0 = [g.spins(r) for r in (0, 1)]
+    g.sweep(2)
+    o.sweep(2)
+    _say(f"largest lattices L={L}: after two sweeps")
+    _compare_state(g, o, f"L={L} t=2")
+    obs = g.measure()
+    S = [g.spins(r) for r in (0, 1)]
+    assert obs.t == 2
+    assert list(obs.unsat) == [_unsat_count(S[r], J, L) for r in (0, 1)]
+    assert list(obs.mag) == [int(S[r].astype(np.int64).sum()) for r in (0, 1)]
+    q = S[0].astype(np.int64) * S[1]
+    assert obs.overlap == int(q.sum())
+    assert list(obs.autocorr[:, 0]) == [int((S[r].astype(np.int64) * S0[r]).sum()) for r in (0, 1)]
+    assert np.array_equal(obs.c4, _axis_c4(q, L))
+
+
 def test_c4_shells_errors(ea_gpu):
     g = ea_gpu.Sim(16, 0.5, 0.8, seed=1)
     for n in (0, 3 * 64 + 2):
