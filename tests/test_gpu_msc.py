@@ -8,6 +8,8 @@ import sys
 import numpy as np
 import pytest
 
+from definitions import axis_c4, unsat_count
+
 pytestmark = pytest.mark.gpu
 
 
@@ -169,6 +171,47 @@ def test_full_size_two_word_sets(ea_gpu, oracle_mod):
         oo = o.measure()
         assert list(ob.unsat) == list(oo.unsat) and ob.overlap == oo.overlap
         assert np.array_equal(ob.c4, oo.c4)
+
+
+@pytest.mark.parametrize("B", [256, 1])
+def test_largest_lattice(ea_gpu, oracle_mod, B):
+    """L = 256, the largest side, with the most samples (256: eight word
+    sets) and with one (32 slabs of 8 planes): couplings and states of the
+    first and last sample equal the oracle's (shared noise) at t = 0 and after
+    two sweeps; the observables of up to three samples equal their
+    definitions on the GPU's state (the oracle's full measurement takes
+    minutes at this size), and every sample has C4(0) = N."""
+    L, N = 256, 256 ** 3
+    g = ea_gpu.Msc(L, B, 0.5, 0.8, seed=4, sample0=0, shared=3, n_slots=1)
+    _say(f"msc largest L={L} B={B}")
+    g.snapshot(0)
+    picked = sorted({0, B // 2, B - 1})
+    first = {b: [g.spins(b, r) for r in (0, 1)] for b in picked}
+    g.sweep(2)
+    for b in sorted({0, B - 1}):
+        _say(f"  sample {b} against the oracle")
+        o = oracle_mod.Sim(L, 0.5, 0.8, seed=4, sample=b)
+        o.share_noise(3)
+        assert np.array_equal(g.bonds(b), o.bonds()), b
+        for r in (0, 1):
+            assert np.array_equal(first[b][r], o.spins(r)), (b, r)
+        o.sweep(2)
+        for r in (0, 1):
+            assert np.array_equal(g.spins(b, r), o.spins(r)), (b, r)
+    obs = g.measure()
+    for ob in obs:
+        assert ob.t == 2 and ob.c4[0][0] == ob.c4[1][0] == ob.c4[2][0] == N
+    for b in picked:
+        _say(f"  sample {b} against the definitions")
+        S = [g.spins(b, r) for r in (0, 1)]
+        J = g.bonds(b)
+        ob = obs[b]
+        assert list(ob.unsat) == [unsat_count(S[r], J, L) for r in (0, 1)], b
+        assert list(ob.mag) == [int(S[r].astype(np.int64).sum()) for r in (0, 1)], b
+        q = S[0].astype(np.int64) * S[1]
+        assert ob.overlap == int(q.sum()), b
+        assert list(ob.autocorr[:, 0]) == [int((S[r].astype(np.int64) * first[b][r]).sum()) for r in (0, 1)], b
+        assert np.array_equal(ob.c4, axis_c4(q, L)), b
 
 
 def test_msc_errors(ea_gpu):

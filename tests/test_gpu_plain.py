@@ -6,6 +6,8 @@ import sys
 import numpy as np
 import pytest
 
+from definitions import axis_c4, unsat_count
+
 pytestmark = pytest.mark.gpu
 
 
@@ -267,26 +269,6 @@ def test_c4_shells_full_size(ea_gpu, L):
     assert np.array_equal(g.c4_shells(), got[:(L // 2) ** 2 + 1])
 
 
-def _unsat_count(S, J, L):
-    """Unsatisfied bonds of one replica, from the definition (J[3 s + d]
-    couples s = x + L (y + L z) with its + x, + y, + z neighbour)."""
-    s = S.reshape(L, L, L).astype(np.int32)  # [z][y][x]
-    j = J.reshape(L, L, L, 3).astype(np.int32)
-    return sum(int(np.count_nonzero(j[..., d] * s * np.roll(s, -1, axis=ax) < 0))
-               for d, ax in enumerate((2, 1, 0)))
-
-
-def _axis_c4(q, L):
-    """sum_x q(x) q(x + r e_d) for r = 0..L/2 along x, y, z, by FFT."""
-    g = q.reshape(L, L, L).astype(np.float64)
-    out = np.zeros((3, L // 2 + 1), dtype=np.int64)
-    for d, ax in enumerate((2, 1, 0)):
-        c = np.fft.irfft(np.abs(np.fft.rfft(g, axis=ax)) ** 2, n=L, axis=ax)
-        other = tuple(a for a in range(3) if a != ax)
-        out[d] = np.rint(c.sum(axis=other)[: L // 2 + 1]).astype(np.int64)
-    return out
-
-
 @pytest.mark.parametrize("L", [200, 256])
 def test_largest_lattices(ea_gpu, oracle_mod, L):
     """The largest plain-form lattices (L = 256, the maximum, and L = 200,
@@ -311,12 +293,12 @@ def test_largest_lattices(ea_gpu, oracle_mod, L):
     obs = g.measure()
     S = [g.spins(r) for r in (0, 1)]
     assert obs.t == 2
-    assert list(obs.unsat) == [_unsat_count(S[r], J, L) for r in (0, 1)]
+    assert list(obs.unsat) == [unsat_count(S[r], J, L) for r in (0, 1)]
     assert list(obs.mag) == [int(S[r].astype(np.int64).sum()) for r in (0, 1)]
     q = S[0].astype(np.int64) * S[1]
     assert obs.overlap == int(q.sum())
     assert list(obs.autocorr[:, 0]) == [int((S[r].astype(np.int64) * S0[r]).sum()) for r in (0, 1)]
-    assert np.array_equal(obs.c4, _axis_c4(q, L))
+    assert np.array_equal(obs.c4, axis_c4(q, L))
 
 
 def test_c4_shells_errors(ea_gpu):
