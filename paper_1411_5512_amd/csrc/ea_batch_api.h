@@ -457,7 +457,7 @@ ea_status batch_create_cfg(const ea_job *jobs, int32_t n_jobs, void *stream, con
 // ---------------------------------------------------------------------------
 // Autotuner.  For one lattice size it times every valid combination of row
 // packing (the default and the next finer one, if its lattice fits LDS),
-// working threads per workgroup (256, 512, 1024, capped by the word count)
+// working threads per workgroup (256, 512, 768, 1024, capped by the word count)
 // and threshold-select variant on a probe batch of 64 samples, keeps only
 // candidates whose results equal the default configuration's bit for bit,
 // and picks the fastest.  Choices are cached per process and, if the
@@ -527,7 +527,7 @@ std::vector<TuneCfg> tune_candidates(int L, size_t lds_limit)
         if (rw == 0) continue;
         if (4 * (size_t)batch_lds_words(L, rw) + 4 * (size_t)ea::kSelectTableWords > lds_limit) continue;
         const int words = L * L * rw;
-        for (int nt : {256, 512, 1024}) {
+        for (int nt : {256, 512, 768, 1024}) {  // 768: three z-planes per thread at L = 48
             if (nt > round_up64(words) && nt != 256) continue;
             for (int sel : {(int)ea::SEL_LDS, (int)ea::SEL_REG}) {
                 TuneCfg c;
