@@ -216,14 +216,28 @@ ea_status launch_init(ea_sim *s)
     return launch_init_lattice(s->lat, s->geom(), s->lay.W, s->seed, s->sample, s->pcut, s->stream);
 }
 
+// Half-step launches with at least this many threads (four waves per SIMD
+// on 256 CUs) screen the rare uphill moves (ea::accept_screened); smaller
+// ones are bound by one wave's latency and keep the plain select.
+constexpr long kScreenThreads = 262144;
+
+int screen_for(long threads) { return threads >= kScreenThreads ? 1 : 0; }
+
 ea_status launch_half_step(ea_sim *s, int half, uint32_t t_off)
 {
     ea::Geom g = s->geom();
     dim3 grid(blocks_for(g.plane), 2, 1);
-    EA_DISPATCH_W(s->lay.W,
-                  hipLaunchKernelGGL((ea::half_step_kernel<WW>), grid, dim3(256), 0, s->stream, s->lat, g,
-                                      half, s->t_dev, t_off, key_lo(s), key_hi(s), s->sample, s->thr[0],
-                                      s->thr[1], s->thr[2]));
+    if (screen_for(2L * g.plane)) {
+        EA_DISPATCH_W(s->lay.W,
+                      hipLaunchKernelGGL((ea::half_step_kernel<WW, true>), grid, dim3(256), 0, s->stream, s->lat,
+                                          g, half, s->t_dev, t_off, key_lo(s), key_hi(s), s->sample, s->thr[0],
+                                          s->thr[1], s->thr[2]));
+    } else {
+        EA_DISPATCH_W(s->lay.W,
+                      hipLaunchKernelGGL((ea::half_step_kernel<WW, false>), grid, dim3(256), 0, s->stream, s->lat,
+                                          g, half, s->t_dev, t_off, key_lo(s), key_hi(s), s->sample, s->thr[0],
+                                          s->thr[1], s->thr[2]));
+    }
     return EA_OK;
 }
 
@@ -536,8 +550,15 @@ ea_status ea_sweep_group(ea_sim *const *sims, int32_t n_sims, uint64_t n)
             for (size_t c = 0; c < chunks.size(); ++c) {
                 const int32_t cnt = std::min<int32_t>(ea::kGroupMax, n_sims - (int32_t)c * ea::kGroupMax);
                 const dim3 grid(blocks_for(g.plane), 2, (unsigned)cnt);
-                EA_DISPATCH_W(lead->lay.W, hipLaunchKernelGGL((ea::group_half_step_kernel<WW>), grid, dim3(256), 0,
-                                                             lead->stream, chunks[c], g, half, (uint32_t)k));
+                if (screen_for(2L * g.plane * cnt)) {
+                    EA_DISPATCH_W(lead->lay.W,
+                                  hipLaunchKernelGGL((ea::group_half_step_kernel<WW, true>), grid, dim3(256), 0,
+                                                     lead->stream, chunks[c], g, half, (uint32_t)k));
+                } else {
+                    EA_DISPATCH_W(lead->lay.W,
+                                  hipLaunchKernelGGL((ea::group_half_step_kernel<WW, false>), grid, dim3(256), 0,
+                                                     lead->stream, chunks[c], g, half, (uint32_t)k));
+                }
             }
     EA_HIP(hipGetLastError());
     ea_status st = group_event(lead);

@@ -61,13 +61,66 @@ __global__ __launch_bounds__(256) void init_kernel(Lattice lat, Geom g, uint32_t
     dst[tid] = bits;
 }
 
+// Bit i set iff u[i] < thr, for all W words (two instructions per site).
+template <int J, int W>
+__device__ __forceinline__ uint32_t below_words(uint32_t accept, const uint32_t (&u)[W], uint32_t thr)
+{
+    accept = append_below4(accept, u[4 * J + 3], thr, u[4 * J + 2], thr, u[4 * J + 1], thr, u[4 * J], thr);
+    if constexpr (J > 0)
+        return below_words<J - 1, W>(accept, u, thr);
+    else
+        return accept;
+}
+
+// The same acceptance as accept_words, cheaper where uphill moves of
+// dE >= 8 are rare.  If none of the W random words falls below thr2 (and
+// thr3 <= thr2), every site with n = 1 or n = 0 is rejected, and a site with
+// n = 2 (any & ~always) flips iff its word is below thr1: one compare and
+// one append per site instead of a per-site threshold select.  Lanes where
+// some word is below thr2 take the general select, so the decisions are the
+// same either way.  Used only while a wave meets such a word rarely (thr2 W
+// < 2^24, i.e. 64 W thr2 / 2^32 < 1/4 expected per wave), where both
+// branches would otherwise run in most waves, and only in launches with
+// several waves per SIMD (SCREEN): a wave that runs alone on its SIMD
+// is bound by its chain of dependent instructions, which the screen
+// lengthens (measured 9% slower for one L = 128 run, 7-12% faster for 5-16
+// runs in one launch).  A separate instantiation, so that the unscreened
+// kernels keep their own schedule.
+template <int W, bool SCREEN>
+__device__ __forceinline__ uint32_t accept_screened(const Decision &d, const uint32_t (&u)[W], uint32_t thr1,
+                                                    uint32_t thr2, uint32_t thr3)
+{
+    if constexpr (!SCREEN) return accept_words<W / 4 - 1, W>(0u, d, u, thr1, thr2, thr3);
+    const bool rare = (uint64_t)thr2 * (uint64_t)W < (1ull << 24) && thr3 <= thr2;  // uniform
+    if (rare) {
+        // the n = 2 compares and a three-way minimum tree (depth 4 for
+        // W = 32) are independent, so their latencies overlap
+        const uint32_t a1 = below_words<W / 4 - 1, W>(0u, u, thr1);
+        uint32_t v[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) v[i] = u[i];
+#pragma unroll
+        for (int n = W; n > 1; n = (n + 2) / 3) {
+#pragma unroll
+            for (int i = 0; 3 * i < n; ++i) {
+                uint32_t m = v[3 * i];
+                if (3 * i + 1 < n) m = min(m, v[3 * i + 1]);
+                if (3 * i + 2 < n) m = min(m, v[3 * i + 2]);
+                v[i] = m;
+            }
+        }
+        if (v[0] >= thr2) return a1 & d.any & ~d.always;
+    }
+    return accept_words<W / 4 - 1, W>(0u, d, u, thr1, thr2, thr3);
+}
+
 // --------------------------------------------------------------------------
 // One checkerboard half-step (Sec. III, eq. 9) of sweep t = *t_base + t_off
 // (the base lives on the device so that a captured graph of sweeps can be
 // replayed).  grid.y = replica r, which updates colour c = r ^ half; all six
 // neighbours of a colour-c site have colour 1 - c, so every thread reads the
 // other colour and writes only its own word.  One thread per (row, word).
-template <int W>
+template <int W, bool SCREEN>
 __device__ __forceinline__ void half_step_word(const Lattice &lat, const Geom &g, int half, uint32_t t, int r,
                                                int tid, uint32_t k0, uint32_t k1, uint32_t sample, uint32_t thr1,
                                                uint32_t thr2, uint32_t thr3)
@@ -124,13 +177,13 @@ __device__ __forceinline__ void half_step_word(const Lattice &lat, const Geom &g
     const uint32_t a6 = xor3(S, Zm, Bzm);
 
     const Decision d = classify(a1, a2, a3, a4, a5, a6);
-    // the register select: this launch is latency-bound, an LDS table would
-    // add a fill and a barrier to every block
-    const uint32_t flips = d.always | accept_words<W / 4 - 1, W>(0u, d, u, thr1, thr2, thr3);
+    // register selects, no LDS table: a table would add a fill and a barrier
+    // to every block of a launch this short
+    const uint32_t flips = d.always | accept_screened<W, SCREEN>(d, u, thr1, thr2, thr3);
     own[base + w] = S ^ flips;
 }
 
-template <int W>
+template <int W, bool SCREEN>
 __global__ __launch_bounds__(256) void half_step_kernel(Lattice lat, Geom g, int half,
                                                         const uint32_t *__restrict__ t_base, uint32_t t_off,
                                                         uint32_t k0, uint32_t k1, uint32_t sample,
@@ -138,7 +191,8 @@ __global__ __launch_bounds__(256) void half_step_kernel(Lattice lat, Geom g, int
 {
     const int tid = xcd_block((int)blockIdx.x, (int)gridDim.x) * (int)blockDim.x + (int)threadIdx.x;
     if (tid >= g.plane) return;
-    half_step_word<W>(lat, g, half, *t_base + t_off, (int)blockIdx.y, tid, k0, k1, sample, thr1, thr2, thr3);
+    half_step_word<W, SCREEN>(lat, g, half, *t_base + t_off, (int)blockIdx.y, tid, k0, k1, sample, thr1, thr2,
+                              thr3);
 }
 
 // Several runs of the same geometry in one launch: grid.z = member.  Each
@@ -156,14 +210,14 @@ struct GroupArgs {
     GroupMember m[kGroupMax];
 };
 
-template <int W>
+template <int W, bool SCREEN>
 __global__ __launch_bounds__(256) void group_half_step_kernel(GroupArgs a, Geom g, int half, uint32_t t_off)
 {
     const int tid = xcd_block((int)blockIdx.x, (int)gridDim.x) * (int)blockDim.x + (int)threadIdx.x;
     if (tid >= g.plane) return;
     const GroupMember &M = a.m[blockIdx.z];
-    half_step_word<W>(M.lat, g, half, *M.t_base + t_off, (int)blockIdx.y, tid, M.k0, M.k1, M.sample, M.thr1,
-                      M.thr2, M.thr3);
+    half_step_word<W, SCREEN>(M.lat, g, half, *M.t_base + t_off, (int)blockIdx.y, tid, M.k0, M.k1, M.sample,
+                              M.thr1, M.thr2, M.thr3);
 }
 
 // --------------------------------------------------------------------------

@@ -360,6 +360,24 @@ def test_sweep_group_equals_single_runs(ea_gpu, L, n_runs, rw):
             assert np.array_equal(a.spins(r), b.spins(r)), (L, i, r)
 
 
+@pytest.mark.parametrize("T", [0.7, 0.88])
+def test_screened_group_matches_oracle(ea_gpu, oracle_mod, T):
+    """Launches with four or more waves per SIMD (here four runs of L = 128
+    in one group) screen the rare uphill moves of dE >= 8 with one minimum
+    per word; at T = 0.88 about one wave in five meets such a random word
+    and takes the general select for those lanes, at T = 0.7 one in fifty.
+    Every member equals its oracle run."""
+    L = 128
+    params = [(0.5, 3, 0), (0.3, 3, 1), (0.2, 8, 2), (0.5, 9, 5)]
+    grp = [ea_gpu.Sim(L, p, T, seed=s, sample=k) for (p, s, k) in params]
+    _say(f"screened group L={L} x{len(grp)} T={T}")
+    ea_gpu.sweep_group(grp, 2)
+    for i, (p, s, k) in enumerate(params):
+        o = oracle_mod.Sim(L, p, T, seed=s, sample=k)
+        o.sweep(2)
+        _compare_state(grp[i], o, f"screened member {i} T={T}")
+
+
 def test_sweep_group_errors(ea_gpu):
     a = ea_gpu.Sim(16, 0.5, 0.8, seed=1)
     b = ea_gpu.Sim(16, 0.5, 0.8, seed=2)
