@@ -598,7 +598,7 @@ ea_status ea_measure(ea_sim *s, ea_obs *out)
     EA_DISPATCH_W(y.W, hipLaunchKernelGGL((ea::measure_kernel<WW>), dim3(blocks_for(2 * (size_t)g.plane)),
                                            dim3(256), 0, s->stream, s->lat, g, s->snaps, slots, s->meas));
     if (out->c4) {
-        dim3 grid(blocks_for(2 * (size_t)g.rows), 3 * (unsigned)(y.R + 1), 1);
+        dim3 grid(blocks_for(2 * (size_t)g.rows), 3 * (unsigned)ea::c4_chunks(y.R), 1);
         EA_DISPATCH_W(y.W, hipLaunchKernelGGL((ea::c4_kernel<WW>), grid, dim3(256), 0, s->stream,
                                                s->lat, g, s->meas + c4_base));
     }

@@ -301,44 +301,62 @@ __device__ __forceinline__ uint32_t q_word(const Lattice &lat, const Geom &g, in
     return lat.spins[plane_off(g, 0, c) + i] ^ lat.spins[plane_off(g, 1, c) + i];
 }
 
-// C4 block (eq. 3): grid.y = d (R+1) + rho, one thread per (colour, row).
-// The partner of site (x,y,z) is (x,y,z) + rho e_d, of colour c ^ (rho & 1).
-// Along y and z it sits at the same half index of the partner row; along x,
-// on a row with x = 2 xh + par, its half index is xh + rho/2 (rho even) or
-// xh + (rho-1)/2 + par (rho odd), modulo R.
+// C4 block (eq. 3): one thread per (colour, row) and chunk of kC4Rho
+// consecutive displacements rho along one axis d; grid.y = d nchunk + chunk,
+// nchunk = ceil((R + 1) / kC4Rho).  The thread reads each of its q words once
+// and compares it with the partner word of every rho of its chunk, then each
+// rho's count is summed over the wave.  The partner of site (x,y,z) is
+// (x,y,z) + rho e_d, of colour c ^ (rho & 1).  Along y and z it sits at the
+// same half index of the partner row; along x, on a row with x = 2 xh + par,
+// its half index is xh + rho/2 (rho even) or xh + (rho-1)/2 + par (rho odd),
+// modulo R.
+constexpr int kC4Rho = 8;
+
+__host__ __device__ constexpr int c4_chunks(int R) { return (R + kC4Rho) / kC4Rho; }
+
 template <int W>
 __global__ __launch_bounds__(256) void c4_kernel(Lattice lat, Geom g, unsigned long long *acc)
 {
     const int gid = blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = gid < 2 * g.rows;
-    const int d = blockIdx.y / (g.R + 1);
-    const int rho = blockIdx.y - d * (g.R + 1);
-    uint32_t diff = 0;
+    const int nchunk = c4_chunks(g.R);
+    const int d = blockIdx.y / nchunk;
+    const int r0 = (blockIdx.y - d * nchunk) * kC4Rho;
+    uint32_t diff[kC4Rho];
+#pragma unroll
+    for (int k = 0; k < kC4Rho; ++k) diff[k] = 0u;
     if (live) {
         const int c = gid / g.rows;
         const int row = gid - c * g.rows;
         const int y = row % g.L;
         const int z = row / g.L;
-        const int cp = c ^ (rho & 1);
-        if (d == 0) {
-            const int par = (y + z + c) & 1;
-            const int k = (rho & 1) ? (rho - 1) / 2 + par : rho / 2;
-            for (int w = 0; w < g.RW; ++w) {
-                const int start = (w * W + k) % g.R;
-                const int wi = start / W;
-                const int off = start - wi * W;
-                const uint32_t lo = q_word(lat, g, cp, row, wi);
-                const uint32_t hi = q_word(lat, g, cp, row, wi + 1 == g.RW ? 0 : wi + 1);
-                const uint32_t win = off == 0 ? lo : (((lo >> off) | (hi << (W - off))) & word_mask<W>());
-                diff += __popc(q_word(lat, g, c, row, w) ^ win);
+        const int par = (y + z + c) & 1;
+        for (int w = 0; w < g.RW; ++w) {
+            const uint32_t own = q_word(lat, g, c, row, w);
+#pragma unroll
+            for (int k = 0; k < kC4Rho; ++k) {
+                const int rho = r0 + k;
+                if (rho > g.R) break;  // uniform: the chunk's tail past R
+                const int cp = c ^ (rho & 1);
+                if (d == 0) {
+                    const int kx = (rho & 1) ? (rho - 1) / 2 + par : rho / 2;
+                    const int start = (w * W + kx) % g.R;
+                    const int wi = start / W;
+                    const int off = start - wi * W;
+                    const uint32_t lo = q_word(lat, g, cp, row, wi);
+                    const uint32_t hi = q_word(lat, g, cp, row, wi + 1 == g.RW ? 0 : wi + 1);
+                    const uint32_t win = off == 0 ? lo : (((lo >> off) | (hi << (W - off))) & word_mask<W>());
+                    diff[k] += __popc(own ^ win);
+                } else {
+                    const int prow = d == 1 ? (y + rho) % g.L + g.L * z : y + g.L * ((z + rho) % g.L);
+                    diff[k] += __popc(own ^ q_word(lat, g, cp, prow, w));
+                }
             }
-        } else {
-            const int prow = d == 1 ? (y + rho) % g.L + g.L * z : y + g.L * ((z + rho) % g.L);
-            for (int w = 0; w < g.RW; ++w)
-                diff += __popc(q_word(lat, g, c, row, w) ^ q_word(lat, g, cp, prow, w));
         }
     }
-    wave_add(acc + blockIdx.y, diff);
+#pragma unroll
+    for (int k = 0; k < kC4Rho; ++k)
+        if (r0 + k <= g.R) wave_add(acc + d * (g.R + 1) + r0 + k, diff[k]);
 }
 
 // --------------------------------------------------------------------------
