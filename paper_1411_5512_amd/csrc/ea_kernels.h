@@ -239,6 +239,23 @@ __device__ __forceinline__ void wave_add(unsigned long long *dst, uint32_t v)
     if ((threadIdx.x & 63) == 0 && v) atomicAdd(dst, (unsigned long long)v);
 }
 
+// The same for a whole 256-thread block: one atomic per block instead of
+// one per wave, since every wave of a launch adds into the same few counters
+// and atomics on one address serialise.  Every thread of the block calls it,
+// the same number of times (it synchronises the block).
+__device__ __forceinline__ void block_add(unsigned long long *dst, uint32_t v)
+{
+    __shared__ uint32_t part[256 / 64];
+    v = wave_sum(v);
+    __syncthreads();  // the previous call has read part
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t t = part[0] + part[1] + part[2] + part[3];
+        if (t) atomicAdd(dst, (unsigned long long)t);
+    }
+}
+
 // Counter layout of one measurement (all uint64):
 //   [0,1] unsatisfied bonds of replica 0/1
 //   [2,3] spins with S = -1, replica 0/1
@@ -281,15 +298,15 @@ __global__ __launch_bounds__(256) void measure_kernel(Lattice lat, Geom g, const
                     __popc(xor3(S[r], oth[row_yp * g.RW + w], lat.bonds[plane_off(g, 1, c) + base + w])) +
                     __popc(xor3(S[r], oth[row_zp * g.RW + w], lat.bonds[plane_off(g, 2, c) + base + w]));
         }
-        wave_add(acc + M_UNSAT + r, unsat);
-        wave_add(acc + M_DOWN + r, __popc(S[r]));
+        block_add(acc + M_UNSAT + r, unsat);
+        block_add(acc + M_DOWN + r, __popc(S[r]));
     }
-    wave_add(acc + M_QDIFF, __popc(S[0] ^ S[1]));
+    block_add(acc + M_QDIFF, __popc(S[0] ^ S[1]));
     for (int k = 0; k < n_slots; ++k) {
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
             const uint32_t ref = live ? snaps[((size_t)k * 2 + r) * 2 * g.plane + plane_off(g, 0, c) + tid] : 0u;
-            wave_add(acc + M_AUTO + 2 * k + r, __popc(S[r] ^ ref));
+            block_add(acc + M_AUTO + 2 * k + r, __popc(S[r] ^ ref));
         }
     }
 }
@@ -356,7 +373,7 @@ __global__ __launch_bounds__(256) void c4_kernel(Lattice lat, Geom g, unsigned l
     }
 #pragma unroll
     for (int k = 0; k < kC4Rho; ++k)
-        if (r0 + k <= g.R) wave_add(acc + d * (g.R + 1) + r0 + k, diff[k]);
+        if (r0 + k <= g.R) block_add(acc + d * (g.R + 1) + r0 + k, diff[k]);
 }
 
 // --------------------------------------------------------------------------
