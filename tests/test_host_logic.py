@@ -82,3 +82,23 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0 and "one GPU" in r.stderr
+
+
+def test_profile_commands_run_committed_files():
+    """Every rocprofv3 command in profiles/ profiles a committed program
+    (bench.py) run from the repository root, and every summary is short text."""
+    import glob
+    import os
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    tracked = set(subprocess.run(["git", "ls-files"], cwd=root, capture_output=True, text=True).stdout.split())
+    files = sorted(glob.glob(os.path.join(root, "profiles", "*")))
+    assert files
+    for path in files:
+        assert path.endswith((".md", ".txt")) and os.path.getsize(path) < 16384, path
+        for line in open(path):
+            if line.startswith("rocprofv3 "):
+                prog = line.split(" -- ", 1)[1].split()
+                assert prog[0] in ("python3", "python"), line
+                if tracked:
+                    assert prog[1] in tracked, line
