@@ -37,6 +37,9 @@ def test_every_declared_symbol_is_exported(ealib):
 
 def test_thresholds_match_oracle(ealib, oracle_mod):
     import paper_1411_5512_amd as ea
+    from test_oracle_rng import EXACT_THRESHOLDS
+    for T, want in EXACT_THRESHOLDS.items():  # eq. (9) floor rule, worked out in decimals
+        assert tuple(int(v) for v in ea.thresholds(T)) == want, T
     for T in [0.0, 0.3, 0.5, 0.6, 0.7, 0.8, 1.0, 1.2, 4.5, 1e300]:
         assert list(ea.thresholds(T)) == list(oracle_mod.thresholds(T))
     with pytest.raises(ea.EAError):

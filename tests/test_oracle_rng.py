@@ -2,8 +2,11 @@
 
 Philox4x32-10 is pinned against an independent implementation (rocRAND's
 host-callable engine, compiled and run here as a black box).  The thresholds
-are pinned by properties of the exponential in eq. (9) and by their limits.
+are pinned to their closed form thr_k = floor(exp(-4k/T) 2^32) (eq. 9 with the
+uint32 floor quantisation), evaluated here in 60-digit decimal arithmetic, by
+properties of the exponential and by their limits.
 """
+from decimal import Decimal, localcontext
 import math
 import os
 import shutil
@@ -105,3 +108,71 @@ def test_thresholds_are_powers_of_one_factor(oracle_mod, T):
     assert abs(t3 - (t1 / two32) * (t2 / two32) * two32) <= 2.5
     # and the factor is the Boltzmann weight of dE = 4 at temperature T
     assert abs(math.log(a) * T + 4.0) < 1e-6 * max(1.0, T) or t1 < 1000
+
+
+# floor(exp(-4k/T) 2^32) for k = 1, 2, 3, worked out in 60-digit decimals
+# (eq. 9 for dE = 4, 8, 12 and the floor rule of the uint32 compare).  The
+# fractional parts are listed so that the table shows which entries a
+# rounding or ceiling rule would change: at T = 0.6 thr_3 is 8.85 -> 8.
+EXACT_THRESHOLDS = {
+    0.5: (1440801, 483, 0),
+    0.6: (5465920, 6956, 8),        # fractions .557 .115 .853
+    0.7: (14166974, 46729, 154),    # fractions .347 .846 .139
+    0.8: (28939262, 194991, 1313),  # fractions .003 .214 .840
+    1.0: (78665070, 1440801, 26389),
+    1.2: (153218634, 5465920, 194991),
+    0.513: (1764607, 724, 0),       # thr_2 = 724.997
+    0.569: (3801220, 3364, 2),      # thr_3 = 2.977
+    2.0: (581260615, 78665070, 10646159),
+}
+
+
+def _exact_floor(T: float, k: int) -> tuple[int, float]:
+    """floor(exp(-4k/T) 2^32) and its fractional part, in 60-digit decimals
+    (T taken as the exact binary value of the double)."""
+    with localcontext() as ctx:
+        ctx.prec = 60
+        v = (Decimal(-4 * k) / Decimal(T)).exp() * Decimal(1 << 32)
+        f = int(v)
+        return f, float(v - f)
+
+
+def test_threshold_table_is_the_closed_form():
+    """The literal table above is floor(exp(-4k/T) 2^32) (checks the table)."""
+    for T, want in EXACT_THRESHOLDS.items():
+        assert tuple(_exact_floor(T, k)[0] for k in (1, 2, 3)) == want, T
+
+
+@pytest.mark.parametrize("T", sorted(EXACT_THRESHOLDS))
+def test_thresholds_exact_floor_table(oracle_mod, T):
+    """eq. (9): u < thr_k accepts dE = 4k with probability thr_k / 2^32, and
+    thr_k = floor(exp(-4k/T) 2^32) exactly -- a round or ceiling rule fails
+    at T = 0.6 (thr_3 8.85), 0.7 (thr_2 .846), 0.513 and 0.569."""
+    assert tuple(int(v) for v in oracle_mod.thresholds(T)) == EXACT_THRESHOLDS[T]
+
+
+def test_thresholds_exact_on_a_grid(oracle_mod):
+    """The floor rule at 400 temperatures in (0.05, 20], wherever the decimal
+    value is not within double rounding (1e-5 units) of an integer."""
+    checked = 0
+    for i in range(1, 401):
+        T = 0.05 * i
+        got = [int(v) for v in oracle_mod.thresholds(T)]
+        for k in (1, 2, 3):
+            f, frac = _exact_floor(T, k)
+            if 1e-5 < frac < 1 - 1e-5:
+                assert got[k - 1] == min(f, 0xffffffff), (T, k)
+                checked += 1
+    assert checked > 1000
+
+
+def test_thresholds_clamp_at_infinite_temperature(oracle_mod):
+    """As T -> infinity exp(-4k/T) 2^32 -> 2^32, which does not fit a uint32:
+    the threshold clamps to 2^32 - 1 (every uphill move but u = 2^32 - 1
+    accepted); just below the clamp the floor still holds."""
+    assert list(oracle_mod.thresholds(1e300)) == [0xffffffff] * 3
+    assert list(oracle_mod.thresholds(float(1 << 60))) == [0xffffffff] * 3
+    T = 1e6
+    assert [int(v) for v in oracle_mod.thresholds(T)] == [_exact_floor(T, k)[0] for k in (1, 2, 3)]
+    assert all(v < 0xffffffff for v in oracle_mod.thresholds(T))
+    assert list(oracle_mod.thresholds(0.0)) == [0, 0, 0]
