@@ -303,8 +303,11 @@ def _exponents(ea_gpu, an, p, seed=2024, n_sweeps=100_000):
 
 
 def test_paper_batch_reproduces_spin_glass_exponents(ea_gpu, paper):
-    """The paper's production batch (128^3, 64 samples sharing the random
-    words, p = 0.5, T = 0.8), 10^5 sweeps with C4 at log-spaced t_w from 10:
+    """A physics sanity check, not a parity test (parity of the multispin
+    batch is the bit-exact comparison with the oracle above; this pins no
+    function).  The paper's production batch (128^3, 64 samples sharing the
+    random words, p = 0.5, T = 0.8), 10^5 sweeps with C4 at log-spaced t_w
+    from 10:
     the eq. 4 multifit gives alpha and beta in the spin-glass ranges of
     Sec. IV (Fig. 3), and the coherence length grows with z in the
     spin-glass range of Fig. 5 (the paper's values: tests/golden).  The run
@@ -323,7 +326,8 @@ def test_paper_batch_reproduces_spin_glass_exponents(ea_gpu, paper):
 
 
 def test_crossover_z_peak_locates_the_transition(ea_gpu, paper):
-    """Sec. IV's crossover analysis on multispin batches (128^3 x 64, T = 0.8,
+    """A physics sanity check, not a parity test (it pins no function).
+    Sec. IV's crossover analysis on multispin batches (128^3 x 64, T = 0.8,
     10^5 sweeps each) across p: z(p) peaks at the spin-glass/ferromagnet
     transition, and a Gaussian fitted to the peak puts it within 0.015 of the
     paper's L = 128 value (Fig. 5; in the paper's convention p counts
@@ -353,7 +357,8 @@ def test_crossover_z_peak_locates_the_transition(ea_gpu, paper):
 
 
 def test_equilibrium_exponent_and_collapse(ea_gpu, paper):
-    """Sec. IV's autocorrelation analysis on a multispin batch (64^3 x 64
+    """A physics sanity check, not a parity test (it pins no function).
+    Sec. IV's autocorrelation analysis on a multispin batch (64^3 x 64
     samples, p = 0.5, T = 0.8, 1.2e6 sweeps, snapshots at t_w = 1e4, 1e5,
     1e6): the power law C_eq ~ t^-x (eq. 8) fitted over t in [100, t_w/1000]
     gives x within 0.006 of the paper's spin-glass value (Fig. 7), and the x

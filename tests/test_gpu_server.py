@@ -57,12 +57,14 @@ def test_server_mix_equals_alone(ea_gpu):
     assert st["completed"] == len(jobs) and st["pending"] == 0 and st["resident"] == 0
     assert 0 < st["hbm_peak"] <= budget
     assert st["epochs"] > 1 and st["p99_latency_s"] >= st["p50_latency_s"] > 0
-    alone = ea_gpu.Batch(jobs)
-    alone.run()
+    # the reference: every job in a batch of its own (one job, one launch)
     for i, (jid, job) in enumerate(zip(ids, jobs)):
         assert srv.poll(jid) == ea_gpu.JOB_DONE
+        alone = ea_gpu.Batch([job])
+        alone.run()
         for k in range(len(job.meas_t)):
-            _same_obs(srv.result(jid, k), alone.result(i, k), f"job {i} meas {k}")
+            _same_obs(srv.result(jid, k), alone.result(0, k), f"job {i} meas {k}")
+        alone.close()
         assert srv.latency(jid) > 0
 
 
