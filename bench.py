@@ -215,6 +215,28 @@ def plain_rate(ea, torch, L: int, sweeps: int = 256) -> float:
     return ms * 1e-3 / (sweeps * 2 * L ** 3) * 1e12
 
 
+def alu_probe():
+    """Sustained lane rate of the instructions the roofline counts as one
+    lane-op each (libea_probe.so, event-timed launches of 4 waves per SIMD
+    on every CU): v_mad_u64_u32, v_bitop3_b32, and whole Philox4x32-10
+    blocks at 40 lane-ops each."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1411_5512_amd", "libea_probe.so"))
+    lib.ea_probe_alu.restype = ctypes.c_int
+    lib.ea_probe_alu.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_double)]
+    out = {"peak_tops": round(VALU_PEAK_TOPS, 2), "blocks": 256 * 16, "threads_per_block": 256}
+    for kind, name, iters in ((0, "v_mad_u64_u32", 20000), (1, "v_bitop3_b32", 20000), (2, "philox4x32_10", 4000)):
+        ms, ops = ctypes.c_double(0.0), ctypes.c_double(0.0)
+        rc = lib.ea_probe_alu(kind, 256 * 16, iters, ctypes.byref(ms), ctypes.byref(ops))
+        if rc != 0:
+            raise RuntimeError(f"ea_probe_alu({name}) failed: {rc}")
+        tops = ops.value / (ms.value * 1e-3) / 1e12
+        out[name] = {"ms": round(ms.value, 3), "lane_ops": ops.value, "tops": round(tops, 3),
+                     "frac_of_peak": round(tops / VALU_PEAK_TOPS, 4)}
+    return out
+
+
 def bench_msc(ea, torch, job, burst: int):
     """The multispin-coded batch (asynchronous multispin coding, shared random
     words) on the paper's production configuration: the whole schedule once
@@ -371,6 +393,9 @@ def main():
     ap.add_argument("--msc-only", action="store_true", help="run only the multispin-coded leg and print it")
     ap.add_argument("--crossover-sweeps", type=int, default=10_000,
                     help="sweeps of each crossover run in the grouped-plain leg (0 = skip)")
+    ap.add_argument("--alu-probe", action="store_true",
+                    help="only measure the lane rate of v_mad_u64_u32, v_bitop3_b32 and whole Philox4x32-10 "
+                         "blocks against the integer-ALU peak (the roofline's op count) and exit")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (a known-size kernel "
                          "for calibrating hardware byte counters) and exit")
@@ -388,6 +413,10 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+
+    if args.alu_probe:
+        print(json.dumps({"alu_probe": alu_probe()}), flush=True)
+        return
 
     if args.copy_probe_mib:
         n = args.copy_probe_mib << 20

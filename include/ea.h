@@ -157,8 +157,9 @@ ea_status ea_reset(ea_sim *sim, uint64_t seed, uint32_t sample);
  * t + n would reach 2^32 (the sweep index is one counter word). */
 ea_status ea_sweep(ea_sim *sim, uint64_t n);
 
-/* Advance n_sims runs of the same L and words_per_row by n sweeps each in
- * one launch per half-step (up to 16 runs per launch), giving exactly the
+/* Advance n_sims runs of the same L and words_per_row by n sweeps each,
+ * up to 16 runs per launch (slab launches as in ea_set_slab_plan, else one
+ * launch per half-step), giving exactly the
  * spins that n_sims separate ea_sweep calls give (Sec. III's update; every
  * run keeps its own key, sample, T and sweep counter).  For several small
  * independent samples, such as Sec. IV's L = 128 averages, whose single
@@ -170,6 +171,31 @@ ea_status ea_sweep(ea_sim *sim, uint64_t n);
  * fastest when its members use the densest packing (fewest words per row),
  * since it needs no extra threads to fill the device. */
 ea_status ea_sweep_group(ea_sim *const *sims, int32_t n_sims, uint64_t n);
+
+/* Persistent slab path of the plain form.  ea_sweep and ea_sweep_group run
+ * a lattice whose plane of one colour has at most 1024 packed words
+ * (L x words_per_row <= 1024) in one persistent launch per call (up to 16384
+ * sweeps each; longer calls are split): every replica is cut into `slabs`
+ * z-slabs of consecutive planes, each held with `ghost` extra planes on
+ * either side in one workgroup's LDS, and the slabs exchange their boundary
+ * planes through device memory once every `ghost` half-steps.  The ghost
+ * planes are updated redundantly with the same keyed random words as their
+ * owners', so results are bit-identical to one launch per half-step
+ * (Sec. III's schedule).  slabs: 0 = the library's choice (the default),
+ * -1 = off (one launch per half-step), 1..L = that many slabs per replica;
+ * ghost: 0 = the library's choice for that slab count, else 1..8.
+ * EA_ERR_ARG if the plan does not fit the device with one workgroup per
+ * compute unit (2 x slabs workgroups per run) or a slab with its ghost
+ * planes does not fit one workgroup's LDS.  Every workgroup of a launch must
+ * be resident at once: if work of other streams keeps compute units busy for
+ * seconds, the launch gives up and the next synchronising call (ea_sync,
+ * ea_measure, ea_get_spins) returns EA_ERR_DEVICE; the run's state is then
+ * undefined until ea_reset.  ea_sweep_group follows the first run's setting.
+ * Allocates nothing (the exchange area is part of ea_footprint). */
+ea_status ea_set_slab_plan(ea_sim *sim, int32_t slabs, int32_t ghost);
+/* The plan ea_sweep uses for this run alone: slabs per replica and ghost
+ * planes, or slabs = -1 and ghost = 0 when it launches once per half-step. */
+ea_status ea_get_slab_plan(const ea_sim *sim, int32_t *slabs, int32_t *ghost);
 
 /* Store the current spins as reference S(t_w) in slot k, t_w = t. */
 ea_status ea_snapshot(ea_sim *sim, int32_t slot);

@@ -128,6 +128,19 @@ class Sim:
         abi.check(abi.lib().ea_words_per_row(self._h, ctypes.byref(rw)))
         return rw.value
 
+    def set_slab_plan(self, slabs: int = 0, ghost: int = 0):
+        """Slab path of ea_sweep (see ea_set_slab_plan): slabs 0 = the
+        library's choice, -1 = one launch per half-step, else that many
+        z-slabs per replica with `ghost` ghost planes (0 = library's choice)."""
+        abi.check(abi.lib().ea_set_slab_plan(self._h, int(slabs), int(ghost)))
+
+    @property
+    def slab_plan(self) -> tuple:
+        """(slabs per replica, ghost planes) ea_sweep uses; (-1, 0) when off."""
+        k, g = ctypes.c_int32(0), ctypes.c_int32(0)
+        abi.check(abi.lib().ea_get_slab_plan(self._h, ctypes.byref(k), ctypes.byref(g)))
+        return k.value, g.value
+
     # -- lifetime -------------------------------------------------------
     def close(self):
         if self._h is not None and self._h.value:

@@ -161,6 +161,9 @@ _SIGS = {
     "ea_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
     "ea_set_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
     "ea_sync": (ctypes.c_int, [ctypes.c_void_p]),
+    "ea_set_slab_plan": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "ea_get_slab_plan": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int32)]),
     "ea_get_spins": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int8)]),
     "ea_set_spins": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int8)]),
     "ea_get_bonds": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int8)]),

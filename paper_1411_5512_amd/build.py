@@ -12,6 +12,9 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libea.so")
 SOURCES = ["ea_api.hip"]
+# instruction-rate probes behind the ALU roofline (loaded by bench.py only)
+PROBE_LIB = os.path.join(PKG, "libea_probe.so")
+PROBE_SOURCES = ["ea_probe.hip"]
 ARCH = "gfx950"
 
 
@@ -27,10 +30,16 @@ def compile_flags() -> list[str]:
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every source into libea.so (always recompiles)."""
-    tmp = LIB + ".tmp"
+    """Compile libea.so and libea_probe.so (always recompiles)."""
+    _compile(SOURCES, LIB, verbose)
+    _compile(PROBE_SOURCES, PROBE_LIB, verbose)
+    return LIB
+
+
+def _compile(sources: list[str], out: str, verbose: bool) -> str:
+    tmp = out + ".tmp"
     cmd = [hipcc(), *compile_flags(), "-shared", "-o", tmp,
-           *[os.path.join(CSRC, s) for s in SOURCES]]
+           *[os.path.join(CSRC, s) for s in sources]]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -40,8 +49,8 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError(f"hipcc failed ({res.returncode}):\n{err}")
     if verbose and err.strip():
         print(err, file=sys.stderr)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

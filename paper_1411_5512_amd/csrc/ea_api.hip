@@ -3,6 +3,7 @@
 // form (one launch per checkerboard half-step).
 #include "ea.h"
 #include "ea_batch_kernels.h"
+#include "ea_slab_kernels.h"
 
 #include <chrono>
 #include <cmath>
@@ -91,9 +92,66 @@ void read_plain_tune_file()
     std::fclose(f);
 }
 
+// Whether the persistent slab path can run a lattice of side L in this
+// packing: one z-plane of one colour (L rw words) must fit one workgroup's
+// threads.
+bool slab_capable(int L, int rw) { return L * rw <= ea::kSlabThreads; }
+
+// Modelled time per sweep (us) of a plan, used to pick one: per half-step
+// the slab's planes times the cost of a packed word on one compute unit (at
+// least one word's dependent chain) plus a barrier, per cycle one exchange
+// (~1 us; with g = 1 the interior planes, updated after the boundary ones,
+// hide part of it).
+double slab_model_us(int L, int rw, int K, int g)
+{
+    const int W = L / 2 / rw, PL = L * rw;
+    const double per_word = 13.2 * W + 40.0;        // VALU lane-instructions per packed word
+    const double rate = 64.0 * 2400.0 / per_word;   // words per us on one compute unit
+    const double chain = per_word * 4.0 / 2400.0;   // one word alone on its SIMD, us
+    const double exchange = 1.0, barrier = 0.1;
+    const int s = (L + K - 1) / K;
+    double cycle = 0.0;
+    for (int k = 1; k <= g; ++k) cycle += std::max(chain, (double)(s + 2 * g - 2 * k) * PL / rate) + barrier;
+    double exposed = exchange;
+    if (g == 1 && s > 2) exposed = std::max(0.2, exchange - (double)(s - 2) * PL / rate);
+    return 2.0 * (cycle + exposed) / g;
+}
+
+// Modelled time per sweep of the best plan for one run of side L in packing
+// rw on a device of 256 compute units with 160 KiB of LDS per workgroup
+// (the plan itself is chosen per launch from the real device), or a negative
+// value when the packing cannot run as slabs.
+double slab_best_model_us(int L, int rw)
+{
+    if (!slab_capable(L, rw)) return -1.0;
+    double best = -1.0;
+    for (int K = 1; K <= L && 2 * K <= 256; ++K)
+        for (int g = 1; g <= 4; ++g) {
+            const int emax = (L + K - 1) / K + 2 * g;
+            if (4 * (8 * (size_t)emax * (size_t)(L * rw) + 16) > 160 * 1024) continue;
+            const double c = slab_model_us(L, rw, K, g);
+            if (best < 0.0 || c < best) best = c;
+        }
+    return best;
+}
+
+// Default packing: for lattices that run as slabs the packing whose best
+// slab plan the model rates fastest; otherwise the coarsest packing refined
+// until one half-step launch has at least kPlainMinThreads threads.
 int plain_default_rw(int L)
 {
     const int R = L / 2;
+    int best_rw = 0;
+    double best = 0.0;
+    for (int d = 1; d <= R / 4; ++d) {
+        if (!rw_valid(R, d)) continue;
+        const double c = slab_best_model_us(L, d);
+        if (c >= 0.0 && (best_rw == 0 || c < best)) {
+            best = c;
+            best_rw = d;
+        }
+    }
+    if (best_rw) return best_rw;
     int rw = words_per_row(R);
     for (int d = rw + 1; d <= R / 4 && 2 * (long)L * L * rw < kPlainMinThreads; ++d)
         if (rw_valid(R, d)) rw = d;
@@ -110,9 +168,13 @@ int plain_rw(int L)
 
 struct Layout {
     int L, R, RW, W, rows, plane;
-    size_t spin_words, bond_words, snap_words, meas_count;
-    size_t off_spins, off_bonds, off_snaps, off_meas, off_ctl, total;
+    size_t spin_words, bond_words, snap_words, meas_count, xbuf_entries;
+    size_t off_spins, off_bonds, off_snaps, off_meas, off_ctl, off_xbuf, total;
 };
+
+// Control words (in the 256-byte control area).
+constexpr size_t kCtlTime = 0;   // uint32 sweep counter base of the captured graph
+constexpr size_t kCtlErr = 64;   // uint32 error word of the slab launches
 
 Layout make_layout(int L, int n_slots, int rw)
 {
@@ -132,7 +194,10 @@ Layout make_layout(int L, int n_slots, int rw)
     y.off_snaps = align256(y.off_bonds + 4 * y.bond_words);
     y.off_meas = align256(y.off_snaps + 4 * y.snap_words);
     y.off_ctl = align256(y.off_meas + 8 * y.meas_count);
-    y.total = align256(y.off_ctl + 256);
+    // slab exchange entries: [replica][slot][colour][plane] 64-bit words
+    y.xbuf_entries = slab_capable(L, rw) ? (size_t)ea::kSlabSlots * 4 * (size_t)y.plane : 0;
+    y.off_xbuf = align256(y.off_ctl + 256);
+    y.total = align256(y.off_xbuf + 8 * y.xbuf_entries);
     return y;
 }
 
@@ -167,6 +232,15 @@ struct ea_sim {
     unsigned long long *c4_scratch = nullptr;
     // event ordering this run's stream with a group sweep (created on first use)
     hipEvent_t group_event = nullptr;
+    // persistent slab path: plan (slabs per replica: 0 automatic, -1 off;
+    // ghost planes: 0 automatic), exchange entries and their epoch serial
+    int32_t slab_K = 0, slab_g = 0;
+    unsigned long long *xbuf = nullptr;
+    uint64_t xserial = 0;
+    bool xbuf_clean = false;
+    bool slab_used = false;
+    uint32_t *err_dev = nullptr;
+    int device = 0;  // the device current at ea_create
 
     ea::Geom geom() const
     {
@@ -276,6 +350,190 @@ ea_status build_graph(ea_sim *s)
         return fail(EA_ERR_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
     }
     s->graph = graph;
+    return EA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Persistent slab path (ea_slab_kernels.h).  A plan cuts each replica into K
+// z-slabs, one workgroup each, with g ghost planes per side (g half-steps per
+// exchange).  Every workgroup of a launch must be resident at once, so the
+// grid never exceeds what the device holds; with work of other streams on
+// the device a launch may wait for compute units, and a launch that cannot
+// become whole within seconds ends with the error word set.
+
+constexpr uint32_t kSlabMaxSweeps = 16384;  // sweeps per launch (a launch stays well under a second)
+constexpr int kSlabMaxGhost = 8;
+
+struct SlabPlan {
+    int K = 0, g = 0, emax = 0;
+    size_t lds = 0;  // dynamic LDS bytes
+};
+
+size_t slab_lds_bytes(int L, int rw, int emax) { return 4 * (8 * (size_t)emax * (size_t)(L * rw) + 16); }
+
+std::mutex g_slab_mu;
+int g_slab_cus = 0, g_slab_lds_limit = 0;
+bool g_slab_attr[33] = {};
+
+// Compute units and the LDS a workgroup may use (queried once), and the
+// kernel attribute that lets the instantiation for width W use all of it.
+ea_status slab_device(int W, int *n_cu, int *lds_limit)
+{
+    std::lock_guard<std::mutex> lk(g_slab_mu);
+    if (!g_slab_cus) {
+        int dev = 0;
+        EA_HIP(hipGetDevice(&dev));
+        EA_HIP(hipDeviceGetAttribute(&g_slab_cus, hipDeviceAttributeMultiprocessorCount, dev));
+        EA_HIP(hipDeviceGetAttribute(&g_slab_lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    }
+    if (W < 4 || W > 32 || W % 4) return fail(EA_ERR_STATE, "unsupported word width %d", W);
+    if (!g_slab_attr[W]) {
+        const void *fn = nullptr;
+        switch (W) {
+        case 4: fn = (const void *)ea::slab_sweep_kernel<4>; break;
+        case 8: fn = (const void *)ea::slab_sweep_kernel<8>; break;
+        case 12: fn = (const void *)ea::slab_sweep_kernel<12>; break;
+        case 16: fn = (const void *)ea::slab_sweep_kernel<16>; break;
+        case 20: fn = (const void *)ea::slab_sweep_kernel<20>; break;
+        case 24: fn = (const void *)ea::slab_sweep_kernel<24>; break;
+        case 28: fn = (const void *)ea::slab_sweep_kernel<28>; break;
+        default: fn = (const void *)ea::slab_sweep_kernel<32>; break;
+        }
+        EA_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, g_slab_lds_limit));
+        g_slab_attr[W] = true;
+    }
+    *n_cu = g_slab_cus;
+    *lds_limit = g_slab_lds_limit;
+    return EA_OK;
+}
+
+bool slab_plan_fits(int L, int rw, int n_runs, int K, int g, int n_cu, int lds_limit, SlabPlan *out)
+{
+    if (K < 1 || K > L || g < 1 || g > kSlabMaxGhost || g > L) return false;
+    if ((long)2 * n_runs * K > (long)n_cu) return false;  // one 1024-thread workgroup per compute unit
+    const int emax = (L + K - 1) / K + 2 * g;
+    const size_t lds = slab_lds_bytes(L, rw, emax);
+    if (lds > (size_t)lds_limit) return false;
+    out->K = K;
+    out->g = g;
+    out->emax = emax;
+    out->lds = lds;
+    return true;
+}
+
+// The plan for n_runs runs of side L in packing rw: the requested one
+// (K > 0; g = 0 picks the best ghost depth for it), else the modelled best.
+ea_status slab_choose(int L, int rw, int n_runs, int K_req, int g_req, SlabPlan *plan)
+{
+    if (!slab_capable(L, rw)) return fail(EA_ERR_ARG, "L=%d with %d words per row has no slab plan", L, rw);
+    int n_cu = 0, lds_limit = 0;
+    ea_status st = slab_device(L / 2 / rw, &n_cu, &lds_limit);
+    if (st != EA_OK) return st;
+    double best = 0.0;
+    bool found = false;
+    const int k_lo = K_req > 0 ? K_req : 1, k_hi = K_req > 0 ? K_req : L;
+    const int g_lo = g_req > 0 ? g_req : 1, g_hi = g_req > 0 ? g_req : 4;
+    for (int K = k_lo; K <= k_hi; ++K)
+        for (int g = g_lo; g <= g_hi; ++g) {
+            SlabPlan p;
+            if (!slab_plan_fits(L, rw, n_runs, K, g, n_cu, lds_limit, &p)) continue;
+            const double c = slab_model_us(L, rw, K, g);
+            if (!found || c < best) {
+                best = c;
+                *plan = p;
+                found = true;
+            }
+        }
+    if (!found)
+        return fail(EA_ERR_ARG, "no slab plan (K=%d, g=%d) fits %d run(s) of L=%d on %d compute units", K_req,
+                    g_req, n_runs, L, n_cu);
+    return EA_OK;
+}
+
+// The plan a run uses alone (K = -1: the slab path is off for it).
+ea_status slab_plan_of(const ea_sim *s, int n_runs, SlabPlan *plan)
+{
+    if (s->slab_K < 0 || !slab_capable(s->lay.L, s->lay.RW)) {
+        plan->K = -1;
+        return EA_OK;
+    }
+    return slab_choose(s->lay.L, s->lay.RW, n_runs, s->slab_K, s->slab_g, plan);
+}
+
+// Advance runs[0..n) (same L and packing, at most kGroupMax) by n sweeps with
+// slab launches on the first run's stream.
+ea_status launch_slab(ea_sim *const *runs, int n, uint64_t sweeps, const SlabPlan &plan)
+{
+    ea_sim *lead = runs[0];
+    const Layout &y = lead->lay;
+    for (int i = 0; i < n; ++i) {
+        ea_sim *m = runs[i];
+        if (!m->xbuf_clean) {  // entries of no earlier epoch
+            hipLaunchKernelGGL(ea::zero_u64_kernel, dim3(blocks_for(y.xbuf_entries)), dim3(256), 0, lead->stream,
+                               m->xbuf, y.xbuf_entries);
+            m->xbuf_clean = true;
+            m->xserial = 0;
+        }
+        m->slab_used = true;
+    }
+    uint64_t done = 0;
+    while (done < sweeps) {
+        const uint32_t chunk = (uint32_t)std::min<uint64_t>(kSlabMaxSweeps, sweeps - done);
+        ea::SlabLaunch a{};
+        a.L = y.L;
+        a.RW = y.RW;
+        a.K = plan.K;
+        a.g = plan.g;
+        a.emax = plan.emax;
+        a.n_half = 2 * chunk;
+        a.err = lead->err_dev;
+        const uint64_t n_cycles = (a.n_half + (uint64_t)plan.g - 1) / (uint64_t)plan.g;
+        for (int i = 0; i < n; ++i) {
+            ea_sim *m = runs[i];
+            if ((m->xserial & 0xffffffffull) + n_cycles + 2 >= (1ull << 32)) {
+                // the 32-bit epochs would wrap: start over from cleared entries
+                hipLaunchKernelGGL(ea::zero_u64_kernel, dim3(blocks_for(y.xbuf_entries)), dim3(256), 0,
+                                   lead->stream, m->xbuf, y.xbuf_entries);
+                m->xserial = 0;
+            }
+            ea::SlabRunDev &d = a.runs[i];
+            d.spins = m->lat.spins;
+            d.bonds = m->lat.bonds;
+            d.xbuf = m->xbuf;
+            d.k0 = key_lo(m);
+            d.k1 = key_hi(m);
+            d.sample = m->sample;
+            d.thr1 = m->thr[0];
+            d.thr2 = m->thr[1];
+            d.thr3 = m->thr[2];
+            d.t0 = (uint32_t)(m->t + done);
+            d.serial = (uint32_t)m->xserial;
+            m->xserial += n_cycles + 1;
+        }
+        const dim3 grid((unsigned)(2 * n * plan.K));
+        EA_DISPATCH_W(y.W, hipLaunchKernelGGL((ea::slab_sweep_kernel<WW>), grid, dim3(ea::kSlabThreads), plan.lds,
+                                              lead->stream, a));
+        EA_HIP(hipGetLastError());
+        done += chunk;
+    }
+    // the launch-wide error word is the lead's; the others copy it
+    for (int i = 1; i < n; ++i)
+        hipLaunchKernelGGL(ea::or_word_kernel, dim3(1), dim3(64), 0, lead->stream, runs[i]->err_dev, lead->err_dev);
+    EA_HIP(hipGetLastError());
+    return EA_OK;
+}
+
+// After a synchronisation: EA_ERR_DEVICE if a slab launch of the run gave up
+// waiting for a neighbouring slab (the run's state is then undefined until
+// ea_reset).
+ea_status slab_check(ea_sim *s)
+{
+    if (!s->slab_used) return EA_OK;
+    uint32_t e = 0;
+    EA_HIP(hipMemcpy(&e, s->err_dev, 4, hipMemcpyDeviceToHost));
+    if (e)
+        return fail(EA_ERR_DEVICE, "a slab launch gave up waiting for a neighbouring slab (its workgroups were not "
+                                   "all resident within seconds); the run's state is undefined until ea_reset");
     return EA_OK;
 }
 
@@ -401,7 +659,11 @@ ea_status ea_create_ex(const ea_config *cfg, ea_sim **out)
     host_thresholds(cfg->T, s->thr);
     s->pcut = (uint64_t)std::floor(std::ldexp(cfg->p, 32));
 
-    hipError_t e;
+    hipError_t e = hipGetDevice(&s->device);
+    if (e != hipSuccess) {
+        delete s;
+        return fail(EA_ERR_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    }
     if (cfg->stream) {
         s->stream = (hipStream_t)cfg->stream;
     } else {
@@ -426,7 +688,10 @@ ea_status ea_create_ex(const ea_config *cfg, ea_sim **out)
     s->lat.bonds = (uint32_t *)(s->buf + lay.off_bonds);
     s->snaps = (uint32_t *)(s->buf + lay.off_snaps);
     s->meas = (unsigned long long *)(s->buf + lay.off_meas);
-    s->t_dev = (uint32_t *)(s->buf + lay.off_ctl);
+    s->t_dev = (uint32_t *)(s->buf + lay.off_ctl + kCtlTime);
+    s->err_dev = (uint32_t *)(s->buf + lay.off_ctl + kCtlErr);
+    s->xbuf = lay.xbuf_entries ? (unsigned long long *)(s->buf + lay.off_xbuf) : nullptr;
+    hipLaunchKernelGGL(ea::zero_u32_kernel, dim3(1), dim3(64), 0, s->stream, s->err_dev, (size_t)1);
 
     ea_status st = launch_init(s);
     if (st != EA_OK) {
@@ -467,6 +732,7 @@ ea_status ea_reset(ea_sim *s, uint64_t seed, uint32_t sample)
     if (s->graph) (void)hipGraphDestroy(s->graph);
     s->graph_exec = nullptr;
     s->graph = nullptr;
+    hipLaunchKernelGGL(ea::zero_u32_kernel, dim3(1), dim3(64), 0, s->stream, s->err_dev, (size_t)1);
     return launch_init(s);
 }
 
@@ -476,6 +742,16 @@ ea_status ea_sweep(ea_sim *s, uint64_t n)
     if (s->t + n >= (1ull << 32) || n >= (1ull << 32))
         return fail(EA_ERR_ARG, "t + n = %llu would reach 2^32", (unsigned long long)(s->t + n));
     if (n == 0) return EA_OK;
+    SlabPlan plan;
+    ea_status pst = slab_plan_of(s, 1, &plan);
+    if (pst != EA_OK) return pst;
+    if (plan.K > 0) {
+        ea_sim *one[1] = {s};
+        pst = launch_slab(one, 1, n, plan);
+        if (pst != EA_OK) return pst;
+        s->t += n;
+        return EA_OK;
+    }
     hipLaunchKernelGGL(ea::set_u32_kernel, dim3(1), dim3(64), 0, s->stream, s->t_dev, (uint32_t)s->t);
     uint64_t left = n;
     if (left >= kGraphSweeps) {
@@ -526,6 +802,25 @@ ea_status ea_sweep_group(ea_sim *const *sims, int32_t n_sims, uint64_t n)
         EA_HIP(hipEventRecord(sims[i]->group_event, sims[i]->stream));
         EA_HIP(hipStreamWaitEvent(lead->stream, sims[i]->group_event, 0));
     }
+    SlabPlan plan;
+    {
+        const int per = std::min<int32_t>(ea::kGroupMax, n_sims);
+        ea_status pst = slab_plan_of(lead, per, &plan);
+        if (pst != EA_OK) return pst;
+    }
+    if (plan.K > 0) {
+        // one slab launch per chunk of at most kGroupMax runs
+        for (int32_t c0 = 0; c0 < n_sims; c0 += ea::kGroupMax) {
+            const int cnt = std::min<int32_t>(ea::kGroupMax, n_sims - c0);
+            SlabPlan pc = plan;
+            if (cnt != std::min<int32_t>(ea::kGroupMax, n_sims)) {
+                ea_status pst = slab_plan_of(lead, cnt, &pc);
+                if (pst != EA_OK) return pst;
+            }
+            ea_status st = launch_slab(sims + c0, cnt, n, pc);
+            if (st != EA_OK) return st;
+        }
+    } else {
     ea::Geom g = lead->geom();
     for (int32_t i = 0; i < n_sims; ++i)
         hipLaunchKernelGGL(ea::set_u32_kernel, dim3(1), dim3(64), 0, lead->stream, sims[i]->t_dev,
@@ -560,6 +855,7 @@ ea_status ea_sweep_group(ea_sim *const *sims, int32_t n_sims, uint64_t n)
                                                      lead->stream, chunks[c], g, half, (uint32_t)k));
                 }
             }
+    }
     EA_HIP(hipGetLastError());
     ea_status st = group_event(lead);
     if (st != EA_OK) return st;
@@ -606,6 +902,8 @@ ea_status ea_measure(ea_sim *s, ea_obs *out)
     EA_HIP(hipMemcpyAsync(s->host_meas.data(), s->meas, n_count * sizeof(unsigned long long),
                           hipMemcpyDeviceToHost, s->stream));
     EA_HIP(hipStreamSynchronize(s->stream));
+    ea_status est = slab_check(s);
+    if (est != EA_OK) return est;
 
     const int64_t N = (int64_t)y.L * y.L * y.L;
     const unsigned long long *m = s->host_meas.data();
@@ -682,6 +980,40 @@ ea_status ea_sync(ea_sim *s)
 {
     if (!s) return fail(EA_ERR_ARG, "sim is NULL");
     EA_HIP(hipStreamSynchronize(s->stream));
+    return slab_check(s);
+}
+
+ea_status ea_set_slab_plan(ea_sim *s, int32_t slabs, int32_t ghost)
+{
+    if (!s) return fail(EA_ERR_ARG, "sim is NULL");
+    if (slabs < -1 || slabs > s->lay.L) return fail(EA_ERR_ARG, "slabs=%d outside [-1, L=%d]", slabs, s->lay.L);
+    if (ghost < 0 || ghost > kSlabMaxGhost) return fail(EA_ERR_ARG, "ghost=%d outside [0, %d]", ghost, kSlabMaxGhost);
+    if (slabs != -1 && !slab_capable(s->lay.L, s->lay.RW))
+        return fail(EA_ERR_ARG, "L=%d with %d words per row cannot run as slabs (a plane of one colour has more "
+                                "than %d words)", s->lay.L, s->lay.RW, ea::kSlabThreads);
+    const int32_t old_K = s->slab_K, old_g = s->slab_g;
+    s->slab_K = slabs;
+    s->slab_g = ghost;
+    if (slabs > 0) {  // the plan must fit a launch of this run alone
+        SlabPlan plan;
+        ea_status st = slab_plan_of(s, 1, &plan);
+        if (st != EA_OK) {
+            s->slab_K = old_K;
+            s->slab_g = old_g;
+            return st;
+        }
+    }
+    return EA_OK;
+}
+
+ea_status ea_get_slab_plan(const ea_sim *s, int32_t *slabs, int32_t *ghost)
+{
+    if (!s || !slabs || !ghost) return fail(EA_ERR_ARG, "NULL argument");
+    SlabPlan plan;
+    ea_status st = slab_plan_of(s, 1, &plan);
+    if (st != EA_OK) return st;
+    *slabs = plan.K;
+    *ghost = plan.K > 0 ? plan.g : 0;
     return EA_OK;
 }
 
@@ -774,6 +1106,8 @@ ea_status ea_get_spins(ea_sim *s, int32_t r, int8_t *pm1)
     EA_HIP(hipMemcpyAsync(words.data(), s->lat.spins + (size_t)r * 2 * y.plane, words.size() * 4,
                           hipMemcpyDeviceToHost, s->stream));
     EA_HIP(hipStreamSynchronize(s->stream));
+    ea_status est = slab_check(s);
+    if (est != EA_OK) return est;
     const int64_t N = (int64_t)y.L * y.L * y.L;
     for (int64_t i = 0; i < N; ++i) {
         SiteAddr a = address_of(y, i);

@@ -198,6 +198,22 @@ ea_status server_advance_streamed(ServerJob &j, uint64_t t_stop)
     return EA_OK;
 }
 
+// Streamed jobs run as slab launches (ea_set_slab_plan) from up to
+// kStreamWorkers threads at once, beside the batched launch: each job's plan
+// uses at most 1/kStreamWorkers of the compute units, so that the slab
+// launches in flight always fit the device together once the batched launch
+// has drained; a lattice whose slabs would not fit LDS at that share uses
+// one launch per half-step.
+ea_status server_slab_plan(ea_sim *sim)
+{
+    int dev = 0, n_cu = 0;
+    EA_HIP(hipGetDevice(&dev));
+    EA_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    const int K = std::max(1, n_cu / (2 * kStreamWorkers));
+    if (ea_set_slab_plan(sim, K, 0) == EA_OK) return EA_OK;
+    return ea_set_slab_plan(sim, -1, 0);
+}
+
 // One epoch: retire, admit, launch, wait.  Returns EA_OK with *progressed = 0
 // when nothing was resident or admissible.
 ea_status server_epoch(ea_server *s, int32_t *progressed)
@@ -232,6 +248,7 @@ ea_status server_epoch(ea_server *s, int32_t *progressed)
                 c.dev_buf_bytes = j->h.bytes;
                 c.words_per_row = j->h.RW;  // the packing its footprint was planned with
                 st = ea_create_ex(&c, &j->sim);
+                if (st == EA_OK) st = server_slab_plan(j->sim);
                 j->results.assign((size_t)j->h.job.n_meas * (size_t)j->h.obs_stride, 0ull);
             } else {
                 st = upload_schedule(j->h, s->stream);

@@ -52,12 +52,15 @@ def test_footprint_and_bad_arguments(ealib):
     import paper_1411_5512_amd as ea
     # densest packing (32 sites per word where the row allows): 2 replicas x N
     # bits of spins + 3N bits of couplings (plus padding); W sites per 32-bit
-    # word cost 32 / W times that
-    for L, rw, W in ((16, 1, 8), (64, 1, 32), (128, 2, 32), (64, 8, 4), (96, 4, 12)):
+    # word cost 32 / W times that.  A packing that can run as slabs (a colour
+    # plane of L rw <= 1024 words) adds the exchange area: 3 slots x 2
+    # replicas x 2 colours of 64-bit entries per packed word.
+    for L, rw, W in ((16, 1, 8), (64, 1, 32), (128, 2, 32), (64, 8, 4), (96, 4, 12), (256, 8, 16)):
         fp = ea.footprint(L, words_per_row=rw)
         dense = 5 * L ** 3 // 8 * 32 // W
-        assert dense <= fp < dense + 4096 + 8 * 2000, (L, rw)
-        assert ea.footprint(L) >= ea.footprint(L, words_per_row={16: 1, 64: 1, 128: 2, 96: 2}[L])
+        xbuf = 12 * 8 * L * L * rw if L * rw <= 1024 else 0
+        assert dense + xbuf <= fp < dense + xbuf + 4096 + 8 * 2000, (L, rw)
+        assert ea.footprint(L) >= ea.footprint(L, words_per_row={16: 1, 64: 1, 128: 2, 96: 2, 256: 4}[L])
     assert ea.footprint(64, 3, words_per_row=1) - ea.footprint(64, 0, words_per_row=1) >= 3 * 2 * 64 ** 3 // 8
     for L, rw in ((64, 3), (64, 16), (96, 5), (16, 0 - 1)):  # not whole 4-site blocks, or W < 4
         with pytest.raises(ea.EAError):

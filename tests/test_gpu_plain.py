@@ -1,6 +1,9 @@
-"""Parity of the plain GPU path (one launch per checkerboard half-step)
-against the CPU oracle: bit-exact couplings, spins and every integer
-observable, on the same seeds and schedules."""
+"""Parity of the plain GPU path (ea_sweep with its default plan: the
+persistent slab launches for every lattice whose plane of one colour fits a
+workgroup, one launch per checkerboard half-step otherwise) against the CPU
+oracle: bit-exact couplings, spins and every integer observable, on the same
+seeds and schedules.  test_gpu_slab.py covers explicit slab plans and the
+one-launch-per-half-step path."""
 import sys
 
 import numpy as np
