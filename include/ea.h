@@ -148,6 +148,19 @@ ea_status ea_words_per_row(const ea_sim *sim, int32_t *rw);
  * ea_destroy.  EA_ERR_ARG for L > 128 or n_shells outside [1, 3 (L/2)^2 + 1]. */
 ea_status ea_c4_shells(ea_sim *sim, int32_t n_shells, int64_t *out);
 
+/* ea_c4_shells for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * The same shell sums, written as int64 to the caller's device array
+ * out_dev[n_shells] (device memory, caller-owned), enqueued on the run's
+ * stream without synchronising: they are valid once the stream has reached
+ * this call.  The scratch (the dense overlap rows) is a static device array
+ * of 512 KiB on every device the library runs on, held until the process
+ * ends; hence L <= 128 (EA_ERR_ARG beyond, and for n_shells outside
+ * [1, 3 (L/2)^2 + 1]).  All calls on one device share that array: calls
+ * that overlap on a device (runs on different streams) race, so order them
+ * on one stream or synchronise between them.  Allocates nothing. */
+ea_status ea_c4_shells_into(ea_sim *sim, int32_t n_shells, int64_t *out_dev);
+
 /* Restart the run in place for another disorder sample: regenerate the
  * couplings and both replicas' initial spins for (seed, sample), set t = 0
  * and forget every snapshot; asynchronous, allocates nothing. */

@@ -961,6 +961,97 @@ ea_status ea_c4_shells(ea_sim *s, int32_t n_shells, int64_t *out)
     return EA_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Scratch of ea_c4_shells_into: the dense q rows of the largest side with
+// full-vector C4 (L = 128: 128 x 128 rows of 4 doubled 64-bit words,
+// 512 KiB), one array per device for the life of the process.  Host code
+// never passes the array's name to a kernel: it passes the device address
+// that hipGetSymbolAddress returned for that device.
+constexpr size_t kScratchWords = (size_t)kMaxShellL * kMaxShellL * 2 * ((kMaxShellL + 63) / 64);
+__device__ __align__(256) unsigned long long scratch[kScratchWords];
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+unsigned long long *g_scratch_ptr[kScratchDevices] = {};  // per device, set on the first call there
+
+// The scratch array's address on `device` (made current by the caller).
+ea_status scratch_on(int device, unsigned long long **out)
+{
+    if (device < 0 || device >= kScratchDevices)
+        return fail(EA_ERR_DEVICE, "device %d beyond the %d the library tracks", device, kScratchDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[(size_t)device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(EA_ERR_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", device,
+                        hipGetErrorString(e));
+        g_scratch_ptr[(size_t)device] = (unsigned long long *)p;
+    }
+    *out = g_scratch_ptr[(size_t)device];
+    return EA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ea_status ea_c4_shells_into(ea_sim *s, int32_t n_shells, int64_t *out_dev)
+{
+    if (!s || !out_dev) return fail(EA_ERR_ARG, "NULL argument");
+    const int L = s->lay.L;
+    if (L > kMaxShellL)
+        return fail(EA_ERR_ARG, "full-vector C4 is offered for L <= %d (L=%d): the scratch array holds the dense "
+                                "overlap of L = %d at most", kMaxShellL, L, kMaxShellL);
+    const int max_shells = 3 * (L / 2) * (L / 2) + 1;
+    if (n_shells < 1 || n_shells > max_shells)
+        return fail(EA_ERR_ARG, "n_shells=%d outside [1, %d]", n_shells, max_shells);
+    const int nw = (L + 63) / 64;
+    const int dw = 2 * nw;
+    const size_t q_words = (size_t)L * L * dw;
+    if (q_words > kScratchWords) return fail(EA_ERR_ARG, "L=%d needs %zu scratch words, %zu exist", L, q_words,
+                                             kScratchWords);
+    int cur = 0;
+    EA_HIP(hipGetDevice(&cur));
+    if (cur != s->device) EA_HIP(hipSetDevice(s->device));
+    unsigned long long *qd = nullptr;
+    ea_status st = scratch_on(s->device, &qd);
+    if (st == EA_OK) {
+        unsigned long long *shells = (unsigned long long *)out_dev;
+        hipLaunchKernelGGL(ea::zero_u64_kernel, dim3(blocks_for((size_t)n_shells)), dim3(256), 0, s->stream,
+                           shells, (size_t)n_shells);
+        ea::Geom g = s->geom();
+        switch (s->lay.W) {
+#define EA_DENSE_Q(WW)                                                                                         \
+    case WW:                                                                                                   \
+        hipLaunchKernelGGL((ea::dense_q_kernel<WW>), dim3(blocks_for(q_words)), dim3(256), 0, s->stream, s->lat, \
+                           g, dw, qd);                                                                         \
+        break;
+            EA_DENSE_Q(4) EA_DENSE_Q(8) EA_DENSE_Q(12) EA_DENSE_Q(16) EA_DENSE_Q(20) EA_DENSE_Q(24) EA_DENSE_Q(28)
+            EA_DENSE_Q(32)
+#undef EA_DENSE_Q
+        default: st = fail(EA_ERR_STATE, "unsupported word width %d", s->lay.W);
+        }
+        if (st == EA_OK) {
+            const dim3 grid((unsigned)((L + ea::kShellRx - 1) / ea::kShellRx), (unsigned)(L * L));
+            if (nw == 1)
+                hipLaunchKernelGGL((ea::c4_shell_kernel<1>), grid, dim3(256), 0, s->stream, qd, L, n_shells, shells);
+            else
+                hipLaunchKernelGGL((ea::c4_shell_kernel<2>), grid, dim3(256), 0, s->stream, qd, L, n_shells, shells);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) st = fail(EA_ERR_DEVICE, "shell kernels: %s", hipGetErrorString(e));
+        }
+    }
+    if (cur != s->device) {
+        const hipError_t e = hipSetDevice(cur);
+        if (st == EA_OK && e != hipSuccess) st = fail(EA_ERR_DEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+    }
+    return st;
+}
+
 ea_status ea_time(const ea_sim *s, uint64_t *t)
 {
     if (!s || !t) return fail(EA_ERR_ARG, "NULL argument");
