@@ -34,12 +34,16 @@ if ROOT not in sys.path:
 
 METRIC = "ps per spin flip (batched vs plain, 1 MI355X, bit-exact); HBM/VALU % of peak"
 
-# Integer-ALU roofline.  Peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz simple
-# 32-bit lane-ops per second.  Algorithmic work per attempted flip: a quarter
-# of a Philox4x32-10 block (10 rounds x (2 multiply-hi-lo + 2 three-way XOR)
-# = 40 lane-ops per 4 words) plus one compare of the word with the threshold.
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-ALG_OPS_PER_FLIP = 40 / 4 + 1
+# Integer-ALU roofline.  Peak: the chip's vector lane rate, 256 CUs x 4 SIMDs
+# x 32 lanes x 2.4 GHz = 78.6e12 lane-ops/s (the fp32 vector peak of
+# 157.3 TFLOP/s counts an FMA as two flops in one lane slot).  Algorithmic
+# work per attempted flip in those slots: a quarter of a Philox4x32-10 block
+# (10 rounds x (2 multiply-hi-lo + 2 three-way XOR) per 4 words), where a
+# 32x32->64-bit multiply-add takes two slots (the --alu-probe measures
+# v_mad_u64_u32 at half the rate of v_bitop3_b32), plus one compare of the
+# word with its threshold: 5 x 2 + 5 + 1 = 16.
+VALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
+ALG_OPS_PER_FLIP = 16.0
 
 # HBM bytes per launch of the batched kernel on this workload, measured with
 # rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by a device-to-device copy of
@@ -167,14 +171,14 @@ def bench_plain(ea, torch, job, steps: int, burst: int):
     tuned = ea.tune_plain(job.L)  # untimed: picks the bit packing of the plain form for this size
     sim = ea.Sim(job.L, job.p, job.T, seed=job.seed, sample=job.sample, n_slots=len(job.tw))
     stream = sim.stream
-    run_plain_job(sim, job)  # warm-up: builds the captured graph
+    run_plain_job(sim, job)  # warm-up
     torch.cuda.synchronize()
     w0 = time.perf_counter()
     for i in range(steps):
         run_plain_job(sim, job)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - w0) * 1e3 / steps
-    # a burst of half-step launches timed with events on the run's stream
+    # one slab launch of `burst` sweeps timed with events on the run's stream
     sim.reset(job.seed, job.sample)
     sim.sweep(64)
     b0 = torch.cuda.Event(enable_timing=True)
@@ -183,27 +187,30 @@ def bench_plain(ea, torch, job, steps: int, burst: int):
     sim.sweep(burst)
     b1.record(stream)
     torch.cuda.synchronize()
-    avg_launch_us = b0.elapsed_time(b1) * 1e3 / (2 * burst)
+    sweep_us = b0.elapsed_time(b1) * 1e3 / burst
+    plan = sim.slab_plan
     sim.close()
+    alu = ALG_OPS_PER_FLIP * 2 * job.L ** 3 / (sweep_us * 1e-6) / 1e12
     return {
         "workload": f"L={job.L} p={job.p} T={job.T}, 1 sample x 2 replicas, {job.n_sweeps} sweeps, "
-                    f"{len(job.meas_t)} measurements, tw={job.tw}; one launch per half-step",
+                    f"{len(job.meas_t)} measurements, tw={job.tw}; persistent slab launches between events",
         "words_per_row": tuned["words_per_row"],
+        "slab_plan": {"slabs_per_replica": plan[0], "ghost_planes": plan[1]},
         "ps_per_flip": round(ms * 1e-3 / job.flips * 1e12, 4),
         "ms_per_step": round(ms, 3),
         "steps": steps,
-        "half_step_avg_us": round(avg_launch_us, 3),
-        "half_step_alu_frac": round(ALG_OPS_PER_FLIP * job.L ** 3 / (avg_launch_us * 1e-6) / 1e12
-                                    / VALU_PEAK_TOPS, 5),
+        "sweep_avg_us": round(sweep_us, 3),
+        "ps_per_flip_sweeps": round(sweep_us * 1e-6 / (2 * job.L ** 3) * 1e12, 4),
+        "alu_frac": round(alu / VALU_PEAK_TOPS, 5),
     }
 
 
 def plain_rate(ea, torch, L: int, sweeps: int = 256) -> float:
     """ps per attempted flip of the plain form at size L (p = 0.5, T = 0.7),
-    a burst of captured sweeps timed with events on the run's stream."""
+    a burst of sweeps (one slab launch) timed with events on the run's stream."""
     ea.tune_plain(L)  # untimed: picks the bit packing of the plain form for this size
     sim = ea.Sim(L, 0.5, 0.7, seed=1)
-    sim.sweep(64)  # builds the captured graph
+    sim.sweep(64)  # warm-up
     b0 = torch.cuda.Event(enable_timing=True)
     b1 = torch.cuda.Event(enable_timing=True)
     b0.record(sim.stream)
@@ -225,15 +232,22 @@ def alu_probe():
     lib.ea_probe_alu.restype = ctypes.c_int
     lib.ea_probe_alu.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_double)]
-    out = {"peak_tops": round(VALU_PEAK_TOPS, 2), "blocks": 256 * 16, "threads_per_block": 256}
-    for kind, name, iters in ((0, "v_mad_u64_u32", 20000), (1, "v_bitop3_b32", 20000), (2, "philox4x32_10", 4000)):
-        ms, ops = ctypes.c_double(0.0), ctypes.c_double(0.0)
-        rc = lib.ea_probe_alu(kind, 256 * 16, iters, ctypes.byref(ms), ctypes.byref(ops))
-        if rc != 0:
-            raise RuntimeError(f"ea_probe_alu({name}) failed: {rc}")
-        tops = ops.value / (ms.value * 1e-3) / 1e12
-        out[name] = {"ms": round(ms.value, 3), "lane_ops": ops.value, "tops": round(tops, 3),
-                     "frac_of_peak": round(tops / VALU_PEAK_TOPS, 4)}
+    out = {"peak_tops": round(VALU_PEAK_TOPS, 2), "threads_per_block": 256,
+           "note": "blocks = 256 CUs x 16 (many waves per SIMD) or 256 CUs x 4 (four per SIMD, as the update "
+                   "kernels run); philox counts 40 lane-ops per block (the roofline's count, in which a "
+                   "multiply-add is one op)"}
+    probes = ((0, "v_mad_u64_u32", 20000), (1, "v_bitop3_b32", 20000), (3, "philox_1_chain", 4000),
+              (2, "philox_2_chains", 4000), (4, "philox_4_chains", 2000))
+    for blocks in (256 * 16, 256 * 4):
+        for kind, name, iters in probes:
+            ms, ops = ctypes.c_double(0.0), ctypes.c_double(0.0)
+            rc = lib.ea_probe_alu(kind, blocks, iters * 16 * 256 // blocks, ctypes.byref(ms), ctypes.byref(ops))
+            if rc != 0:
+                raise RuntimeError(f"ea_probe_alu({name}) failed: {rc}")
+            tops = ops.value / (ms.value * 1e-3) / 1e12
+            out[f"{name}@{blocks // 256}wg_per_cu"] = {"ms": round(ms.value, 3), "lane_ops": ops.value,
+                                                       "tops": round(tops, 3),
+                                                       "frac_of_peak": round(tops / VALU_PEAK_TOPS, 4)}
     return out
 
 
@@ -293,10 +307,13 @@ def bench_msc(ea, torch, job, burst: int):
     }
 
 
-def bench_crossover(ea, torch, jobs):
-    """The crossover runs (five L = 128 samples, one per p) with their own
-    schedules: grouped (shared launches between events) and one after the
-    other, wall clock with the measurements."""
+def bench_crossover(ea, torch, jobs, sample_sweeps: int, burst: int):
+    """The crossover runs (five L = 128 samples, one per p, 10^6 sweeps and 30
+    measurements each) with their own schedules, grouped: one slab launch for
+    all five between events (wall clock, measurements included).  Beside it a
+    burst of grouped sweeps timed with events (the kernel alone) and, for
+    context, the runs one after the other on a bounded sample of
+    `sample_sweeps` sweeps."""
     flips = sum(j.flips for j in jobs)
     ea.run_group(jobs[:1])  # warm-up: kernels and the plain packing
     torch.cuda.synchronize()
@@ -304,8 +321,24 @@ def bench_crossover(ea, torch, jobs):
     ea.run_group(jobs)
     torch.cuda.synchronize()
     grouped = time.perf_counter() - w0
+    sims = [ea.Sim(j.L, j.p, j.T, seed=j.seed, sample=j.sample) for j in jobs]
+    ea.sweep_group(sims, 64)
+    b0 = torch.cuda.Event(enable_timing=True)
+    b1 = torch.cuda.Event(enable_timing=True)
+    b0.record(sims[0].stream)
+    ea.sweep_group(sims, burst)
+    b1.record(sims[0].stream)
+    torch.cuda.synchronize()
+    sweep_us = b0.elapsed_time(b1) * 1e3 / burst
+    plan = sims[0].slab_plan
+    for s_ in sims:
+        s_.close()
+    flips_sweep = sum(2 * j.L ** 3 for j in jobs)
+    alu = ALG_OPS_PER_FLIP * flips_sweep / (sweep_us * 1e-6) / 1e12
+    from paper_1411_5512_amd import workloads as wl
+    small = wl.crossover_jobs(sample_sweeps)
     w0 = time.perf_counter()
-    for j in jobs:
+    for j in small:
         ea.run_group([j])
     torch.cuda.synchronize()
     separate = time.perf_counter() - w0
@@ -313,7 +346,13 @@ def bench_crossover(ea, torch, jobs):
         "workload": f"{len(jobs)} plain runs, L={jobs[0].L}, p in {[j.p for j in jobs]}, T={jobs[0].T}, "
                     f"{jobs[0].n_sweeps} sweeps, {len(jobs[0].meas_t)} measurements each",
         "ps_per_flip_grouped": round(grouped / flips * 1e12, 4),
-        "ps_per_flip_one_by_one": round(separate / flips * 1e12, 4),
+        "wall_s_grouped": round(grouped, 3),
+        "sweep_avg_us_grouped": round(sweep_us, 3),
+        "ps_per_flip_sweeps_grouped": round(sweep_us * 1e-6 / flips_sweep * 1e12, 4),
+        "alu_frac_grouped": round(alu / VALU_PEAK_TOPS, 5),
+        "slab_plan_alone": {"slabs_per_replica": plan[0], "ghost_planes": plan[1]},
+        "ps_per_flip_one_by_one": round(separate / sum(j.flips for j in small) * 1e12, 4),
+        "one_by_one_sample": f"the same five runs one after the other, {sample_sweeps} sweeps each",
     }
 
 
@@ -348,7 +387,12 @@ def bench_serving(ea, torch, wl, n_jobs: int, load: float, sweep_hi: int, ps_bat
     st = srv.stats()
     total = sum(j.flips for _, j in stream)
     srv.close()
+    full = n_jobs >= 2000 and sweep_hi >= 1_000_000
     return {
+        "config5": full,
+        "sample": ("the serving configuration as stated (2000 jobs, sweeps log-uniform in [1e3, 1e6])" if full else
+                   f"a bounded sample of the serving configuration: {n_jobs} of its 2000 jobs, sweeps "
+                   f"log-uniform in [1e3, {sweep_hi:.0e}] instead of [1e3, 1e6]"),
         "workload": f"{n_jobs} Poisson arrivals (mean gap {gap_s * 1e3:.2f} ms = load {load} of the capacity "
                     f"measured per form), L uniform in {{16,24,32,48,64,96,128}} (L > 64 streamed from HBM "
                     f"beside the batched launch), p~U[0.1,0.5], T~U[0.5,1.2], sweeps log-uniform in "
@@ -391,8 +435,12 @@ def main():
     ap.add_argument("--msc-samples", type=int, default=64, help="samples of the multispin-coded batch")
     ap.add_argument("--msc-burst", type=int, default=1024, help="sweeps in its kernel-timing burst")
     ap.add_argument("--msc-only", action="store_true", help="run only the multispin-coded leg and print it")
-    ap.add_argument("--crossover-sweeps", type=int, default=10_000,
+    ap.add_argument("--crossover-only", action="store_true", help="run only the crossover leg and print it")
+    ap.add_argument("--plain-only", action="store_true", help="run only the mid-size plain leg and print it")
+    ap.add_argument("--crossover-sweeps", type=int, default=1_000_000,
                     help="sweeps of each crossover run in the grouped-plain leg (0 = skip)")
+    ap.add_argument("--crossover-sample-sweeps", type=int, default=10_000,
+                    help="sweeps of the bounded one-after-the-other sample beside it")
     ap.add_argument("--alu-probe", action="store_true",
                     help="only measure the lane rate of v_mad_u64_u32, v_bitop3_b32 and whole Philox4x32-10 "
                          "blocks against the integer-ALU peak (the roofline's op count) and exit")
@@ -426,6 +474,15 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": n, "read": n, "written": n}), flush=True)
+        return
+
+    if args.crossover_only:
+        print(json.dumps({"crossover": bench_crossover(ea, torch, wl.crossover_jobs(args.crossover_sweeps),
+                                                       args.crossover_sample_sweeps, args.burst)}), flush=True)
+        return
+    if args.plain_only:
+        print(json.dumps({"plain": bench_plain(ea, torch, wl.mid_job(args.sweeps), args.plain_steps, args.burst)}),
+              flush=True)
         return
 
     if args.msc_only:
@@ -513,7 +570,7 @@ def main():
             "kernel": "batch_kernel",
             "achieved": round(achieved, 3),
             "peak": round(VALU_PEAK_TOPS, 2),
-            "unit": "Tops/s (32-bit lane-ops)",
+            "unit": "Tops/s (32-bit lane-op slots)",
             "frac": round(achieved / VALU_PEAK_TOPS, 4),
             "traffic": traffic,
             "launch_ms": round(launch_s * 1e3, 3),
@@ -541,7 +598,8 @@ def main():
         out["msc"] = bench_msc(ea, torch, wl.msc_job(args.msc_sweeps, args.msc_samples), args.msc_burst)
     if args.crossover_sweeps:
         log("crossover runs, grouped ...")
-        out["crossover"] = bench_crossover(ea, torch, wl.crossover_jobs(args.crossover_sweeps))
+        out["crossover"] = bench_crossover(ea, torch, wl.crossover_jobs(args.crossover_sweeps),
+                                           args.crossover_sample_sweeps, args.burst)
     if not args.no_plain:
         log("plain form ...")
         plain = bench_plain(ea, torch, wl.mid_job(args.sweeps), args.plain_steps, args.burst)

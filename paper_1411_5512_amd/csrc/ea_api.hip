@@ -97,24 +97,25 @@ void read_plain_tune_file()
 // threads.
 bool slab_capable(int L, int rw) { return L * rw <= ea::kSlabThreads; }
 
-// Modelled time per sweep (us) of a plan, used to pick one: per half-step
-// the slab's planes times the cost of a packed word on one compute unit (at
-// least one word's dependent chain) plus a barrier, per cycle one exchange
-// (~1 us; with g = 1 the interior planes, updated after the boundary ones,
-// hide part of it).
+// Modelled time per sweep (us) of a plan, used to pick one, with constants
+// measured on MI355X: a packed word costs ~(13.2 W + 40) VALU
+// lane-instructions, ~370 words of 32 sites per us on one compute unit, and
+// no less than one word's chain of dependent instructions per half-step.
+// With g = 1 a half-step costs ~0.9 us of exchange and barrier beyond its
+// slab's words; a cycle of g >= 2 half-steps costs ~3 us
+// beyond its words (the ghost planes are read only after the neighbours'
+// whole cycle, with a barrier on either side).
 double slab_model_us(int L, int rw, int K, int g)
 {
     const int W = L / 2 / rw, PL = L * rw;
-    const double per_word = 13.2 * W + 40.0;        // VALU lane-instructions per packed word
-    const double rate = 64.0 * 2400.0 / per_word;   // words per us on one compute unit
-    const double chain = per_word * 4.0 / 2400.0;   // one word alone on its SIMD, us
-    const double exchange = 1.0, barrier = 0.1;
+    const double per_word = 13.2 * W + 40.0;
+    const double rate = 370.0 * (13.2 * 32 + 40.0) / per_word;  // words per us on one compute unit
+    const double chain = per_word * 4.0 / 2400.0;  // one word's dependent instructions alone on a SIMD, us
     const int s = (L + K - 1) / K;
-    double cycle = 0.0;
-    for (int k = 1; k <= g; ++k) cycle += std::max(chain, (double)(s + 2 * g - 2 * k) * PL / rate) + barrier;
-    double exposed = exchange;
-    if (g == 1 && s > 2) exposed = std::max(0.2, exchange - (double)(s - 2) * PL / rate);
-    return 2.0 * (cycle + exposed) / g;
+    if (g == 1) return 2.0 * (0.9 + std::max(chain, (double)s * PL / rate));
+    double cycle = 3.0;
+    for (int k = 1; k <= g; ++k) cycle += std::max(chain, (double)(s + 2 * g - 2 * k) * PL / rate);
+    return 2.0 * cycle / g;
 }
 
 // Modelled time per sweep of the best plan for one run of side L in packing
@@ -128,7 +129,8 @@ double slab_best_model_us(int L, int rw)
     for (int K = 1; K <= L && 2 * K <= 256; ++K)
         for (int g = 1; g <= 4; ++g) {
             const int emax = (L + K - 1) / K + 2 * g;
-            if (4 * (8 * (size_t)emax * (size_t)(L * rw) + 16) > 160 * 1024) continue;
+            if (4 * (8 * (size_t)emax * (size_t)(L * rw) + 16) > 160 * 1024 - 4 * (size_t)ea::kSelectTableWords)
+                continue;
             const double c = slab_model_us(L, rw, K, g);
             if (best < 0.0 || c < best) best = c;
         }
@@ -136,8 +138,10 @@ double slab_best_model_us(int L, int rw)
 }
 
 // Default packing: for lattices that run as slabs the packing whose best
-// slab plan the model rates fastest; otherwise the coarsest packing refined
-// until one half-step launch has at least kPlainMinThreads threads.
+// slab plan the model rates fastest, a finer one only if it is rated 5%
+// faster than a coarser one (grouped runs, whose slabs are thicker, do best
+// with the coarsest); otherwise the coarsest packing refined until one
+// half-step launch has at least kPlainMinThreads threads.
 int plain_default_rw(int L)
 {
     const int R = L / 2;
@@ -146,7 +150,7 @@ int plain_default_rw(int L)
     for (int d = 1; d <= R / 4; ++d) {
         if (!rw_valid(R, d)) continue;
         const double c = slab_best_model_us(L, d);
-        if (c >= 0.0 && (best_rw == 0 || c < best)) {
+        if (c >= 0.0 && (best_rw == 0 || c < 0.95 * best)) {
             best = c;
             best_rw = d;
         }
@@ -375,31 +379,40 @@ std::mutex g_slab_mu;
 int g_slab_cus = 0, g_slab_lds_limit = 0;
 bool g_slab_attr[33] = {};
 
-// Compute units and the LDS a workgroup may use (queried once), and the
-// kernel attribute that lets the instantiation for width W use all of it.
+template <bool SCREEN>
+const void *slab_kernel_fn(int W)
+{
+    switch (W) {
+    case 4: return (const void *)ea::slab_sweep_kernel<4, SCREEN>;
+    case 8: return (const void *)ea::slab_sweep_kernel<8, SCREEN>;
+    case 12: return (const void *)ea::slab_sweep_kernel<12, SCREEN>;
+    case 16: return (const void *)ea::slab_sweep_kernel<16, SCREEN>;
+    case 20: return (const void *)ea::slab_sweep_kernel<20, SCREEN>;
+    case 24: return (const void *)ea::slab_sweep_kernel<24, SCREEN>;
+    case 28: return (const void *)ea::slab_sweep_kernel<28, SCREEN>;
+    default: return (const void *)ea::slab_sweep_kernel<32, SCREEN>;
+    }
+}
+
+// Compute units and the dynamic LDS a slab workgroup may use beside the
+// static select tables (queried once), and the kernel attribute that lets
+// the instantiations for width W use all of it.
 ea_status slab_device(int W, int *n_cu, int *lds_limit)
 {
     std::lock_guard<std::mutex> lk(g_slab_mu);
     if (!g_slab_cus) {
-        int dev = 0;
+        int dev = 0, per_block = 0;
         EA_HIP(hipGetDevice(&dev));
         EA_HIP(hipDeviceGetAttribute(&g_slab_cus, hipDeviceAttributeMultiprocessorCount, dev));
-        EA_HIP(hipDeviceGetAttribute(&g_slab_lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        EA_HIP(hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        g_slab_lds_limit = per_block - 4 * ea::kSelectTableWords;
     }
     if (W < 4 || W > 32 || W % 4) return fail(EA_ERR_STATE, "unsupported word width %d", W);
     if (!g_slab_attr[W]) {
-        const void *fn = nullptr;
-        switch (W) {
-        case 4: fn = (const void *)ea::slab_sweep_kernel<4>; break;
-        case 8: fn = (const void *)ea::slab_sweep_kernel<8>; break;
-        case 12: fn = (const void *)ea::slab_sweep_kernel<12>; break;
-        case 16: fn = (const void *)ea::slab_sweep_kernel<16>; break;
-        case 20: fn = (const void *)ea::slab_sweep_kernel<20>; break;
-        case 24: fn = (const void *)ea::slab_sweep_kernel<24>; break;
-        case 28: fn = (const void *)ea::slab_sweep_kernel<28>; break;
-        default: fn = (const void *)ea::slab_sweep_kernel<32>; break;
-        }
-        EA_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, g_slab_lds_limit));
+        EA_HIP(hipFuncSetAttribute(slab_kernel_fn<false>(W), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   g_slab_lds_limit));
+        EA_HIP(hipFuncSetAttribute(slab_kernel_fn<true>(W), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   g_slab_lds_limit));
         g_slab_attr[W] = true;
     }
     *n_cu = g_slab_cus;
@@ -511,8 +524,14 @@ ea_status launch_slab(ea_sim *const *runs, int n, uint64_t sweeps, const SlabPla
             m->xserial += n_cycles + 1;
         }
         const dim3 grid((unsigned)(2 * n * plan.K));
-        EA_DISPATCH_W(y.W, hipLaunchKernelGGL((ea::slab_sweep_kernel<WW>), grid, dim3(ea::kSlabThreads), plan.lds,
-                                              lead->stream, a));
+        // the screen pays where every slab gives each SIMD four waves of work
+        if ((long)(y.L / plan.K) * y.L * y.RW >= ea::kSlabThreads) {
+            EA_DISPATCH_W(y.W, hipLaunchKernelGGL((ea::slab_sweep_kernel<WW, true>), grid, dim3(ea::kSlabThreads),
+                                                  plan.lds, lead->stream, a));
+        } else {
+            EA_DISPATCH_W(y.W, hipLaunchKernelGGL((ea::slab_sweep_kernel<WW, false>), grid, dim3(ea::kSlabThreads),
+                                                  plan.lds, lead->stream, a));
+        }
         EA_HIP(hipGetLastError());
         done += chunk;
     }

@@ -66,36 +66,43 @@ __global__ __launch_bounds__(256) void bitop3_probe(uint32_t iters, uint32_t see
     sink[blockIdx.x * blockDim.x + threadIdx.x] = acc;
 }
 
-// Whole Philox4x32-10 blocks, two interleaved per thread, counter varied per
-// iteration: 40 lane-ops per block by the roofline's count.
+// Whole Philox4x32-10 blocks, NB interleaved per thread (independent
+// dependency chains side by side), counter varied per iteration: 40 lane-ops
+// per block by the roofline's count.  Counter words 0 and 2 and the key are
+// uniform across the wavefront, as in the update.
+template <int NB>
 __global__ __launch_bounds__(256) void philox_probe(uint32_t iters, uint32_t seed, uint32_t *sink)
 {
     uint32_t acc = 0;
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     for (uint32_t i = 0; i < iters; ++i) {
-        uint32_t a0 = i, a1 = tid, a2 = 0x100u, a3 = seed;
-        uint32_t b0 = i, b1 = tid ^ 0x80000000u, b2 = 0x100u, b3 = seed;
+        uint32_t x0[NB], x1[NB], x2[NB], x3[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            x0[b] = i;
+            x1[b] = tid * NB + (uint32_t)b;
+            x2[b] = 0x100u;
+            x3[b] = seed;
+        }
         uint32_t k0 = seed, k1 = ~seed;
 #pragma unroll
         for (int r = 0; r < 10; ++r) {
-            const uint64_t ma0 = (uint64_t)a0 * 0xD2511F53u, mb0 = (uint64_t)b0 * 0xD2511F53u;
-            const uint64_t ma2 = (uint64_t)a2 * 0xCD9E8D57u, mb2 = (uint64_t)b2 * 0xCD9E8D57u;
-            const uint32_t ya0 = __builtin_amdgcn_bitop3_b32((uint32_t)(ma2 >> 32), a1, k0, 0x96);
-            const uint32_t yb0 = __builtin_amdgcn_bitop3_b32((uint32_t)(mb2 >> 32), b1, k0, 0x96);
-            const uint32_t ya2 = __builtin_amdgcn_bitop3_b32((uint32_t)(ma0 >> 32), a3, k1, 0x96);
-            const uint32_t yb2 = __builtin_amdgcn_bitop3_b32((uint32_t)(mb0 >> 32), b3, k1, 0x96);
-            a1 = (uint32_t)ma2;
-            b1 = (uint32_t)mb2;
-            a3 = (uint32_t)ma0;
-            b3 = (uint32_t)mb0;
-            a0 = ya0;
-            b0 = yb0;
-            a2 = ya2;
-            b2 = yb2;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const uint64_t m0 = (uint64_t)x0[b] * 0xD2511F53u;
+                const uint64_t m2 = (uint64_t)x2[b] * 0xCD9E8D57u;
+                const uint32_t y0 = __builtin_amdgcn_bitop3_b32((uint32_t)(m2 >> 32), x1[b], k0, 0x96);
+                const uint32_t y2 = __builtin_amdgcn_bitop3_b32((uint32_t)(m0 >> 32), x3[b], k1, 0x96);
+                x1[b] = (uint32_t)m2;
+                x3[b] = (uint32_t)m0;
+                x0[b] = y0;
+                x2[b] = y2;
+            }
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
         }
-        acc ^= a0 ^ a1 ^ a2 ^ a3 ^ b0 ^ b1 ^ b2 ^ b3;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc ^= x0[b] ^ x1[b] ^ x2[b] ^ x3[b];
     }
     sink[tid] = acc;
 }
@@ -105,13 +112,13 @@ __global__ __launch_bounds__(256) void philox_probe(uint32_t iters, uint32_t see
 extern "C" {
 
 // Run probe `kind` (0: v_mad_u64_u32, 1: v_bitop3_b32, 2: Philox4x32-10
-// blocks) on `blocks` workgroups of 256 threads for `iters`
-// iterations; *ms receives the event-timed duration of the timed launch
+// blocks two at a time, 3: one at a time, 4: four at a time) on `blocks`
+// workgroups of 256 threads for `iters` iterations; *ms receives the event-timed duration of the timed launch
 // (after one untimed warm-up launch) and *ops the lane-operations it counts
 // (instructions x lanes; 40 per Philox block).  Returns 0, or the HIP error.
 int ea_probe_alu(int kind, int blocks, unsigned iters, double *ms, double *ops)
 {
-    if (kind < 0 || kind > 2 || blocks < 1 || !ms || !ops) return -1;
+    if (kind < 0 || kind > 4 || blocks < 1 || !ms || !ops) return -1;
     uint32_t *sink = nullptr;
     hipError_t e = hipMalloc((void **)&sink, (size_t)blocks * 256 * 4);
     if (e != hipSuccess) return (int)e;
@@ -130,9 +137,17 @@ int ea_probe_alu(int kind, int blocks, unsigned iters, double *ms, double *ops)
             hipLaunchKernelGGL(bitop3_probe, dim3(blocks), dim3(256), 0, 0, iters, 12345u, sink);
             per_iter = kChains * kSteps;
             break;
-        default:
-            hipLaunchKernelGGL(philox_probe, dim3(blocks), dim3(256), 0, 0, iters, 12345u, sink);
+        case 2:
+            hipLaunchKernelGGL(philox_probe<2>, dim3(blocks), dim3(256), 0, 0, iters, 12345u, sink);
             per_iter = 2 * 40;
+            break;
+        case 3:
+            hipLaunchKernelGGL(philox_probe<1>, dim3(blocks), dim3(256), 0, 0, iters, 12345u, sink);
+            per_iter = 40;
+            break;
+        default:
+            hipLaunchKernelGGL(philox_probe<4>, dim3(blocks), dim3(256), 0, 0, iters, 12345u, sink);
+            per_iter = 4 * 40;
             break;
         }
         (void)hipEventRecord(b, 0);

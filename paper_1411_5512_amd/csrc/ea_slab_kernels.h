@@ -80,7 +80,170 @@ __device__ __forceinline__ int slab_item_plane(int j, int s, int g, int k)
     return j < lo ? k + j : g + s + (j - lo);
 }
 
+// Acceptance bits of a word's W sites from their random words u and their
+// thresholds thr (bit i set iff u[i] < thr[i]), built from the top block
+// down as in accept_words.
+template <int J, int W>
+__device__ __forceinline__ uint32_t below_each(uint32_t accept, const uint32_t (&u)[W], const uint32_t (&thr)[W])
+{
+    accept = append_below4(accept, u[4 * J + 3], thr[4 * J + 3], u[4 * J + 2], thr[4 * J + 2], u[4 * J + 1],
+                           thr[4 * J + 1], u[4 * J], thr[4 * J]);
+    if constexpr (J > 0)
+        return below_each<J - 1, W>(accept, u, thr);
+    else
+        return accept;
+}
+
+// The general acceptance of a word with thresholds from the LDS select
+// tables (fill_select_tables): four sites per 16-byte read, as in
+// flip_mask_lds, but with the random words already drawn.
 template <int W>
+__device__ __forceinline__ uint32_t accept_words_tab(const Decision &d, const uint32_t (&u)[W], const uint32_t *tab)
+{
+    const uint32_t *spread_any = tab + kSelectQuadWords;
+    const uint32_t *spread_odd = tab + kSelectQuadWords + 256;
+    uint32_t thr[W];
+#pragma unroll
+    for (int j = 0; j < (W + 7) / 8; ++j) {
+        const uint32_t off = spread_any[__builtin_amdgcn_ubfe(d.any, 8 * j, 8)] |
+                             spread_odd[__builtin_amdgcn_ubfe(d.odd, 8 * j, 8)];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int gq = 2 * j + h;  // 4-site block
+            if (gq < W / 4) {
+                const uint32_t byte_off = h ? off >> 16 : off & 0xffffu;
+                const uint4 q4 = *(const uint4 *)((const char *)tab + byte_off);
+                thr[4 * gq + 0] = q4.x;
+                thr[4 * gq + 1] = q4.y;
+                thr[4 * gq + 2] = q4.z;
+                thr[4 * gq + 3] = q4.w;
+            }
+        }
+    }
+    return below_each<W / 4 - 1, W>(0u, u, thr);
+}
+
+// accept_screened with the general case through the tables: where uphill
+// moves of dE >= 8 are rare, a word none of whose random words falls below
+// thr2 accepts exactly its n = 2 sites whose word is below thr1; other words
+// take the table select, so the decisions are the same either way.
+template <int W, bool SCREEN>
+__device__ __forceinline__ uint32_t accept_slab(const Decision &d, const uint32_t (&u)[W], uint32_t thr1,
+                                                uint32_t thr2, uint32_t thr3, const uint32_t *tab)
+{
+    if constexpr (SCREEN) {
+        const bool rare = (uint64_t)thr2 * (uint64_t)W < (1ull << 24) && thr3 <= thr2;  // uniform
+        if (rare) {
+            const uint32_t a1 = below_words<W / 4 - 1, W>(0u, u, thr1);
+            uint32_t v[W];
+#pragma unroll
+            for (int i = 0; i < W; ++i) v[i] = u[i];
+#pragma unroll
+            for (int n = W; n > 1; n = (n + 2) / 3) {
+#pragma unroll
+                for (int i = 0; 3 * i < n; ++i) {
+                    uint32_t m = v[3 * i];
+                    if (3 * i + 1 < n) m = min(m, v[3 * i + 1]);
+                    if (3 * i + 2 < n) m = min(m, v[3 * i + 2]);
+                    v[i] = m;
+                }
+            }
+            if (v[0] >= thr2) return a1 & d.any & ~d.always;
+        }
+    }
+    return accept_words_tab<W>(d, u, tab);
+}
+
+// The LDS planes a half-step of colour c reads and writes.
+struct SlabPlanes {
+    uint32_t *own;
+    const uint32_t *oth, *bx_own, *by_own, *bz_own, *bx_oth, *by_oth, *bz_oth;
+};
+
+__device__ __forceinline__ SlabPlanes slab_planes(uint32_t *lspin, const uint32_t *lbond, int stride, int c)
+{
+    SlabPlanes P;
+    P.own = lspin + c * stride;
+    P.oth = lspin + (c ^ 1) * stride;
+    P.bx_own = lbond + (0 + c) * stride;
+    P.by_own = lbond + (2 + c) * stride;
+    P.bz_own = lbond + (4 + c) * stride;
+    P.bx_oth = lbond + (1 - c) * stride;
+    P.by_oth = lbond + (3 - c) * stride;
+    P.bz_oth = lbond + (5 - c) * stride;
+    return P;
+}
+
+// One packed word's update (eq. 9): its own word and the fifteen words
+// around it, the W random words, and the flip decision.  Zm and Zp (the z
+// neighbours of the other colour) may be replaced before update() by words
+// that come from a neighbouring slab.
+template <int W>
+struct SlabWord {
+    uint32_t S, O, Om, Op, Xo, Xom, Bx, By, Bz, Yp, Ym, Bym, Zp, Zm, Bzm;
+    uint32_t u[W];
+
+    __device__ __forceinline__ void load(const SlabPlanes &P, int base, int q, int qm, int qp, int qym, int qyp,
+                                         int PL)
+    {
+        S = P.own[base + q];
+        O = P.oth[base + q];
+        Om = P.oth[base + qm];
+        Op = P.oth[base + qp];
+        Xo = P.bx_oth[base + q];
+        Xom = P.bx_oth[base + qm];
+        Bx = P.bx_own[base + q];
+        By = P.by_own[base + q];
+        Bz = P.bz_own[base + q];
+        Yp = P.oth[base + qyp];
+        Ym = P.oth[base + qym];
+        Bym = P.by_oth[base + qym];
+        Zp = P.oth[base + PL + q];
+        Zm = P.oth[base - PL + q];
+        Bzm = P.bz_oth[base - PL + q];
+    }
+
+    __device__ __forceinline__ void draw(uint32_t t, uint32_t quad0, uint32_t c2, uint32_t sample, uint32_t k0,
+                                         uint32_t k1)
+    {
+        random_words<W / 4 - 1, W>(t, quad0, c2, sample, k0, k1, u);
+    }
+
+    // par: the row's x parity (x = 2 xh + par)
+    template <bool SCREEN>
+    __device__ __forceinline__ uint32_t update(int par, uint32_t thr1, uint32_t thr2, uint32_t thr3,
+                                               const uint32_t *tab) const
+    {
+        const uint32_t pm = 0u - (uint32_t)par;
+        const uint32_t xp = __builtin_amdgcn_bitop3_b32(pm, take_plus1<W>(O, Op), O, kBitopSelect);
+        const uint32_t xm = __builtin_amdgcn_bitop3_b32(pm, O ^ Xo, take_minus1<W>(O ^ Xo, Om ^ Xom), kBitopSelect);
+        const Decision d = classify(S ^ xp ^ Bx, S ^ xm, xor3(S, Yp, By), xor3(S, Ym, Bym), xor3(S, Zp, Bz),
+                                    xor3(S, Zm, Bzm));
+        return S ^ (d.always | accept_slab<W, SCREEN>(d, u, thr1, thr2, thr3, tab));
+    }
+};
+
+// Wait until the entry at p carries `epoch` (it did not on a first look);
+// false if the error word is set or the wait times out.
+__device__ __forceinline__ bool slab_poll(const unsigned long long *p, uint32_t epoch, uint32_t *err,
+                                          unsigned long long &v)
+{
+    const unsigned long long start = __builtin_amdgcn_s_memrealtime();
+    for (;;) {
+        __builtin_amdgcn_s_sleep(1);
+        v = __hip_atomic_load(const_cast<unsigned long long *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((uint32_t)(v >> 32) == epoch) return true;
+        if (slab_err_seen(err) || __builtin_amdgcn_s_memrealtime() - start > kSlabSpinTicks) return false;
+    }
+}
+
+__shared__ __align__(16) uint32_t slab_select_tables[kSelectTableWords];
+
+// SCREEN: launches whose slabs give every SIMD four or more waves of work
+// per half-step screen the rare uphill moves (accept_slab); smaller ones are
+// bound by one wave's chain of dependent instructions, which the screen
+// lengthens.
+template <int W, bool SCREEN>
 __global__ __launch_bounds__(kSlabThreads) void slab_sweep_kernel(SlabLaunch a)
 {
     const int K = a.K, L = a.L, RW = a.RW, PL = L * RW, R = L / 2;
@@ -112,6 +275,7 @@ __global__ __launch_bounds__(kSlabThreads) void slab_sweep_kernel(SlabLaunch a)
     }
     __syncthreads();
     if (flag[0]) return;
+    const uint32_t *tab = slab_select_tables;
 
     // the extended region from the state in HBM (the launch boundary makes it whole)
     const size_t plane = (size_t)L * L * RW;
@@ -125,115 +289,154 @@ __global__ __launch_bounds__(kSlabThreads) void slab_sweep_kernel(SlabLaunch a)
 #pragma unroll
         for (int dc = 0; dc < 6; ++dc) lbond[(dc * EM + e) * PL + c0] = run.bonds[(size_t)dc * plane + src];
     }
+    fill_select_tables(slab_select_tables, run.thr1, run.thr2, run.thr3, tid, kSlabThreads);
     __syncthreads();
 
     const uint32_t n_half = a.n_half;
-    const uint32_t n_cycles = (n_half + (uint32_t)g - 1) / (uint32_t)g;
     const size_t xrep = (size_t)kSlabSlots * 2 * (size_t)L * PL;  // entries per replica
     unsigned long long *xb = run.xbuf + (size_t)r * xrep;
-    uint32_t j_half = 0;
-    for (uint32_t m = 0; m < n_cycles; ++m) {
-        const int G = (int)min((uint32_t)g, n_half - m * (uint32_t)g);
-        const uint32_t epoch = run.serial + m + 1u;
-        const int slot = (int)(m % (uint32_t)kSlabSlots);
-        for (int k = 1; k <= G; ++k, ++j_half) {
-            const uint32_t t = run.t0 + (j_half >> 1);
-            const int c = r ^ (int)(j_half & 1u);
-            const bool publish = k >= G - 1;  // the colour's last update in this cycle
+
+    if (g == 1) {
+        // One half-step per exchange.  A boundary word's only neighbour outside
+        // the slab is its z neighbour in the ghost plane, same column, of the
+        // colour the neighbouring slab updated in the previous half-step: the
+        // thread that updates the word loads that entry itself before its
+        // random words and checks the epoch after them, so no ghost pass and
+        // no extra barrier are needed, and the interior planes overlap the
+        // exchange.  Ghost planes in LDS are read only in the first half-step.
+        // (Measured: a look after the random words instead, or a second look
+        // there, is 5-10% slower at L = 64.)
+        const int zlo = wrap(z0 - 1, L), zhi = wrap(z0 + s, L);
+        for (uint32_t j = 0; j < n_half; ++j) {
+            const uint32_t t = run.t0 + (j >> 1);
+            const int c = r ^ (int)(j & 1u);
+            const uint32_t ep_prev = run.serial + j, ep_now = run.serial + j + 1u;
+            const int slot_now = (int)(j % (uint32_t)kSlabSlots);
+            const int slot_prev = (int)((j + (uint32_t)kSlabSlots - 1u) % (uint32_t)kSlabSlots);
+            unsigned long long *gl = xb + (((size_t)slot_prev * 2 + (c ^ 1)) * L + zlo) * PL + q;
+            unsigned long long *gu = xb + (((size_t)slot_prev * 2 + (c ^ 1)) * L + zhi) * PL + q;
+            unsigned long long *pub = xb + ((size_t)slot_now * 2 + c) * (size_t)L * PL + q;
+            const SlabPlanes P = slab_planes(lspin, lbond, EM * PL, c);
             const uint32_t c2 = counter_word2(TAG_METRO, (uint32_t)c, (uint32_t)r);
-            uint32_t *own = lspin + c * EM * PL;
-            const uint32_t *oth = lspin + (c ^ 1) * EM * PL;
-            const uint32_t *bx_own = lbond + (0 + c) * EM * PL, *by_own = lbond + (2 + c) * EM * PL,
-                           *bz_own = lbond + (4 + c) * EM * PL;
-            const uint32_t *bx_oth = lbond + (1 - c) * EM * PL, *by_oth = lbond + (3 - c) * EM * PL,
-                           *bz_oth = lbond + (5 - c) * EM * PL;
-            const int n_items = E - 2 * k;
             if (worker) {
-                for (int it = zoff; it < n_items; it += zstep) {
-                    const int e = slab_item_plane(it, s, g, k);
-                    const int zg = wrap(zb + e, L);
-                    const int par = (y + zg + c) & 1;
-                    const int base = e * PL;
-                    const uint32_t S = own[base + q];
-                    const uint32_t O = oth[base + q], Om = oth[base + qm], Op = oth[base + qp];
-                    const uint32_t Xo = bx_oth[base + q], Xom = bx_oth[base + qm];
-                    const uint32_t Bx = bx_own[base + q], By = by_own[base + q], Bz = bz_own[base + q];
-                    const uint32_t Yp = oth[base + qyp], Ym = oth[base + qym], Bym = by_oth[base + qym];
-                    const uint32_t Zp = oth[base + PL + q], Zm = oth[base - PL + q], Bzm = bz_oth[base - PL + q];
-                    const uint32_t quad0 = (uint32_t)(((y + L * zg) * R + w * W) >> 2);
-                    uint32_t uw[W];
-                    random_words<W / 4 - 1, W>(t, quad0, c2, run.sample, run.k0, run.k1, uw);
-                    const uint32_t pm = 0u - (uint32_t)par;
-                    const uint32_t xp = __builtin_amdgcn_bitop3_b32(pm, take_plus1<W>(O, Op), O, kBitopSelect);
-                    const uint32_t xm =
-                        __builtin_amdgcn_bitop3_b32(pm, O ^ Xo, take_minus1<W>(O ^ Xo, Om ^ Xom), kBitopSelect);
-                    const Decision d = classify(S ^ xp ^ Bx, S ^ xm, xor3(S, Yp, By), xor3(S, Ym, Bym),
-                                                xor3(S, Zp, Bz), xor3(S, Zm, Bzm));
-                    const uint32_t v = S ^ (d.always | accept_words<W / 4 - 1, W>(0u, d, uw, run.thr1, run.thr2,
-                                                                                    run.thr3));
-                    own[base + q] = v;
-                    // owned planes within g of a face are read by the neighbours
-                    if (publish && it < s && (e - g < g || g + s - 1 - e < g))
-                        __hip_atomic_store(xb + (((size_t)slot * 2 + c) * L + zg) * PL + q,
-                                           ((unsigned long long)epoch << 32) | v, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
+                for (int it = zoff; it < s; it += zstep) {
+                    const int e = 1 + ((it & 1) ? s - 1 - (it >> 1) : (it >> 1));
+                    const bool lo = e == 1, hi = e == s;
+                    const bool need_lo = lo && j > 0, need_hi = hi && j > 0;
+                    const int zg = z0 + e - 1;
+                    // the ghost words are loaded first, so that their latency
+                    // overlaps the LDS loads and the random words
+                    unsigned long long vl = 0, vu = 0;
+                    if (need_lo) vl = __hip_atomic_load(gl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (need_hi) vu = __hip_atomic_load(gu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    SlabWord<W> sw;
+                    sw.load(P, e * PL, q, qm, qp, qym, qyp, PL);
+                    __builtin_amdgcn_sched_barrier(0);
+                    sw.draw(t, (uint32_t)(((y + L * zg) * R + w * W) >> 2), c2, run.sample, run.k0, run.k1);
+                    if (need_lo && (uint32_t)(vl >> 32) != ep_prev && !slab_poll(gl, ep_prev, a.err, vl)) flag[1] = 1;
+                    if (need_hi && (uint32_t)(vu >> 32) != ep_prev && !slab_poll(gu, ep_prev, a.err, vu)) flag[1] = 1;
+                    if (need_lo) sw.Zm = (uint32_t)vl;
+                    if (need_hi) sw.Zp = (uint32_t)vu;
+                    const uint32_t v = sw.template update<SCREEN>((y + zg + c) & 1, run.thr1, run.thr2, run.thr3, tab);
+                    P.own[e * PL + q] = v;
+                    if (lo || hi)
+                        __hip_atomic_store(pub + (size_t)zg * PL, ((unsigned long long)ep_now << 32) | v,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
             __syncthreads();
-        }
-        if (m + 1 == n_cycles) break;
-
-        // the ghost planes of the next cycle from the owners' publications:
-        // both colours, or with g = 1 only the one just updated
-        const int nc = g == 1 ? 1 : 2;
-        const int c_last = r ^ (int)((j_half - 1) & 1u);
-        const int n_ent = 2 * g * nc * PL;
-        int bad = 0;
-        for (int i0 = tid; i0 < n_ent; i0 += 4 * kSlabThreads) {
-            unsigned long long v[4];
-            size_t src[4];
-            int dst[4];
-#pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                const int i = i0 + h * kSlabThreads;
-                if (i < n_ent) {
-                    const int col = i % PL, rest = i / PL;
-                    const int cc = nc == 1 ? c_last : (rest & 1);
-                    const int gp = rest / nc;  // ghost plane 0 .. 2g-1
-                    const int e = gp < g ? gp : s + gp;
-                    const int zg = wrap(zb + e, L);
-                    src[h] = (((size_t)slot * 2 + cc) * L + zg) * PL + col;
-                    dst[h] = (cc * EM + e) * PL + col;
-                    v[h] = __hip_atomic_load(xb + src[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
+            if (flag[1]) {
+                if (tid == 0) __hip_atomic_store(a.err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return;  // after an error the run's state is undefined
             }
-#pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                const int i = i0 + h * kSlabThreads;
-                if (i >= n_ent) continue;
-                if ((uint32_t)(v[h] >> 32) != epoch) {
-                    const unsigned long long start = __builtin_amdgcn_s_memrealtime();
-                    for (;;) {
-                        __builtin_amdgcn_s_sleep(1);
-                        v[h] = __hip_atomic_load(xb + src[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        if ((uint32_t)(v[h] >> 32) == epoch) break;
-                        if (slab_err_seen(a.err) || __builtin_amdgcn_s_memrealtime() - start > kSlabSpinTicks) {
-                            bad = 1;
-                            break;
-                        }
+        }
+    } else {
+        // g half-steps per exchange on the shrinking extended region, then
+        // the 2g ghost planes (both colours) from the owners' publications.
+        const uint32_t n_cycles = (n_half + (uint32_t)g - 1) / (uint32_t)g;
+        uint32_t j_half = 0;
+        for (uint32_t m = 0; m < n_cycles; ++m) {
+            const int G = (int)min((uint32_t)g, n_half - m * (uint32_t)g);
+            const uint32_t epoch = run.serial + m + 1u;
+            const int slot = (int)(m % (uint32_t)kSlabSlots);
+            for (int k = 1; k <= G; ++k, ++j_half) {
+                const uint32_t t = run.t0 + (j_half >> 1);
+                const int c = r ^ (int)(j_half & 1u);
+                const bool publish = k >= G - 1;  // the colour's last update in this cycle
+                const uint32_t c2 = counter_word2(TAG_METRO, (uint32_t)c, (uint32_t)r);
+                const SlabPlanes P = slab_planes(lspin, lbond, EM * PL, c);
+                const int n_items = E - 2 * k;
+                if (worker) {
+                    for (int it = zoff; it < n_items; it += zstep) {
+                        const int e = slab_item_plane(it, s, g, k);
+                        const int zg = wrap(zb + e, L);
+                        SlabWord<W> sw;
+                        sw.load(P, e * PL, q, qm, qp, qym, qyp, PL);
+                        sw.draw(t, (uint32_t)(((y + L * zg) * R + w * W) >> 2), c2, run.sample, run.k0, run.k1);
+                        const uint32_t v =
+                            sw.template update<SCREEN>((y + zg + c) & 1, run.thr1, run.thr2, run.thr3, tab);
+                        P.own[e * PL + q] = v;
+                        // owned planes within g of a face are read by the neighbours
+                        if (publish && it < s && (e - g < g || g + s - 1 - e < g))
+                            __hip_atomic_store(xb + (((size_t)slot * 2 + c) * L + zg) * PL + q,
+                                               ((unsigned long long)epoch << 32) | v, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
                     }
                 }
-                if (bad) break;
-                lspin[dst[h]] = (uint32_t)v[h];
+                __syncthreads();
             }
-            if (bad) break;
+            if (m + 1 == n_cycles) break;
+
+            // the ghost planes of the next cycle, both colours: each thread's
+            // entries, up to eight at a time, all re-read together until their
+            // epochs match
+            const int n_ent = 2 * g * 2 * PL;
+            bool ok = true;
+            for (int i0 = tid; ok && i0 < n_ent; i0 += 8 * kSlabThreads) {
+                unsigned long long *src[8];
+                int dst[8];
+                uint32_t pend = 0;
+#pragma unroll
+                for (int h = 0; h < 8; ++h) {
+                    const int i = i0 + h * kSlabThreads;
+                    src[h] = xb;
+                    dst[h] = 0;
+                    if (i < n_ent) {
+                        const int col = i % PL, rest = i / PL;
+                        const int cc = rest & 1, gp = rest >> 1;  // ghost plane 0 .. 2g-1
+                        const int e = gp < g ? gp : s + gp;
+                        src[h] = xb + (((size_t)slot * 2 + cc) * L + wrap(zb + e, L)) * PL + col;
+                        dst[h] = (cc * EM + e) * PL + col;
+                        pend |= 1u << h;
+                    }
+                }
+                const unsigned long long start = __builtin_amdgcn_s_memrealtime();
+                for (;;) {
+                    unsigned long long v[8];
+#pragma unroll
+                    for (int h = 0; h < 8; ++h)
+                        if ((pend >> h) & 1u) v[h] = __hip_atomic_load(src[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+                    for (int h = 0; h < 8; ++h)
+                        if (((pend >> h) & 1u) && (uint32_t)(v[h] >> 32) == epoch) {
+                            lspin[dst[h]] = (uint32_t)v[h];
+                            pend &= ~(1u << h);
+                        }
+                    if (!pend) break;
+                    if (slab_err_seen(a.err) || __builtin_amdgcn_s_memrealtime() - start > kSlabSpinTicks) {
+                        ok = false;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+            if (!ok) {
+                __hip_atomic_store(a.err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                flag[1] = 1;
+            }
+            __syncthreads();
+            if (flag[1]) return;  // after an error the run's state is undefined
         }
-        if (bad) {
-            __hip_atomic_store(a.err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            flag[1] = 1;
-        }
-        __syncthreads();
-        if (flag[1]) return;  // after an error the run's state is undefined
     }
 
     // the owned planes back to HBM

@@ -215,3 +215,19 @@ def test_slab_plan_errors(ea_gpu):
     with pytest.raises(ea_gpu.EAError):
         big.set_slab_plan(16, 1)
     big.close()
+
+
+@pytest.mark.parametrize("T", [0.6, 1.2])
+def test_screened_slabs_match_oracle(ea_gpu, oracle_mod, T):
+    """Slabs thick enough to give every SIMD four waves per half-step take
+    the screened instantiation (rare uphill moves ruled out per word); at
+    T = 0.6 the screen applies, at T = 1.2 moves with dE >= 8 are too
+    frequent and every word takes the table select."""
+    g = ea_gpu.Sim(64, 0.5, T, seed=13, sample=0, words_per_row=4)
+    g.set_slab_plan(4, 1)
+    o = oracle_mod.Sim(64, 0.5, T, seed=13, sample=0)
+    g.sweep(4)
+    o.sweep(4)
+    _compare_state(g, o, f"screened slabs T={T}")
+    _compare_obs(g.measure(), o.measure(), f"screened slabs T={T}")
+    g.close()
