@@ -205,23 +205,6 @@ def bench_plain(ea, torch, job, steps: int, burst: int):
     }
 
 
-def plain_rate(ea, torch, L: int, sweeps: int = 256) -> float:
-    """ps per attempted flip of the plain form at size L (p = 0.5, T = 0.7),
-    a burst of sweeps (one slab launch) timed with events on the run's stream."""
-    ea.tune_plain(L)  # untimed: picks the bit packing of the plain form for this size
-    sim = ea.Sim(L, 0.5, 0.7, seed=1)
-    sim.sweep(64)  # warm-up
-    b0 = torch.cuda.Event(enable_timing=True)
-    b1 = torch.cuda.Event(enable_timing=True)
-    b0.record(sim.stream)
-    sim.sweep(sweeps)
-    b1.record(sim.stream)
-    torch.cuda.synchronize()
-    ms = b0.elapsed_time(b1)
-    sim.close()
-    return ms * 1e-3 / (sweeps * 2 * L ** 3) * 1e12
-
-
 def alu_probe():
     """Sustained lane rate of the instructions the roofline counts as one
     lane-op each (libea_probe.so, event-timed launches of 4 waves per SIMD
@@ -359,34 +342,52 @@ def bench_crossover(ea, torch, jobs, sample_sweeps: int, burst: int):
 SERVE_SIZES = (16, 24, 32, 48, 64, 96, 128)
 
 
-def bench_serving(ea, torch, wl, n_jobs: int, load: float, sweep_hi: int, ps_batched: float):
-    """Poisson stream of jobs (L uniform over {16,...,128}, p ~ U[0.1,0.5],
-    T ~ U[0.5,1.2], sweeps log-uniform in [1e3, sweep_hi], log-spaced
-    schedules) offered at `load` times the capacity measured for each form
-    (batched rate for L <= 64, plain rate per size above); continuous
-    batching with admission by an HBM budget."""
-    stream = wl.serve_jobs(n_jobs=n_jobs, sweep_range=(1_000, sweep_hi), sizes=SERVE_SIZES)
-    rate = {L: ps_batched for L in SERVE_SIZES if L <= 64}
-    for L in SERVE_SIZES:
-        if L > 64:
-            rate[L] = plain_rate(ea, torch, L)
-    capacity_s = sum(j.flips * rate[j.L] for _, j in stream) * 1e-12
-    gap_s = capacity_s / len(stream) / load
-    budget = 1 << 30
+def _serve(ea, stream, gap_s: float, budget: int, what: str):
+    """Submit `stream` ((arrival in mean gaps, job) pairs) to a server at the
+    given mean gap and wait for every job; progress lines on stderr."""
     srv = ea.Server(hbm_budget=budget, max_resident=512)
     srv.start()
     t0 = time.perf_counter()
-    for arrival, job in stream:
+    last = t0
+    for i, (arrival, job) in enumerate(stream):
         delay = t0 + arrival * gap_s - time.perf_counter()
         if delay > 0:
             time.sleep(delay)
         srv.submit(job)
-    srv.drain(1200)
+        if time.perf_counter() - last > 20.0:
+            last = time.perf_counter()
+            log(f"{what}: {i + 1}/{len(stream)} submitted, {srv.stats()['completed']} done, "
+                f"{last - t0:.0f} s")
+    while True:
+        try:
+            srv.drain(20.0)
+            break
+        except ea.EAError as e:
+            if e.status != ea.abi.EA_ERR_BUSY or time.perf_counter() - t0 > 3600:
+                raise
+            log(f"{what}: {srv.stats()['completed']}/{len(stream)} done, {time.perf_counter() - t0:.0f} s")
     wall = time.perf_counter() - t0
     srv.stop()
     st = srv.stats()
-    total = sum(j.flips for _, j in stream)
     srv.close()
+    return st, wall
+
+
+def bench_serving(ea, torch, wl, n_jobs: int, load: float, sweep_hi: int, calib_jobs: int = 100):
+    """Poisson stream of jobs (L uniform over {16,...,128}, p ~ U[0.1,0.5],
+    T ~ U[0.5,1.2], sweeps log-uniform in [1e3, sweep_hi], log-spaced
+    schedules) offered at `load` times the serving form's own capacity,
+    measured first on a burst of `calib_jobs` jobs of the same distribution
+    (another seed) submitted at once; continuous batching with admission by
+    an HBM budget."""
+    budget = 1 << 30
+    calib = wl.serve_jobs(n_jobs=calib_jobs, gen_seed=6, sweep_range=(1_000, sweep_hi), sizes=SERVE_SIZES)
+    st, wall = _serve(ea, [(0.0, j) for _, j in calib], 0.0, budget, "serving capacity burst")
+    ps_capacity = wall / sum(j.flips for _, j in calib) * 1e12
+    stream = wl.serve_jobs(n_jobs=n_jobs, sweep_range=(1_000, sweep_hi), sizes=SERVE_SIZES)
+    total = sum(j.flips for _, j in stream)
+    gap_s = total * ps_capacity * 1e-12 / len(stream) / load
+    st, wall = _serve(ea, stream, gap_s, budget, f"serving at load {load}")
     full = n_jobs >= 2000 and sweep_hi >= 1_000_000
     return {
         "config5": full,
@@ -394,15 +395,17 @@ def bench_serving(ea, torch, wl, n_jobs: int, load: float, sweep_hi: int, ps_bat
                    f"a bounded sample of the serving configuration: {n_jobs} of its 2000 jobs, sweeps "
                    f"log-uniform in [1e3, {sweep_hi:.0e}] instead of [1e3, 1e6]"),
         "workload": f"{n_jobs} Poisson arrivals (mean gap {gap_s * 1e3:.2f} ms = load {load} of the capacity "
-                    f"measured per form), L uniform in {{16,24,32,48,64,96,128}} (L > 64 streamed from HBM "
-                    f"beside the batched launch), p~U[0.1,0.5], T~U[0.5,1.2], sweeps log-uniform in "
-                    f"[1e3,{sweep_hi:.0e}], 20 log-spaced measurements; HBM budget {budget >> 20} MiB",
+                    f"measured on a burst of {calib_jobs} jobs), L uniform in {{16,24,32,48,64,96,128}} "
+                    f"(L > 64 as slab launches after each epoch's batched launch), p~U[0.1,0.5], T~U[0.5,1.2], "
+                    f"sweeps log-uniform in [1e3,{sweep_hi:.0e}], 20 log-spaced measurements; HBM budget "
+                    f"{budget >> 20} MiB",
         "p50_latency_s": round(st["p50_latency_s"], 4),
         "p99_latency_s": round(st["p99_latency_s"], 4),
         "mean_latency_s": round(st["mean_latency_s"], 4),
+        "max_latency_s": round(st["max_latency_s"], 4),
         "ps_per_flip_busy": round(st["ps_per_flip"], 4),
         "ps_per_flip_wall": round(wall / total * 1e12, 4),
-        "plain_ps_per_flip": {str(L): round(rate[L], 3) for L in SERVE_SIZES if L > 64},
+        "ps_per_flip_capacity_burst": round(ps_capacity, 4),
         "flips": total,
         "epochs": int(st["epochs"]),
         "hbm_peak_mib": round(st["hbm_peak"] / 2 ** 20, 1),
@@ -436,6 +439,9 @@ def main():
     ap.add_argument("--msc-burst", type=int, default=1024, help="sweeps in its kernel-timing burst")
     ap.add_argument("--msc-only", action="store_true", help="run only the multispin-coded leg and print it")
     ap.add_argument("--crossover-only", action="store_true", help="run only the crossover leg and print it")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving leg(s) and print them (e.g. --serve-jobs 2000 --serve-sweeps "
+                         "1000000 for the serving configuration as stated)")
     ap.add_argument("--plain-only", action="store_true", help="run only the mid-size plain leg and print it")
     ap.add_argument("--crossover-sweeps", type=int, default=1_000_000,
                     help="sweeps of each crossover run in the grouped-plain leg (0 = skip)")
@@ -476,6 +482,13 @@ def main():
         print(json.dumps({"copy_probe_bytes": n, "read": n, "written": n}), flush=True)
         return
 
+    if args.serve_only:
+        res = {"serving": bench_serving(ea, torch, wl, args.serve_jobs, args.serve_load, args.serve_sweeps)}
+        if args.serve_load2 > 0:
+            res["serving_light"] = bench_serving(ea, torch, wl, args.serve_jobs, args.serve_load2,
+                                                 args.serve_sweeps)
+        print(json.dumps(res), flush=True)
+        return
     if args.crossover_only:
         print(json.dumps({"crossover": bench_crossover(ea, torch, wl.crossover_jobs(args.crossover_sweeps),
                                                        args.crossover_sample_sweeps, args.burst)}), flush=True)
@@ -587,12 +600,11 @@ def main():
 
     if args.serve_jobs:
         log("serving form ...")
-        out["serving"] = bench_serving(ea, torch, wl, args.serve_jobs, args.serve_load, args.serve_sweeps,
-                                       ps_per_flip)
+        out["serving"] = bench_serving(ea, torch, wl, args.serve_jobs, args.serve_load, args.serve_sweeps)
         if args.serve_load2 > 0:
             log(f"serving form at load {args.serve_load2} ...")
             out["serving_light"] = bench_serving(ea, torch, wl, args.serve_jobs, args.serve_load2,
-                                                 args.serve_sweeps, ps_per_flip)
+                                                 args.serve_sweeps)
     if args.msc_sweeps:
         log("multispin-coded batch ...")
         out["msc"] = bench_msc(ea, torch, wl.msc_job(args.msc_sweeps, args.msc_samples), args.msc_burst)

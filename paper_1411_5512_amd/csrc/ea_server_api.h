@@ -16,12 +16,12 @@
 //
 // Lattices too large for one workgroup's LDS (L > 64) are "streamed" jobs:
 // each is a plain-form simulation placed in its pool region with a stream of
-// its own, advanced during the epoch through the HBM-streaming kernels by up
-// to kStreamWorkers host threads at once, so that the half-steps of several
-// such jobs and the batched launch run on the device together.  A streamed
-// job's span is sized by time (its own measured seconds per sweep), so that
-// the streamed work of an epoch takes about as long as the previous epoch's
-// batched launch.
+// its own, advanced in the epoch by slab launches (ea_set_slab_plan) from up
+// to kStreamWorkers host threads at once, after the epoch's batched launch
+// (persistent slab workgroups beside a batched launch would wait for its
+// compute units while holding their own).  A streamed job's span is sized by
+// time (its own measured seconds per sweep), so that the streamed work of an
+// epoch takes about as long as the previous epoch's batched launch.
 #pragma once
 
 #include <algorithm>
@@ -304,7 +304,19 @@ ea_status server_epoch(ea_server *s, int32_t *progressed)
     // kStreamWorkers host threads share them out, each thread's jobs splitting
     // the expected epoch time
     if (!streamed.empty()) {
-        const double target = std::max(s->last_batch_s, 2e-3);
+        // The streamed phase follows the batched launch (which may hold few
+        // jobs and leave most compute units idle), so it gets the batched
+        // launch's time scaled by the ratio of the streamed jobs' remaining
+        // site-updates to the batched jobs', between 1x and 16x (and at least
+        // 2 ms): both forms then progress in proportion to their work.
+        double rem_streamed = 0.0, rem_batched = 0.0;
+        for (ServerJob *j : run) {
+            const double N = (double)j->h.job.L * j->h.job.L * j->h.job.L;
+            const double rem = N * (double)(j->h.job.n_sweeps - j->h.t_host);
+            (j->streamed ? rem_streamed : rem_batched) += rem;
+        }
+        const double ratio = rem_batched > 0.0 ? std::min(16.0, std::max(1.0, rem_streamed / rem_batched)) : 16.0;
+        const double target = std::max(s->last_batch_s * ratio, 2e-3);
         const int n_workers = std::min<int>(kStreamWorkers, (int)streamed.size());
         std::vector<std::vector<size_t>> lists((size_t)n_workers);
         int n = 0;
@@ -313,6 +325,13 @@ ea_status server_epoch(ea_server *s, int32_t *progressed)
         std::vector<std::string> errs((size_t)n_workers);
         auto advance = [&](int k) {
             (void)hipSetDevice(s->device);
+            // after the batched launch: slab workgroups that became resident
+            // beside it would wait for its compute units (and the per-sweep
+            // timing below would include that wait)
+            if (!batched.empty() && hipEventSynchronize(s->ev_batch[1]) != hipSuccess) {
+                errs[(size_t)k] = "hipEventSynchronize failed";
+                return;
+            }
             const double budget = target / (double)lists[(size_t)k].size();
             for (size_t i : lists[(size_t)k]) {
                 ServerJob *j = run[i];
