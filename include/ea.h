@@ -142,10 +142,10 @@ ea_status ea_words_per_row(const ea_sim *sim, int32_t *rw);
  * k = 0 .. n_shells - 1.  n_shells = (L/2)^2 + 1 covers |r| <= L/2, the range
  * of the integral estimators (eqs. 5, 6); 3 (L/2)^2 + 1 covers every r.
  * Dividing a shell by N and by the number of lattice vectors in it gives the
- * shell average of C4.  L <= 128 (the work grows as L^6 / 64).
- * Synchronises; allocates a device scratch buffer of
- * 8 (2 L^2 ceil(L/64) + 3 (L/2)^2 + 1) bytes on the first call, kept until
- * ea_destroy.  EA_ERR_ARG for L > 128 or n_shells outside [1, 3 (L/2)^2 + 1]. */
+ * shell average of C4.  The work grows as L^6 / 64: about 20 ms at L = 128,
+ * over a second at L = 256.  Synchronises; allocates a device scratch buffer
+ * of 8 (2 L^2 ceil(L/64) + 3 (L/2)^2 + 1) bytes on the first call, kept
+ * until ea_destroy.  EA_ERR_ARG for n_shells outside [1, 3 (L/2)^2 + 1]. */
 ea_status ea_c4_shells(ea_sim *sim, int32_t n_shells, int64_t *out);
 
 /* ea_c4_shells for callers that cannot allocate device memory: code under
@@ -155,7 +155,7 @@ ea_status ea_c4_shells(ea_sim *sim, int32_t n_shells, int64_t *out);
  * stream without synchronising: they are valid once the stream has reached
  * this call.  The scratch (the dense overlap rows) is a static device array
  * of 512 KiB on every device the library runs on, held until the process
- * ends; hence L <= 128 (EA_ERR_ARG beyond, and for n_shells outside
+ * ends; hence L <= 128 here (EA_ERR_ARG beyond, and for n_shells outside
  * [1, 3 (L/2)^2 + 1]).  All calls on one device share that array: calls
  * that overlap on a device (runs on different streams) race, so order them
  * on one stream or synchronise between them.  Allocates nothing. */
@@ -323,6 +323,15 @@ ea_status ea_batch_time(ea_batch *b, int32_t job, uint64_t *t);
  * measurement report autocorr 0).  EA_ERR_STATE if it was not reached. */
 ea_status ea_batch_result(ea_batch *b, int32_t job, int32_t k, ea_obs *out);
 
+/* Full-vector C4 shells (as ea_c4_shells, eq. 3 over every displacement) of
+ * job `job` at its measurement k, from the configuration of both replicas
+ * that the batched kernel publishes at each measurement: out[n_shells].
+ * Synchronises; allocates and frees a scratch buffer of
+ * 8 (2 L^2 + n_shells) bytes for the call.  EA_ERR_ARG for a job or k out of
+ * range or n_shells outside [1, 3 (L/2)^2 + 1]; EA_ERR_STATE if measurement
+ * k has not been reached. */
+ea_status ea_batch_c4_shells(ea_batch *b, int32_t job, int32_t k, int32_t n_shells, int64_t *out);
+
 /* Current spins of replica r of job j, int8 +-1 in canonical order [L^3]. */
 ea_status ea_batch_get_spins(ea_batch *b, int32_t job, int32_t r, int8_t *pm1);
 
@@ -469,6 +478,13 @@ ea_status ea_msc_snapshot(ea_msc *batch, int32_t slot);
  * b < n_samples, each filled as ea_measure fills its ea_obs (tw/autocorr
  * and c4 may be NULL per sample).  Synchronises. */
 ea_status ea_msc_measure(ea_msc *batch, ea_obs *out);
+
+/* Full-vector C4 shells (as ea_c4_shells) of sample `sample` (0 .. B-1) of
+ * the batch at the current time: out[n_shells].  Synchronises; allocates and
+ * frees a scratch buffer of 8 (2 L^2 ceil(L/64) + n_shells) bytes for the
+ * call.  EA_ERR_ARG for a sample out of range or n_shells outside
+ * [1, 3 (L/2)^2 + 1]. */
+ea_status ea_msc_c4_shells(ea_msc *m, int32_t sample, int32_t n_shells, int64_t *out);
 
 /* Spins of sample b, replica r, as int8 +-1 [N] in canonical order; set
  * rejects values other than +-1.  Couplings of sample b, [3N] as in

@@ -325,6 +325,14 @@ class Msc:
                     bufs[b][0][:ns].copy(), bufs[b][1][:, :ns].copy(), bufs[b][2] if c4 else None)
                 for b in range(B)]
 
+    def c4_shells(self, sample: int, n_shells: int | None = None) -> np.ndarray:
+        """Full-vector C4 sums by minimum-image squared distance of one
+        sample (see ea_msc_c4_shells); n_shells defaults to (L/2)^2 + 1."""
+        n = (self.L // 2) ** 2 + 1 if n_shells is None else int(n_shells)
+        out = np.zeros(n, dtype=np.int64)
+        abi.check(abi.lib().ea_msc_c4_shells(self._h, int(sample), n, abi.ptr(out, ctypes.c_int64)))
+        return out
+
     def spins(self, b: int, r: int) -> np.ndarray:
         out = np.zeros(self.N, dtype=np.int8)
         abi.check(abi.lib().ea_msc_get_spins(self._h, int(b), int(r), abi.ptr(out, ctypes.c_int8)))
@@ -487,6 +495,15 @@ class Batch:
         bufs = _obs_buffers(J.L, len(J.tw), c4, o)
         abi.check(abi.lib().ea_batch_result(self._h, int(job), int(k), ctypes.byref(o)))
         return _obs_from(o, len(J.tw), *bufs, c4)
+
+    def c4_shells(self, job: int, k: int, n_shells: int | None = None) -> np.ndarray:
+        """Full-vector C4 sums by minimum-image squared distance of job
+        `job` at its measurement k (see ea_batch_c4_shells)."""
+        L = self.jobs[job].L if 0 <= job < len(self.jobs) else 8  # a bad index: the library reports it
+        n = (L // 2) ** 2 + 1 if n_shells is None else int(n_shells)
+        out = np.zeros(n, dtype=np.int64)
+        abi.check(abi.lib().ea_batch_c4_shells(self._h, int(job), int(k), n, abi.ptr(out, ctypes.c_int64)))
+        return out
 
     def spins(self, job: int, r: int) -> np.ndarray:
         out = np.zeros(self.jobs[job].L ** 3, dtype=np.int8)

@@ -175,6 +175,10 @@ _SIGS = {
     "ea_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
     "ea_c4_shells": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
     "ea_c4_shells_into": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "ea_batch_c4_shells": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_int64)]),
+    "ea_msc_c4_shells": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int64)]),
     "ea_tune_plain": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(TuneChoice), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "ea_footprint_ex": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_size_t)]),

@@ -4,6 +4,7 @@
 #include "ea.h"
 #include "ea_batch_kernels.h"
 #include "ea_slab_kernels.h"
+#include "ea_shells.h"
 
 #include <chrono>
 #include <cmath>
@@ -58,7 +59,8 @@ bool rw_valid(int R, int rw) { return rw >= 1 && R % 4 == 0 && (R / 4) % rw == 0
 // kPlainMinThreads threads (one wave per SIMD of every CU): below that a
 // launch lasts as long as one thread's chain of dependent instructions.
 constexpr long kPlainMinThreads = 65536;
-constexpr int kMaxShellL = 128;  // largest side with full-vector C4 (its cost grows as L^6 / 64)
+constexpr int kMaxShellL = 256;      // largest side with full-vector C4 (its cost grows as L^6 / 64)
+constexpr int kMaxShellLNoAlloc = 128;  // largest side of the allocation-free variant (its static scratch)
 std::mutex g_plain_mu;
 std::map<int, int> g_plain_tuned;  // L -> words per row
 bool g_plain_file_read = false;
@@ -97,7 +99,8 @@ void read_plain_tune_file()
 // threads.
 bool slab_capable(int L, int rw) { return L * rw <= ea::kSlabThreads; }
 
-// Modelled time per sweep (us) of a plan, used to pick one, with constants
+// Modelled time per sweep (us) of a plan whose workgroups own at most s
+// planes each, used to pick one, with constants
 // measured on MI355X: a packed word costs ~(13.2 W + 40) VALU
 // lane-instructions, ~370 words of 32 sites per us on one compute unit, and
 // no less than one word's chain of dependent instructions per half-step.
@@ -105,13 +108,12 @@ bool slab_capable(int L, int rw) { return L * rw <= ea::kSlabThreads; }
 // slab's words; a cycle of g >= 2 half-steps costs ~3 us
 // beyond its words (the ghost planes are read only after the neighbours'
 // whole cycle, with a barrier on either side).
-double slab_model_us(int L, int rw, int K, int g)
+double slab_model_us(int L, int rw, int s, int g)
 {
     const int W = L / 2 / rw, PL = L * rw;
     const double per_word = 13.2 * W + 40.0;
     const double rate = 370.0 * (13.2 * 32 + 40.0) / per_word;  // words per us on one compute unit
     const double chain = per_word * 4.0 / 2400.0;  // one word's dependent instructions alone on a SIMD, us
-    const int s = (L + K - 1) / K;
     if (g == 1) return 2.0 * (0.9 + std::max(chain, (double)s * PL / rate));
     double cycle = 3.0;
     for (int k = 1; k <= g; ++k) cycle += std::max(chain, (double)(s + 2 * g - 2 * k) * PL / rate);
@@ -131,7 +133,7 @@ double slab_best_model_us(int L, int rw)
             const int emax = (L + K - 1) / K + 2 * g;
             if (4 * (8 * (size_t)emax * (size_t)(L * rw) + 16) > 160 * 1024 - 4 * (size_t)ea::kSelectTableWords)
                 continue;
-            const double c = slab_model_us(L, rw, K, g);
+            const double c = slab_model_us(L, rw, (L + K - 1) / K, g);
             if (best < 0.0 || c < best) best = c;
         }
     return best;
@@ -368,10 +370,28 @@ ea_status build_graph(ea_sim *s)
 constexpr uint32_t kSlabMaxSweeps = 16384;  // sweeps per launch (a launch stays well under a second)
 constexpr int kSlabMaxGhost = 8;
 
+// A launch plan: B workgroups share the replicas' planes laid end to end
+// (ea_slab_kernels.h), g ghost planes per side; K = B / (2 runs) when every
+// workgroup holds one slab of one replica (explicit plans always do).
 struct SlabPlan {
-    int K = 0, g = 0, emax = 0;
-    size_t lds = 0;  // dynamic LDS bytes
+    int K = 0, B = 0, g = 0, emax = 0;
+    size_t lds = 0;  // dynamic LDS bytes without a second select table
 };
+
+// Largest extended region (LDS planes) of any workgroup of a plan, computed
+// as the kernel splits the shares.
+int slab_emax(int L, int n_runs, int B, int g)
+{
+    const long P = 2L * n_runs * L;
+    int emax = 0;
+    for (int b = 0; b < B; ++b) {
+        const int start = (int)((long)b * P / B), end = (int)((long)(b + 1) * P / B);
+        const int cut = (start / L + 1) * L;
+        const int e = end <= cut ? end - start + 2 * g : (cut - start + 2 * g) + (end - cut + 2 * g);
+        emax = std::max(emax, e);
+    }
+    return emax;
+}
 
 size_t slab_lds_bytes(int L, int rw, int emax) { return 4 * (8 * (size_t)emax * (size_t)(L * rw) + 16); }
 
@@ -420,43 +440,63 @@ ea_status slab_device(int W, int *n_cu, int *lds_limit)
     return EA_OK;
 }
 
-bool slab_plan_fits(int L, int rw, int n_runs, int K, int g, int n_cu, int lds_limit, SlabPlan *out)
+// A plan of B workgroups (g > 1: whole slabs only, B = 2 runs K) if it fits
+// the device: at most one 1024-thread workgroup per compute unit, shares
+// within one replica's length, the extended regions within the LDS.
+bool slab_plan_fits(int L, int rw, int n_runs, int B, int g, int n_cu, int lds_limit, SlabPlan *out)
 {
-    if (K < 1 || K > L || g < 1 || g > kSlabMaxGhost || g > L) return false;
-    if ((long)2 * n_runs * K > (long)n_cu) return false;  // one 1024-thread workgroup per compute unit
-    const int emax = (L + K - 1) / K + 2 * g;
+    const long P = 2L * n_runs * L;
+    if (B < 2 * n_runs || B > P || B > n_cu || g < 1 || g > kSlabMaxGhost || g > L) return false;
+    const bool whole = B % (2 * n_runs) == 0;
+    if (g > 1 && !whole) return false;
+    const int emax = slab_emax(L, n_runs, B, g);
     const size_t lds = slab_lds_bytes(L, rw, emax);
-    if (lds > (size_t)lds_limit) return false;
-    out->K = K;
+    // shares that span two runs may need a second select table
+    const size_t extra = (!whole && n_runs > 1) ? 4 * (size_t)ea::kSelectTableWords : 0;
+    if (lds + extra > (size_t)lds_limit) return false;
+    out->K = whole ? B / (2 * n_runs) : 0;
+    out->B = B;
     out->g = g;
     out->emax = emax;
     out->lds = lds;
     return true;
 }
 
-// The plan for n_runs runs of side L in packing rw: the requested one
-// (K > 0; g = 0 picks the best ghost depth for it), else the modelled best.
+// The plan for n_runs runs of side L in packing rw: the requested slabs per
+// replica (K > 0; g = 0 picks the best ghost depth for it), else the
+// modelled best, where shares of g = 1 plans may span two replicas (an even
+// number of workgroups).
 ea_status slab_choose(int L, int rw, int n_runs, int K_req, int g_req, SlabPlan *plan)
 {
     if (!slab_capable(L, rw)) return fail(EA_ERR_ARG, "L=%d with %d words per row has no slab plan", L, rw);
     int n_cu = 0, lds_limit = 0;
     ea_status st = slab_device(L / 2 / rw, &n_cu, &lds_limit);
     if (st != EA_OK) return st;
+    const long P = 2L * n_runs * L;
     double best = 0.0;
     bool found = false;
-    const int k_lo = K_req > 0 ? K_req : 1, k_hi = K_req > 0 ? K_req : L;
-    const int g_lo = g_req > 0 ? g_req : 1, g_hi = g_req > 0 ? g_req : 4;
-    for (int K = k_lo; K <= k_hi; ++K)
-        for (int g = g_lo; g <= g_hi; ++g) {
-            SlabPlan p;
-            if (!slab_plan_fits(L, rw, n_runs, K, g, n_cu, lds_limit, &p)) continue;
-            const double c = slab_model_us(L, rw, K, g);
-            if (!found || c < best) {
-                best = c;
-                *plan = p;
-                found = true;
-            }
+    auto consider = [&](int B, int g) {
+        SlabPlan p;
+        if (!slab_plan_fits(L, rw, n_runs, B, g, n_cu, lds_limit, &p)) return;
+        const double c = slab_model_us(L, rw, (int)((P + B - 1) / B), g);
+        if (!found || c < best) {
+            best = c;
+            *plan = p;
+            found = true;
         }
+    };
+    const int g_lo = g_req > 0 ? g_req : 1, g_hi = g_req > 0 ? g_req : 4;
+    if (K_req > 0) {
+        if (K_req <= L)
+            for (int g = g_lo; g <= g_hi; ++g) consider(2 * n_runs * K_req, g);
+    } else {
+        for (int g = g_lo; g <= g_hi; ++g) {
+            if (g == 1)
+                for (int B = 2 * n_runs; B <= n_cu && B <= P; B += 2) consider(B, 1);
+            else
+                for (int K = 1; K <= L; ++K) consider(2 * n_runs * K, g);
+        }
+    }
     if (!found)
         return fail(EA_ERR_ARG, "no slab plan (K=%d, g=%d) fits %d run(s) of L=%d on %d compute units", K_req,
                     g_req, n_runs, L, n_cu);
@@ -489,15 +529,30 @@ ea_status launch_slab(ea_sim *const *runs, int n, uint64_t sweeps, const SlabPla
         }
         m->slab_used = true;
     }
+    // a second select table when some workgroup's two pieces belong to runs
+    // of different temperature
+    int tables = 1;
+    for (int b = 0; b < plan.B; ++b) {
+        const long P = 2L * n * y.L;
+        const int start = (int)((long)b * P / plan.B), end = (int)((long)(b + 1) * P / plan.B);
+        const int q0 = start / y.L;
+        if (end > (q0 + 1) * y.L) {
+            const ea_sim *u = runs[q0 / 2], *v = runs[(q0 + 1) / 2];
+            if (u->thr[0] != v->thr[0] || u->thr[1] != v->thr[1] || u->thr[2] != v->thr[2]) tables = 2;
+        }
+    }
+    const size_t lds = plan.lds + (tables == 2 ? 4 * (size_t)ea::kSelectTableWords : 0);
     uint64_t done = 0;
     while (done < sweeps) {
         const uint32_t chunk = (uint32_t)std::min<uint64_t>(kSlabMaxSweeps, sweeps - done);
         ea::SlabLaunch a{};
         a.L = y.L;
         a.RW = y.RW;
-        a.K = plan.K;
         a.g = plan.g;
+        a.B = plan.B;
+        a.P = 2 * n * y.L;
         a.emax = plan.emax;
+        a.tables = tables;
         a.n_half = 2 * chunk;
         a.err = lead->err_dev;
         const uint64_t n_cycles = (a.n_half + (uint64_t)plan.g - 1) / (uint64_t)plan.g;
@@ -523,14 +578,14 @@ ea_status launch_slab(ea_sim *const *runs, int n, uint64_t sweeps, const SlabPla
             d.serial = (uint32_t)m->xserial;
             m->xserial += n_cycles + 1;
         }
-        const dim3 grid((unsigned)(2 * n * plan.K));
-        // the screen pays where every slab gives each SIMD four waves of work
-        if ((long)(y.L / plan.K) * y.L * y.RW >= ea::kSlabThreads) {
+        const dim3 grid((unsigned)plan.B);
+        // the screen pays where every workgroup gives each SIMD four waves of work
+        if ((long)(a.P / plan.B) * y.L * y.RW >= ea::kSlabThreads) {
             EA_DISPATCH_W(y.W, hipLaunchKernelGGL((ea::slab_sweep_kernel<WW, true>), grid, dim3(ea::kSlabThreads),
-                                                  plan.lds, lead->stream, a));
+                                                  lds, lead->stream, a));
         } else {
             EA_DISPATCH_W(y.W, hipLaunchKernelGGL((ea::slab_sweep_kernel<WW, false>), grid, dim3(ea::kSlabThreads),
-                                                  plan.lds, lead->stream, a));
+                                                  lds, lead->stream, a));
         }
         EA_HIP(hipGetLastError());
         done += chunk;
@@ -553,6 +608,22 @@ ea_status slab_check(ea_sim *s)
     if (e)
         return fail(EA_ERR_DEVICE, "a slab launch gave up waiting for a neighbouring slab (its workgroups were not "
                                    "all resident within seconds); the run's state is undefined until ea_reset");
+    return EA_OK;
+}
+
+// Shell sums of dense overlap rows (ea_shells.h) for any L up to 256.
+ea_status launch_shell_rows(const unsigned long long *qd, int L, int n_shells, unsigned long long *shells,
+                            hipStream_t stream)
+{
+    const dim3 grid((unsigned)((L + ea::kShellChunk - 1) / ea::kShellChunk), (unsigned)(L * L));
+    switch ((L + 63) / 64) {
+    case 1: hipLaunchKernelGGL((ea::c4_shell_rows_kernel<1>), grid, dim3(256), 0, stream, qd, L, n_shells, shells); break;
+    case 2: hipLaunchKernelGGL((ea::c4_shell_rows_kernel<2>), grid, dim3(256), 0, stream, qd, L, n_shells, shells); break;
+    case 3: hipLaunchKernelGGL((ea::c4_shell_rows_kernel<3>), grid, dim3(256), 0, stream, qd, L, n_shells, shells); break;
+    case 4: hipLaunchKernelGGL((ea::c4_shell_rows_kernel<4>), grid, dim3(256), 0, stream, qd, L, n_shells, shells); break;
+    default: return fail(EA_ERR_ARG, "full-vector C4 needs L <= 256 (L=%d)", L);
+    }
+    EA_HIP(hipGetLastError());
     return EA_OK;
 }
 
@@ -764,7 +835,7 @@ ea_status ea_sweep(ea_sim *s, uint64_t n)
     SlabPlan plan;
     ea_status pst = slab_plan_of(s, 1, &plan);
     if (pst != EA_OK) return pst;
-    if (plan.K > 0) {
+    if (plan.B > 0) {
         ea_sim *one[1] = {s};
         pst = launch_slab(one, 1, n, plan);
         if (pst != EA_OK) return pst;
@@ -827,7 +898,7 @@ ea_status ea_sweep_group(ea_sim *const *sims, int32_t n_sims, uint64_t n)
         ea_status pst = slab_plan_of(lead, per, &plan);
         if (pst != EA_OK) return pst;
     }
-    if (plan.K > 0) {
+    if (plan.B > 0) {
         // one slab launch per chunk of at most kGroupMax runs
         for (int32_t c0 = 0; c0 < n_sims; c0 += ea::kGroupMax) {
             const int cnt = std::min<int32_t>(ea::kGroupMax, n_sims - c0);
@@ -969,11 +1040,16 @@ ea_status ea_c4_shells(ea_sim *s, int32_t n_shells, int64_t *out)
     ea::Geom g = s->geom();
     EA_DISPATCH_W(s->lay.W, hipLaunchKernelGGL((ea::dense_q_kernel<WW>), dim3(blocks_for(q_words)), dim3(256), 0,
                                                s->stream, s->lat, g, dw, qd));
-    const dim3 grid((unsigned)((L + ea::kShellRx - 1) / ea::kShellRx), (unsigned)(L * L));
-    if (nw == 1)
-        hipLaunchKernelGGL((ea::c4_shell_kernel<1>), grid, dim3(256), 0, s->stream, qd, L, n_shells, shells);
-    else
-        hipLaunchKernelGGL((ea::c4_shell_kernel<2>), grid, dim3(256), 0, s->stream, qd, L, n_shells, shells);
+    if (nw <= 2) {
+        const dim3 grid((unsigned)((L + ea::kShellRx - 1) / ea::kShellRx), (unsigned)(L * L));
+        if (nw == 1)
+            hipLaunchKernelGGL((ea::c4_shell_kernel<1>), grid, dim3(256), 0, s->stream, qd, L, n_shells, shells);
+        else
+            hipLaunchKernelGGL((ea::c4_shell_kernel<2>), grid, dim3(256), 0, s->stream, qd, L, n_shells, shells);
+    } else {
+        ea_status st = launch_shell_rows(qd, L, n_shells, shells, s->stream);
+        if (st != EA_OK) return st;
+    }
     EA_HIP(hipGetLastError());
     EA_HIP(hipMemcpyAsync(out, shells, 8 * (size_t)n_shells, hipMemcpyDeviceToHost, s->stream));
     EA_HIP(hipStreamSynchronize(s->stream));
@@ -989,7 +1065,8 @@ namespace {
 // 512 KiB), one array per device for the life of the process.  Host code
 // never passes the array's name to a kernel: it passes the device address
 // that hipGetSymbolAddress returned for that device.
-constexpr size_t kScratchWords = (size_t)kMaxShellL * kMaxShellL * 2 * ((kMaxShellL + 63) / 64);
+constexpr size_t kScratchWords =
+    (size_t)kMaxShellLNoAlloc * kMaxShellLNoAlloc * 2 * ((kMaxShellLNoAlloc + 63) / 64);
 __device__ __align__(256) unsigned long long scratch[kScratchWords];
 
 constexpr int kScratchDevices = 64;
@@ -1022,9 +1099,10 @@ ea_status ea_c4_shells_into(ea_sim *s, int32_t n_shells, int64_t *out_dev)
 {
     if (!s || !out_dev) return fail(EA_ERR_ARG, "NULL argument");
     const int L = s->lay.L;
-    if (L > kMaxShellL)
-        return fail(EA_ERR_ARG, "full-vector C4 is offered for L <= %d (L=%d): the scratch array holds the dense "
-                                "overlap of L = %d at most", kMaxShellL, L, kMaxShellL);
+    if (L > kMaxShellLNoAlloc)
+        return fail(EA_ERR_ARG, "the allocation-free full-vector C4 is offered for L <= %d (L=%d): the scratch "
+                                "array holds the dense overlap of L = %d at most", kMaxShellLNoAlloc, L,
+                    kMaxShellLNoAlloc);
     const int max_shells = 3 * (L / 2) * (L / 2) + 1;
     if (n_shells < 1 || n_shells > max_shells)
         return fail(EA_ERR_ARG, "n_shells=%d outside [1, %d]", n_shells, max_shells);
@@ -1122,8 +1200,8 @@ ea_status ea_get_slab_plan(const ea_sim *s, int32_t *slabs, int32_t *ghost)
     SlabPlan plan;
     ea_status st = slab_plan_of(s, 1, &plan);
     if (st != EA_OK) return st;
-    *slabs = plan.K;
-    *ghost = plan.K > 0 ? plan.g : 0;
+    *slabs = plan.K > 0 ? plan.K : (plan.K < 0 ? -1 : plan.B / 2);
+    *ghost = plan.K < 0 ? 0 : plan.g;
     return EA_OK;
 }
 
@@ -1287,3 +1365,4 @@ ea_status ea_set_bonds(ea_sim *s, const int8_t *pm1)
 #include "ea_batch_api.h"
 #include "ea_server_api.h"
 #include "ea_msc_api.h"
+#include "ea_shells_api.h"

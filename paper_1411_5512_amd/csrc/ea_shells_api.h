@@ -1,0 +1,104 @@
+// ea_shells_api.h -- full-vector C4 shells (eq. 3 over every displacement)
+// of the batched form's published configurations and of the multispin-coded
+// batch's samples (ea_batch_c4_shells, ea_msc_c4_shells in ea.h).
+#pragma once
+
+namespace {
+
+// A device buffer for one call, freed on every return path.
+struct CallScratch {
+    unsigned long long *p = nullptr;
+    ~CallScratch()
+    {
+        if (p) (void)hipFree(p);
+    }
+};
+
+// Zero the shells, sum them from the dense rows, copy them to the host and
+// wait.
+ea_status shells_to_host(const unsigned long long *qd, unsigned long long *shells, int L, int n_shells, int64_t *out,
+                         hipStream_t stream)
+{
+    ea_status st = launch_shell_rows(qd, L, n_shells, shells, stream);
+    if (st != EA_OK) return st;
+    EA_HIP(hipMemcpyAsync(out, shells, 8 * (size_t)n_shells, hipMemcpyDeviceToHost, stream));
+    EA_HIP(hipStreamSynchronize(stream));
+    return EA_OK;
+}
+
+ea_status shell_scratch(CallScratch &sc, int L, int n_shells, unsigned long long **qd, unsigned long long **shells,
+                        int *dw, hipStream_t stream)
+{
+    *dw = 2 * ((L + 63) / 64);
+    const size_t q_words = (size_t)L * L * (size_t)*dw;
+    const hipError_t e = hipMalloc((void **)&sc.p, 8 * (q_words + (size_t)n_shells));
+    if (e != hipSuccess) {
+        sc.p = nullptr;
+        return fail(EA_ERR_NOMEM, "hipMalloc(C4 shell scratch): %s", hipGetErrorString(e));
+    }
+    *qd = sc.p;
+    *shells = sc.p + q_words;
+    hipLaunchKernelGGL(ea::zero_u64_kernel, dim3(blocks_for((size_t)n_shells)), dim3(256), 0, stream, *shells,
+                       (size_t)n_shells);
+    EA_HIP(hipGetLastError());
+    return EA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ea_status ea_batch_c4_shells(ea_batch *b, int32_t job, int32_t k, int32_t n_shells, int64_t *out)
+{
+    if (!b || !out) return fail(EA_ERR_ARG, "NULL argument");
+    if (job < 0 || job >= (int32_t)b->jobs.size()) return fail(EA_ERR_ARG, "job %d out of range", job);
+    const BatchJobHost &h = b->jobs[(size_t)job];
+    if (k < 0 || k >= h.job.n_meas) return fail(EA_ERR_ARG, "measurement %d out of range", k);
+    if (h.meas_t[(size_t)k] > h.t_host || !h.started)
+        return fail(EA_ERR_STATE, "measurement %d (t=%u) not reached", k, h.meas_t[(size_t)k]);
+    const int L = h.job.L;
+    const int max_shells = 3 * (L / 2) * (L / 2) + 1;
+    if (n_shells < 1 || n_shells > max_shells)
+        return fail(EA_ERR_ARG, "n_shells=%d outside [1, %d]", n_shells, max_shells);
+    CallScratch sc;
+    unsigned long long *qd = nullptr, *shells = nullptr;
+    int dw = 0;
+    ea_status st = shell_scratch(sc, L, n_shells, &qd, &shells, &dw, b->stream);
+    if (st != EA_OK) return st;
+    // the configuration published at measurement k: [replica][colour][POS]
+    ea::Lattice lat{};
+    lat.spins = (uint32_t *)(h.base + h.off_mspins) + (size_t)k * 4 * (size_t)h.POS;
+    ea::Geom g{};
+    g.L = L;
+    g.R = L / 2;
+    g.RW = h.RW;
+    g.rows = L * L;
+    g.plane = h.POS;
+    const size_t q_words = (size_t)L * L * (size_t)dw;
+    EA_DISPATCH_W(h.W, hipLaunchKernelGGL((ea::dense_q_kernel<WW>), dim3(blocks_for(q_words)), dim3(256), 0,
+                                          b->stream, lat, g, dw, qd));
+    EA_HIP(hipGetLastError());
+    return shells_to_host(qd, shells, L, n_shells, out, b->stream);
+}
+
+ea_status ea_msc_c4_shells(ea_msc *m, int32_t sample, int32_t n_shells, int64_t *out)
+{
+    if (!m || !out) return fail(EA_ERR_ARG, "NULL argument");
+    if (sample < 0 || sample >= m->B) return fail(EA_ERR_ARG, "sample %d outside [0, %d)", sample, m->B);
+    const int L = m->L;
+    const int max_shells = 3 * (L / 2) * (L / 2) + 1;
+    if (n_shells < 1 || n_shells > max_shells)
+        return fail(EA_ERR_ARG, "n_shells=%d outside [1, %d]", n_shells, max_shells);
+    CallScratch sc;
+    unsigned long long *qd = nullptr, *shells = nullptr;
+    int dw = 0;
+    ea_status st = shell_scratch(sc, L, n_shells, &qd, &shells, &dw, m->stream);
+    if (st != EA_OK) return st;
+    const size_t q_words = (size_t)L * L * (size_t)dw;
+    hipLaunchKernelGGL(ea::msc_dense_q_kernel, dim3(blocks_for(q_words)), dim3(256), 0, m->stream, m->lat, m->geom,
+                       m->M, sample / m->M, sample % m->M, dw, qd);
+    EA_HIP(hipGetLastError());
+    return shells_to_host(qd, shells, L, n_shells, out, m->stream);
+}
+
+}  // extern "C"

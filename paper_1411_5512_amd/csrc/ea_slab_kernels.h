@@ -52,14 +52,48 @@ struct SlabRunDev {
     uint32_t serial;          // epoch of cycle m is serial + m + 1
 };
 
-// Workgroup b runs slab b mod K of replica (b / K) mod 2 of run b / (2K):
-// slab k owns the planes [k L / K, (k + 1) L / K).
+// The replicas of a launch laid end to end (replica q = 2 run + r, its
+// plane z at index q L + z, P = 2 L runs planes in all); workgroup b owns the
+// planes [b P / B, (b + 1) P / B): one slab of one replica, or the end of one
+// replica and the start of the next (B >= 2 runs keeps a share within L
+// planes).  With B = 2 runs K this is K slabs per replica, slab k owning the
+// planes [k L / K, (k + 1) L / K).
 struct SlabLaunch {
     SlabRunDev runs[kGroupMax];
-    int32_t L, RW, K, g, emax;  // emax: LDS planes per array, at least s + 2 g of every slab
-    uint32_t n_half;            // half-steps in this launch (the first is half 0 of sweep t0)
-    uint32_t *err;              // set when a wait timed out; every workgroup then ends
+    int32_t L, RW, g;
+    int32_t B, P;        // workgroups, planes of all replicas
+    int32_t emax;        // LDS planes per array: the extended regions of a workgroup's pieces
+    int32_t tables;      // 2: a workgroup's second piece (another run) has its own select table
+    uint32_t n_half;     // half-steps in this launch (the first is half 0 of sweep t0)
+    uint32_t *err;       // set when a wait timed out; every workgroup then ends
 };
+
+// One piece of a workgroup's share: owned planes [z0, z0 + s) of replica r
+// of run `run`, its extended region (g ghost planes either side) at local
+// LDS planes [off, off + s + 2 g).
+struct SlabPiece {
+    int run, r, z0, s, off;
+};
+
+__device__ __forceinline__ int slab_pieces(const SlabLaunch &a, int b, SlabPiece &p0, SlabPiece &p1)
+{
+    const int L = a.L;
+    const int start = (int)((long long)b * a.P / a.B), end = (int)((long long)(b + 1) * a.P / a.B);
+    const int q0 = start / L, cut = (q0 + 1) * L;
+    p0.run = q0 >> 1;
+    p0.r = q0 & 1;
+    p0.z0 = start - q0 * L;
+    p0.s = min(end, cut) - start;
+    p0.off = 0;
+    p1 = p0;
+    if (end <= cut) return 1;
+    p1.run = (q0 + 1) >> 1;
+    p1.r = (q0 + 1) & 1;
+    p1.z0 = 0;
+    p1.s = end - cut;
+    p1.off = p0.s + 2 * a.g;
+    return 2;
+}
 
 extern __shared__ uint32_t slab_lds[];
 
@@ -246,17 +280,16 @@ __shared__ __align__(16) uint32_t slab_select_tables[kSelectTableWords];
 template <int W, bool SCREEN>
 __global__ __launch_bounds__(kSlabThreads) void slab_sweep_kernel(SlabLaunch a)
 {
-    const int K = a.K, L = a.L, RW = a.RW, PL = L * RW, R = L / 2;
-    const int b = (int)blockIdx.x;
-    const int slab = b % K, r = (b / K) & 1;
-    const SlabRunDev &run = a.runs[b / (2 * K)];
-    const int z0 = slab * L / K, s = (slab + 1) * L / K - z0;
-    const int g = a.g, E = s + 2 * g, EM = a.emax;
-    const int zb = z0 - g;  // global plane of local plane 0, before wrapping
-    // LDS: [colour][EM][PL] spins, [direction][colour][EM][PL] couplings, flags
+    const int L = a.L, RW = a.RW, PL = L * RW, R = L / 2;
+    const int g = a.g, EM = a.emax;
+    SlabPiece p0, p1;
+    const int np = slab_pieces(a, (int)blockIdx.x, p0, p1);
+    // LDS: [colour][EM][PL] spins, [direction][colour][EM][PL] couplings,
+    // 16 flag words, then (tables = 2) the second piece's select table
     uint32_t *lspin = slab_lds;
     uint32_t *lbond = slab_lds + 2 * EM * PL;
     uint32_t *flag = slab_lds + 8 * EM * PL;
+    uint32_t *tab1 = flag + 16;
 
     // threads: column q of the z-planes, plane offset zoff, zstep planes at once
     const int zstep = kSlabThreads / PL;
@@ -275,30 +308,40 @@ __global__ __launch_bounds__(kSlabThreads) void slab_sweep_kernel(SlabLaunch a)
     }
     __syncthreads();
     if (flag[0]) return;
-    const uint32_t *tab = slab_select_tables;
-
-    // the extended region from the state in HBM (the launch boundary makes it whole)
-    const size_t plane = (size_t)L * L * RW;
-    for (int i = tid; i < E * PL; i += kSlabThreads) {
-        const int e = i / PL, c0 = i - e * PL;
-        const int zg = wrap(zb + e, L);
-        const size_t src = (size_t)zg * PL + c0;
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-            lspin[(c * EM + e) * PL + c0] = run.spins[((size_t)r * 2 + c) * plane + src];
-#pragma unroll
-        for (int dc = 0; dc < 6; ++dc) lbond[(dc * EM + e) * PL + c0] = run.bonds[(size_t)dc * plane + src];
+    if (g > 1 && np > 1) {  // the host plans ghost depths above 1 with whole slabs only
+        if (tid == 0) __hip_atomic_store(a.err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
     }
-    fill_select_tables(slab_select_tables, run.thr1, run.thr2, run.thr3, tid, kSlabThreads);
+
+    // the extended regions from the state in HBM (the launch boundary makes them whole)
+    const size_t plane = (size_t)L * L * RW;
+    for (int pi = 0; pi < np; ++pi) {
+        const SlabPiece pc = pi ? p1 : p0;
+        const SlabRunDev &run = a.runs[pc.run];
+        const int E = pc.s + 2 * g, zb = pc.z0 - g;
+        for (int i = tid; i < E * PL; i += kSlabThreads) {
+            const int e = i / PL, c0 = i - e * PL;
+            const int le = pc.off + e;
+            const size_t src = (size_t)wrap(zb + e, L) * PL + c0;
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+                lspin[(c * EM + le) * PL + c0] = run.spins[((size_t)pc.r * 2 + c) * plane + src];
+#pragma unroll
+            for (int dc = 0; dc < 6; ++dc) lbond[(dc * EM + le) * PL + c0] = run.bonds[(size_t)dc * plane + src];
+        }
+    }
+    const SlabRunDev &run0 = a.runs[p0.run];
+    const SlabRunDev &run1 = a.runs[p1.run];
+    fill_select_tables(slab_select_tables, run0.thr1, run0.thr2, run0.thr3, tid, kSlabThreads);
+    if (a.tables == 2 && np > 1) fill_select_tables(tab1, run1.thr1, run1.thr2, run1.thr3, tid, kSlabThreads);
     __syncthreads();
 
     const uint32_t n_half = a.n_half;
     const size_t xrep = (size_t)kSlabSlots * 2 * (size_t)L * PL;  // entries per replica
-    unsigned long long *xb = run.xbuf + (size_t)r * xrep;
 
     if (g == 1) {
         // One half-step per exchange.  A boundary word's only neighbour outside
-        // the slab is its z neighbour in the ghost plane, same column, of the
+        // its piece is its z neighbour in the ghost plane, same column, of the
         // colour the neighbouring slab updated in the previous half-step: the
         // thread that updates the word loads that entry itself before its
         // random words and checks the epoch after them, so no ghost pass and
@@ -306,21 +349,34 @@ __global__ __launch_bounds__(kSlabThreads) void slab_sweep_kernel(SlabLaunch a)
         // exchange.  Ghost planes in LDS are read only in the first half-step.
         // (Measured: a look after the random words instead, or a second look
         // there, is 5-10% slower at L = 64.)
-        const int zlo = wrap(z0 - 1, L), zhi = wrap(z0 + s, L);
+        const uint32_t *tab_1 = a.tables == 2 ? tab1 : slab_select_tables;
         for (uint32_t j = 0; j < n_half; ++j) {
-            const uint32_t t = run.t0 + (j >> 1);
-            const int c = r ^ (int)(j & 1u);
-            const uint32_t ep_prev = run.serial + j, ep_now = run.serial + j + 1u;
             const int slot_now = (int)(j % (uint32_t)kSlabSlots);
             const int slot_prev = (int)((j + (uint32_t)kSlabSlots - 1u) % (uint32_t)kSlabSlots);
-            unsigned long long *gl = xb + (((size_t)slot_prev * 2 + (c ^ 1)) * L + zlo) * PL + q;
-            unsigned long long *gu = xb + (((size_t)slot_prev * 2 + (c ^ 1)) * L + zhi) * PL + q;
-            unsigned long long *pub = xb + ((size_t)slot_now * 2 + c) * (size_t)L * PL + q;
-            const SlabPlanes P = slab_planes(lspin, lbond, EM * PL, c);
-            const uint32_t c2 = counter_word2(TAG_METRO, (uint32_t)c, (uint32_t)r);
-            if (worker) {
-                for (int it = zoff; it < s; it += zstep) {
-                    const int e = 1 + ((it & 1) ? s - 1 - (it >> 1) : (it >> 1));
+            // the pieces one after the other, each with its constants uniform
+            // across the workgroup; a thread's items continue its stride
+            // (items zoff, zoff + zstep, ... over both pieces' planes)
+            for (int pi = 0; pi < np; ++pi) {
+                const SlabPiece pc = pi ? p1 : p0;
+                const SlabRunDev &run = pi ? run1 : run0;
+                const uint32_t *tab = pi ? tab_1 : slab_select_tables;
+                const int s = pc.s, z0 = pc.z0, r = pc.r, off = pc.off;
+                const int first = pi ? p0.s : 0;  // item number of the piece's first plane
+                const int c = r ^ (int)(j & 1u);
+                const uint32_t t = run.t0 + (j >> 1);
+                const uint32_t ep_prev = run.serial + j, ep_now = run.serial + j + 1u;
+                const uint32_t c2 = counter_word2(TAG_METRO, (uint32_t)c, (uint32_t)r);
+                unsigned long long *xb = run.xbuf + (size_t)r * xrep;
+                unsigned long long *gl = xb + (((size_t)slot_prev * 2 + (c ^ 1)) * L + wrap(z0 - 1, L)) * PL + q;
+                unsigned long long *gu = xb + (((size_t)slot_prev * 2 + (c ^ 1)) * L + wrap(z0 + s, L)) * PL + q;
+                unsigned long long *pub = xb + ((size_t)slot_now * 2 + c) * (size_t)L * PL + q;
+                const SlabPlanes P = slab_planes(lspin, lbond, EM * PL, c);
+                if (!worker) continue;
+                int it = zoff;
+                if (first > it) it += ((first - it + zstep - 1) / zstep) * zstep;
+                for (; it < first + s; it += zstep) {
+                    const int jj = it - first;
+                    const int e = 1 + ((jj & 1) ? s - 1 - (jj >> 1) : (jj >> 1));
                     const bool lo = e == 1, hi = e == s;
                     const bool need_lo = lo && j > 0, need_hi = hi && j > 0;
                     const int zg = z0 + e - 1;
@@ -329,8 +385,9 @@ __global__ __launch_bounds__(kSlabThreads) void slab_sweep_kernel(SlabLaunch a)
                     unsigned long long vl = 0, vu = 0;
                     if (need_lo) vl = __hip_atomic_load(gl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     if (need_hi) vu = __hip_atomic_load(gu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const int base = (off + e) * PL;
                     SlabWord<W> sw;
-                    sw.load(P, e * PL, q, qm, qp, qym, qyp, PL);
+                    sw.load(P, base, q, qm, qp, qym, qyp, PL);
                     __builtin_amdgcn_sched_barrier(0);
                     sw.draw(t, (uint32_t)(((y + L * zg) * R + w * W) >> 2), c2, run.sample, run.k0, run.k1);
                     if (need_lo && (uint32_t)(vl >> 32) != ep_prev && !slab_poll(gl, ep_prev, a.err, vl)) flag[1] = 1;
@@ -338,7 +395,7 @@ __global__ __launch_bounds__(kSlabThreads) void slab_sweep_kernel(SlabLaunch a)
                     if (need_lo) sw.Zm = (uint32_t)vl;
                     if (need_hi) sw.Zp = (uint32_t)vu;
                     const uint32_t v = sw.template update<SCREEN>((y + zg + c) & 1, run.thr1, run.thr2, run.thr3, tab);
-                    P.own[e * PL + q] = v;
+                    P.own[base + q] = v;
                     if (lo || hi)
                         __hip_atomic_store(pub + (size_t)zg * PL, ((unsigned long long)ep_now << 32) | v,
                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -351,8 +408,13 @@ __global__ __launch_bounds__(kSlabThreads) void slab_sweep_kernel(SlabLaunch a)
             }
         }
     } else {
-        // g half-steps per exchange on the shrinking extended region, then
-        // the 2g ghost planes (both colours) from the owners' publications.
+        // g half-steps per exchange on the shrinking extended region of the
+        // workgroup's one slab, then the 2g ghost planes (both colours) from
+        // the owners' publications.
+        const SlabRunDev &run = run0;
+        const int r = p0.r, z0 = p0.z0, s = p0.s, E = s + 2 * g, zb = z0 - g;
+        unsigned long long *xb = run.xbuf + (size_t)r * xrep;
+        const uint32_t *tab = slab_select_tables;
         const uint32_t n_cycles = (n_half + (uint32_t)g - 1) / (uint32_t)g;
         uint32_t j_half = 0;
         for (uint32_t m = 0; m < n_cycles; ++m) {
@@ -440,11 +502,16 @@ __global__ __launch_bounds__(kSlabThreads) void slab_sweep_kernel(SlabLaunch a)
     }
 
     // the owned planes back to HBM
-    for (int i = tid; i < s * PL; i += kSlabThreads) {
-        const int e = g + i / PL, c0 = i % PL;
-        const size_t dst = (size_t)(z0 + i / PL) * PL + c0;
+    for (int pi = 0; pi < np; ++pi) {
+        const SlabPiece pc = pi ? p1 : p0;
+        const SlabRunDev &run = a.runs[pc.run];
+        for (int i = tid; i < pc.s * PL; i += kSlabThreads) {
+            const int e = pc.off + g + i / PL, c0 = i % PL;
+            const size_t dst = (size_t)(pc.z0 + i / PL) * PL + c0;
 #pragma unroll
-        for (int c = 0; c < 2; ++c) run.spins[((size_t)r * 2 + c) * plane + dst] = lspin[(c * EM + e) * PL + c0];
+            for (int c = 0; c < 2; ++c)
+                run.spins[((size_t)pc.r * 2 + c) * plane + dst] = lspin[(c * EM + e) * PL + c0];
+        }
     }
 }
 

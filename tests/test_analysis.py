@@ -89,6 +89,58 @@ def test_multifit_recovers_shared_exponents():
     assert np.allclose(fit["xi"], xis, rtol=0.05)
 
 
+def test_multifit_statistical_errors_match_the_scatter():
+    """The reported 1-sigma errors of alpha, beta and xi agree with the
+    scatter of the fitted values over independent noise realisations (to
+    within 35%: 60 realisations): weighted by relative errors, and
+    unweighted with homoscedastic noise (scaled by the residual variance)."""
+    alpha, beta = 0.5, 1.5
+    rng = np.random.default_rng(11)
+    cases = [(np.arange(0, 33, dtype=np.float64), np.array([2.5, 4.0]), "weighted"),
+             (np.arange(0, 13, dtype=np.float64), np.array([4.0, 6.0]), "unweighted")]
+    for r, xis, kind in cases:
+        amps = np.array([0.8, 0.7])
+        clean = np.array([an.c4_form(np.maximum(r, 1e-9), a, alpha, x, beta) for a, x in zip(amps, xis)])
+        sigma = 0.02 * clean + 1e-4 if kind == "weighted" else np.full_like(clean, 1e-4)
+        fits = [an.multifit_c4(r, clean + sigma * rng.standard_normal(clean.shape), r_min=3.0,
+                               errors=sigma if kind == "weighted" else None) for _ in range(60)]
+        for key in ("alpha", "beta"):
+            spread = np.std([f[key] for f in fits], ddof=1)
+            reported = np.mean([f[key + "_err"] for f in fits])
+            assert 0.65 < reported / spread < 1.35, (kind, key, reported, spread)
+        spread = np.std([f["xi"] for f in fits], axis=0, ddof=1)
+        reported = np.mean([f["xi_err"] for f in fits], axis=0)
+        assert np.all((0.65 < reported / spread) & (reported / spread < 1.35)), (kind, reported, spread)
+
+
+def test_multifit_error_axis_against_all_r():
+    """Sec. IV's error estimate: an isotropic C4 seen at the axis points and
+    at every shell distance gives the same fit (error ~0 without noise); with
+    noise the error is the difference of the two fits plus both statistical
+    errors."""
+    L = 32
+    r_axis = np.arange(0, L // 2 + 1, dtype=np.float64)
+    k = np.nonzero(an.shell_counts(L, (L // 2) ** 2 + 1))[0]
+    r_all = np.sqrt(k.astype(np.float64))
+    alpha, beta, xis, amps = 0.48, 1.45, np.array([2.0, 3.5]), np.array([0.9, 0.75])
+    f = lambda rr: np.array([an.c4_form(np.maximum(rr, 1e-9), a, alpha, x, beta) for a, x in zip(amps, xis)])
+    res = an.multifit_error(r_axis, f(r_axis), r_all, f(r_all))
+    assert res["alpha_err"] < 1e-4 and res["beta_err"] < 1e-4 and np.all(res["xi_err"] < 1e-3 * xis)
+    assert abs(res["axis"]["alpha"] - alpha) < 1e-4 and abs(res["all_r"]["beta"] - beta) < 1e-4
+    rng = np.random.default_rng(5)
+    ax = f(r_axis) * (1 + 0.02 * rng.standard_normal((2, r_axis.size)))
+    al = f(r_all) * (1 + 0.02 * rng.standard_normal((2, r_all.size)))
+    ea_, ee = 0.02 * f(r_axis) + 1e-6, 0.02 * f(r_all) + 1e-6
+    res = an.multifit_error(r_axis, ax, r_all, al, axis_errors=ea_, all_errors=ee)
+    a, b = res["axis"], res["all_r"]
+    assert res["alpha_err"] == pytest.approx(abs(a["alpha"] - b["alpha"]) + a["alpha_err"] + b["alpha_err"])
+    assert res["beta_err"] == pytest.approx(abs(a["beta"] - b["beta"]) + a["beta_err"] + b["beta_err"])
+    assert np.allclose(res["xi_err"], np.abs(a["xi"] - b["xi"]) + a["xi_err"] + b["xi_err"])
+    # the true values lie within the estimated errors
+    assert 0 < res["alpha_err"] and abs(a["alpha"] - alpha) <= res["alpha_err"]
+    assert abs(a["beta"] - beta) <= res["beta_err"] and np.all(np.abs(a["xi"] - xis) <= res["xi_err"])
+
+
 def test_growth_fits_recover_z_and_log_form():
     tw = np.logspace(1, 6, 25)
     xi = 1.7 * tw ** (1 / 10.5) - 0.8

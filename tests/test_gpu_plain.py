@@ -254,11 +254,12 @@ def test_c4_shells_match_oracle(ea_gpu, oracle_mod, L, rw):
         assert np.array_equal(g.c4_shells(n), o.c4_shells(n)), (L, n)
 
 
-@pytest.mark.parametrize("L", [64, 96, 128])
+@pytest.mark.parametrize("L", [64, 96, 128, 136, 256])
 def test_c4_shells_full_size(ea_gpu, L):
     """At full size (no oracle): equal to an FFT autocorrelation of the GPU's
     own q, and the shell identities (r = 0, unit shell = axis C4 at 1, sum of
-    every shell = Q^2)."""
+    every shell = Q^2).  L = 136 and 256 take the rows kernel of three and four
+    64-bit words per row."""
     g = ea_gpu.Sim(L, 0.3, 0.7, seed=1)
     g.sweep(50)
     _say(f"c4 shells full size L={L}")
@@ -309,9 +310,8 @@ def test_c4_shells_errors(ea_gpu):
     for n in (0, 3 * 64 + 2):
         with pytest.raises(ea_gpu.EAError):
             g.c4_shells(n)
-    big = ea_gpu.Sim(136, 0.5, 0.8, seed=1)
-    with pytest.raises(ea_gpu.EAError):
-        big.c4_shells(10)
+    big = ea_gpu.Sim(136, 0.5, 0.8, seed=1)  # beyond 128: the rows kernel
+    assert big.c4_shells(10)[0] == 136 ** 3
 
 
 def test_sweep_group_matches_oracle(ea_gpu, oracle_mod):

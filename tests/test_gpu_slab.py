@@ -231,3 +231,21 @@ def test_screened_slabs_match_oracle(ea_gpu, oracle_mod, T):
     _compare_state(g, o, f"screened slabs T={T}")
     _compare_obs(g.measure(), o.measure(), f"screened slabs T={T}")
     g.close()
+
+
+def test_group_shares_spanning_replicas(ea_gpu, oracle_mod):
+    """Three L = 64 runs of different p and T in one group: 384 planes on
+    at most 256 workgroups, so shares of one or two planes span the end of
+    one replica and the start of the next, sometimes of another run (with
+    its own select table); every run against the oracle."""
+    params = [(0.5, 0.5), (0.3, 0.9), (0.2, 1.3)]
+    sims = [ea_gpu.Sim(64, p, T, seed=17, sample=i, words_per_row=4) for i, (p, T) in enumerate(params)]
+    ea_gpu.sweep_group(sims, 1)
+    ea_gpu.sweep_group(sims, 4)
+    for i, ((p, T), s) in enumerate(zip(params, sims)):
+        o = oracle_mod.Sim(64, p, T, seed=17, sample=i)
+        o.sweep(5)
+        _compare_state(s, o, f"spanning group run {i} p={p} T={T}")
+        _compare_obs(s.measure(), o.measure(), f"spanning group run {i}")
+    for s in sims:
+        s.close()
