@@ -124,6 +124,30 @@ ea_status ea_footprint_ex(const ea_config *cfg, size_t *bytes);
 /* Acceptance thresholds of eq. (9): out[k-1] for dE = 4k, k = 1..3. */
 ea_status ea_thresholds(double T, uint32_t out[3]);
 
+/* Race and order debug mode.  Within a half-step of the checkerboard
+ * schedule (Sec. III, Fig. 1) the sites of one colour depend only on the
+ * other colour, so the result may not depend on which workgroup updates
+ * which part of the lattice, in what order, or on what LDS held before a
+ * kernel started; this mode changes all three so that a test can check that
+ * the bits stay the same.  flags (any combination; 0 = off, the default):
+ *   EA_DEBUG_REVERSE  workgroups take their tiles in reverse order: blocks
+ *                     of the half-step launches (plain, grouped, multispin),
+ *                     shares of the slab launches, units of the batched and
+ *                     serving launches (split pairs stay in front, so that
+ *                     they are still resident together);
+ *   EA_DEBUG_ROTATE   the same orders rotated by `seed` positions;
+ *   EA_DEBUG_POISON   the persistent kernels (slab, batched) fill their LDS
+ *                     with a pattern derived from `seed` before loading.
+ * Process-wide; it applies to launches made after the call, on any device
+ * (a graph captured before keeps the mode it was captured with; the plain
+ * form's own sweep graph is captured again).  Set it while no work of the
+ * library is in flight.  Results are bit-identical in every mode; the
+ * launches are as fast as the default ones up to the changed placement.
+ * EA_ERR_ARG for unknown flag bits. */
+enum { EA_DEBUG_REVERSE = 1, EA_DEBUG_ROTATE = 2, EA_DEBUG_POISON = 4 };
+ea_status ea_set_debug(uint32_t flags, uint32_t seed);
+ea_status ea_get_debug(uint32_t *flags, uint32_t *seed);
+
 /* Create a run and generate its couplings and initial spins on the device
  * (t = 0).  EA_ERR_ARG for L not a multiple of 8 or outside 8..256, p outside
  * [0,1] or NaN, T negative or not finite, n_tw_slots outside 0..64, or a

@@ -15,7 +15,8 @@ import numpy as np
 from . import abi
 from .abi import EAError
 
-__all__ = ["Sim", "Batch", "Server", "EAError", "thresholds", "footprint", "version", "tune", "sweep_group", "run_group", "Msc"]
+__all__ = ["Sim", "Batch", "Server", "EAError", "thresholds", "footprint", "version", "tune", "sweep_group", "run_group", "Msc",
+           "set_debug", "get_debug", "DEBUG_REVERSE", "DEBUG_ROTATE", "DEBUG_POISON"]
 
 
 def version() -> str:
@@ -26,6 +27,22 @@ def thresholds(T: float) -> np.ndarray:
     out = np.zeros(3, dtype=np.uint32)
     abi.check(abi.lib().ea_thresholds(float(T), abi.ptr(out, ctypes.c_uint32)))
     return out
+
+
+DEBUG_REVERSE, DEBUG_ROTATE, DEBUG_POISON = 1, 2, 4
+
+
+def set_debug(flags: int = 0, seed: int = 0) -> None:
+    """Race and order debug mode (ea_set_debug): reversed and/or rotated
+    workgroup order, LDS poisoned before the persistent kernels load; 0 = off.
+    Applies to launches made after the call."""
+    abi.check(abi.lib().ea_set_debug(int(flags), int(seed) & 0xFFFFFFFF))
+
+
+def get_debug() -> tuple:
+    f, s = ctypes.c_uint32(0), ctypes.c_uint32(0)
+    abi.check(abi.lib().ea_get_debug(ctypes.byref(f), ctypes.byref(s)))
+    return int(f.value), int(s.value)
 
 
 def footprint(L: int, n_tw: int = 0, words_per_row: int = 0) -> int:

@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <algorithm>
+#include <atomic>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -42,6 +43,43 @@ ea_status fail(ea_status st, const char *fmt, ...)
 
 constexpr int kMaxSlots = 64;
 constexpr int kMaxL = 256;
+
+// Race and order debug mode (ea_set_debug): read at every launch.
+std::atomic<uint32_t> g_debug_flags{0}, g_debug_seed{0};
+
+// Order word of the grid launches (ea::debug_block): bit 31 reverses, bits
+// 0..30 rotate; 0 = the default order.
+uint32_t debug_grid_order()
+{
+    const uint32_t f = g_debug_flags.load();
+    uint32_t o = 0;
+    if (f & EA_DEBUG_REVERSE) o |= 0x80000000u;
+    if (f & EA_DEBUG_ROTATE) o |= g_debug_seed.load() & 0x7fffffffu;
+    return o;
+}
+
+// LDS fill pattern of the persistent kernels (ea::debug_poison); 0 = off.
+uint32_t debug_poison_word()
+{
+    if (!(g_debug_flags.load() & EA_DEBUG_POISON)) return 0;
+    const uint32_t w = 0xA5C3E187u ^ (g_debug_seed.load() * 0x9E3779B9u);
+    return w ? w : 0xFFFFFFFFu;
+}
+
+// The same order on the host, for lists of units: position i of the list
+// run by workgroup i becomes position perm(i).
+template <class T>
+void debug_permute(T *v, size_t n)
+{
+    const uint32_t o = debug_grid_order();
+    if (o == 0 || n < 2) return;
+    std::vector<T> src(v, v + n);
+    for (size_t i = 0; i < n; ++i) {
+        size_t j = (o & 0x80000000u) ? n - 1 - i : i;
+        j = (j + (size_t)(o & 0x7fffffffu) % n) % n;
+        v[j] = src[i];
+    }
+}
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
@@ -234,6 +272,7 @@ struct ea_sim {
     // captured graph of kGraphSweeps sweeps (built on first use)
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    uint32_t graph_order = 0;  // debug order the graph was captured with
     // scratch of ea_c4_shells (allocated on first use)
     unsigned long long *c4_scratch = nullptr;
     // event ordering this run's stream with a group sweep (created on first use)
@@ -256,6 +295,7 @@ struct ea_sim {
         g.RW = lay.RW;
         g.rows = lay.rows;
         g.plane = lay.plane;
+        g.order = debug_grid_order();
         return g;
     }
 };
@@ -340,6 +380,7 @@ ea_status launch_sweeps(ea_sim *s, uint32_t n)
 // Capture kGraphSweeps sweeps followed by the counter advance.
 ea_status build_graph(ea_sim *s)
 {
+    s->graph_order = debug_grid_order();
     EA_HIP(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
     ea_status st = launch_sweeps(s, kGraphSweeps);
     hipLaunchKernelGGL(ea::advance_u32_kernel, dim3(1), dim3(64), 0, s->stream, s->t_dev, kGraphSweeps);
@@ -555,6 +596,8 @@ ea_status launch_slab(ea_sim *const *runs, int n, uint64_t sweeps, const SlabPla
         a.tables = tables;
         a.n_half = 2 * chunk;
         a.err = lead->err_dev;
+        a.order = debug_grid_order();
+        a.poison = debug_poison_word();
         const uint64_t n_cycles = (a.n_half + (uint64_t)plan.g - 1) / (uint64_t)plan.g;
         for (int i = 0; i < n; ++i) {
             ea_sim *m = runs[i];
@@ -703,6 +746,23 @@ ea_status ea_thresholds(double T, uint32_t out[3])
     return EA_OK;
 }
 
+ea_status ea_set_debug(uint32_t flags, uint32_t seed)
+{
+    const uint32_t known = EA_DEBUG_REVERSE | EA_DEBUG_ROTATE | EA_DEBUG_POISON;
+    if (flags & ~known) return fail(EA_ERR_ARG, "unknown debug flags 0x%x", flags & ~known);
+    g_debug_seed.store(seed);
+    g_debug_flags.store(flags);
+    return EA_OK;
+}
+
+ea_status ea_get_debug(uint32_t *flags, uint32_t *seed)
+{
+    if (!flags || !seed) return fail(EA_ERR_ARG, "NULL argument");
+    *flags = g_debug_flags.load();
+    *seed = g_debug_seed.load();
+    return EA_OK;
+}
+
 ea_status ea_create(int32_t L, double p, double T, uint64_t seed, ea_sim **out)
 {
     ea_config cfg{};
@@ -845,6 +905,13 @@ ea_status ea_sweep(ea_sim *s, uint64_t n)
     hipLaunchKernelGGL(ea::set_u32_kernel, dim3(1), dim3(64), 0, s->stream, s->t_dev, (uint32_t)s->t);
     uint64_t left = n;
     if (left >= kGraphSweeps) {
+        if (s->graph_exec && s->graph_order != debug_grid_order()) {
+            // captured under another debug order: capture again
+            (void)hipGraphExecDestroy(s->graph_exec);
+            (void)hipGraphDestroy(s->graph);
+            s->graph_exec = nullptr;
+            s->graph = nullptr;
+        }
         if (!s->graph_exec) {
             ea_status st = build_graph(s);
             if (st != EA_OK) return st;

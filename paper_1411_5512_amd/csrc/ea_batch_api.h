@@ -8,6 +8,7 @@
 #include <mutex>
 #include <numeric>
 #include <queue>
+#include <type_traits>
 
 namespace {
 
@@ -334,6 +335,30 @@ void order_units(const std::vector<BatchJobHost *> &jobs, const std::vector<uint
     for (int32_t j : order)
         for (int32_t r = 0; r < 2; ++r)
             for (int32_t k = 0; k < jobs[(size_t)j]->parts; ++k) units.push_back(ea::BatchUnit{j, r, 0u, 1, k});
+}
+
+// The debug order (ea_set_debug) of a unit list made by order_units: the
+// split pairs among themselves (each pair kept together, so that all of them
+// are still dispatched, and resident, first) and the whole replicas among
+// themselves.  jobs: indexed by BatchUnit::job.
+template <class JobRef>
+void debug_order_units(const JobRef *jobs, std::vector<ea::BatchUnit> &units)
+{
+    if (debug_grid_order() == 0) return;
+    auto parts = [&](const ea::BatchUnit &u) {
+        if constexpr (std::is_pointer<JobRef>::value) return jobs[u.job]->parts;
+        else return jobs[u.job].parts;
+    };
+    size_t n_split = 0;
+    while (n_split < units.size() && parts(units[n_split]) > 1) ++n_split;
+    std::vector<std::pair<ea::BatchUnit, ea::BatchUnit>> pairs;
+    for (size_t i = 0; i + 1 < n_split; i += 2) pairs.push_back({units[i], units[i + 1]});
+    debug_permute(pairs.data(), pairs.size());
+    for (size_t i = 0; i < pairs.size(); ++i) {
+        units[2 * i] = pairs[i].first;
+        units[2 * i + 1] = pairs[i].second;
+    }
+    debug_permute(units.data() + n_split, units.size() - n_split);
 }
 
 // Which jobs to split.  For each size threshold (none, 64, 56, 48) whose
@@ -868,10 +893,12 @@ ea_status ea_batch_run(ea_batch *b, uint64_t t_stop)
         any = any || u.t_stop > h.t_host || u.first;
     }
     if (!any) return EA_OK;
-    EA_HIP(hipMemcpyAsync(b->d_units, b->units.data(), sizeof(ea::BatchUnit) * b->units.size(),
+    std::vector<ea::BatchUnit> launch = b->units;
+    debug_order_units(b->jobs.data(), launch);
+    EA_HIP(hipMemcpyAsync(b->d_units, launch.data(), sizeof(ea::BatchUnit) * launch.size(),
                           hipMemcpyHostToDevice, b->stream));
-    hipLaunchKernelGGL(ea::batch_kernel, dim3((unsigned)b->units.size()), dim3(ea::kBatchThreads), b->lds_bytes,
-                       b->stream, b->d_jobs, b->d_units);
+    hipLaunchKernelGGL(ea::batch_kernel, dim3((unsigned)launch.size()), dim3(ea::kBatchThreads), b->lds_bytes,
+                       b->stream, b->d_jobs, b->d_units, debug_poison_word(), (int)(b->lds_bytes / 4));
     EA_HIP(hipGetLastError());
     for (auto &h : b->jobs) {
         h.t_host = std::max<uint64_t>(h.t_host, std::min<uint64_t>(t_stop, h.job.n_sweeps));
@@ -892,6 +919,7 @@ ea_status ea_batch_capture(ea_batch *b)
         u.t_stop = (uint32_t)b->jobs[(size_t)u.job].job.n_sweeps;
         u.first = 1;
     }
+    debug_order_units(b->jobs.data(), full);
     EA_HIP(hipMemcpyAsync(b->d_units_graph, full.data(), sizeof(ea::BatchUnit) * full.size(),
                           hipMemcpyHostToDevice, b->stream));
     EA_HIP(hipStreamSynchronize(b->stream));
@@ -899,7 +927,7 @@ ea_status ea_batch_capture(ea_batch *b)
     ea_status st = reset_batch_device(b);
     if (st == EA_OK)
         hipLaunchKernelGGL(ea::batch_kernel, dim3((unsigned)full.size()), dim3(ea::kBatchThreads), b->lds_bytes,
-                           b->stream, b->d_jobs, b->d_units_graph);
+                           b->stream, b->d_jobs, b->d_units_graph, debug_poison_word(), (int)(b->lds_bytes / 4));
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(b->stream, &graph);
     if (st != EA_OK) {

@@ -720,9 +720,17 @@ __device__ __forceinline__ void batch_dispatch_L(const BatchJobDev &J, int r, in
     }
 }
 
+// poison, lds_words: the debug LDS fill (debug_poison; poison = 0: off) of
+// the launch's dynamic LDS words and the select tables.
 __global__ __launch_bounds__(kBatchThreads) void batch_kernel(const BatchJobDev *__restrict__ jobs,
-                                                              const BatchUnit *__restrict__ units)
+                                                              const BatchUnit *__restrict__ units,
+                                                              uint32_t poison, int lds_words)
 {
+    if (poison) {
+        debug_poison(batch_lds, lds_words, poison, (int)threadIdx.x, kBatchThreads);
+        debug_poison(batch_select_tables, kSelectTableWords, poison, (int)threadIdx.x, kBatchThreads);
+        __syncthreads();
+    }
     const BatchUnit u = units[blockIdx.x];
     const BatchJobDev J = jobs[u.job];
     const bool first = u.first != 0;

@@ -131,6 +131,25 @@ __device__ __forceinline__ int xcd_block(int b, int n)
     return (n & 7) ? b : (b & 7) * (n >> 3) + (b >> 3);
 }
 
+// Debug order of a launch's workgroups (ea_set_debug).  order = 0 keeps
+// block b; otherwise bit 31 reverses the order and bits 0..30 rotate it.
+// Always a permutation of [0, n), so every tile is still taken exactly once.
+__device__ __forceinline__ int debug_block(int b, int n, uint32_t order)
+{
+    if (order == 0) return b;
+    if (order & 0x80000000u) b = n - 1 - b;
+    return (int)(((uint32_t)b + (order & 0x7fffffffu) % (uint32_t)n) % (uint32_t)n);
+}
+
+// Debug fill of LDS words [0, n) (ea_set_debug's poison; 0 = off), so that a
+// word read before the kernel wrote it shows up as a wrong result instead of
+// a stale value that happens to be right.  The caller synchronises after it.
+__device__ __forceinline__ void debug_poison(uint32_t *lds, int n, uint32_t poison, int tid, int nthreads)
+{
+    if (poison == 0) return;
+    for (int i = tid; i < n; i += nthreads) lds[i] = poison ^ (uint32_t)i * 0x01000193u;
+}
+
 __device__ __forceinline__ int wrap(int v, int L)
 {
     return v < 0 ? v + L : (v >= L ? v - L : v);

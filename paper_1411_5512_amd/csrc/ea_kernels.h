@@ -14,6 +14,7 @@ struct Geom {
     int RW;      // words per row
     int rows;    // L * L
     int plane;   // words per colour plane, rows * RW
+    uint32_t order = 0;  // debug order of the half-step launches' blocks (debug_block)
 };
 
 // Device pointers of one run.
@@ -189,7 +190,8 @@ __global__ __launch_bounds__(256) void half_step_kernel(Lattice lat, Geom g, int
                                                         uint32_t k0, uint32_t k1, uint32_t sample,
                                                         uint32_t thr1, uint32_t thr2, uint32_t thr3)
 {
-    const int tid = xcd_block((int)blockIdx.x, (int)gridDim.x) * (int)blockDim.x + (int)threadIdx.x;
+    const int blk = debug_block((int)blockIdx.x, (int)gridDim.x, g.order);
+    const int tid = xcd_block(blk, (int)gridDim.x) * (int)blockDim.x + (int)threadIdx.x;
     if (tid >= g.plane) return;
     half_step_word<W, SCREEN>(lat, g, half, *t_base + t_off, (int)blockIdx.y, tid, k0, k1, sample, thr1, thr2,
                               thr3);
@@ -213,7 +215,8 @@ struct GroupArgs {
 template <int W, bool SCREEN>
 __global__ __launch_bounds__(256) void group_half_step_kernel(GroupArgs a, Geom g, int half, uint32_t t_off)
 {
-    const int tid = xcd_block((int)blockIdx.x, (int)gridDim.x) * (int)blockDim.x + (int)threadIdx.x;
+    const int blk = debug_block((int)blockIdx.x, (int)gridDim.x, g.order);
+    const int tid = xcd_block(blk, (int)gridDim.x) * (int)blockDim.x + (int)threadIdx.x;
     if (tid >= g.plane) return;
     const GroupMember &M = a.m[blockIdx.z];
     half_step_word<W, SCREEN>(M.lat, g, half, *M.t_base + t_off, (int)blockIdx.y, tid, M.k0, M.k1, M.sample,

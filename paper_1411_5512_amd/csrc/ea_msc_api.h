@@ -29,6 +29,7 @@ struct ea_msc {
     std::vector<unsigned long long> host_meas;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    uint32_t graph_order = 0;  // debug order the graph was captured with
 };
 
 namespace {
@@ -94,7 +95,8 @@ ea_status msc_layout(const ea_msc_config *cfg, MscLayout &y)
 
 ea_status msc_half_step(ea_msc *s, int half, uint32_t t_off)
 {
-    const ea::MscGeom g = s->geom;
+    ea::MscGeom g = s->geom;
+    g.order = debug_grid_order();
     // two blocks (one per replica) per tile of 256 threads; grid.y = word set
     const dim3 grid(2 * blocks_for((size_t)g.q), (unsigned)s->G, 1);
     EA_DISPATCH_M(s->M, hipLaunchKernelGGL((ea::msc_half_step_kernel<MM>), grid, dim3(256), 0, s->stream, s->lat,
@@ -114,6 +116,7 @@ ea_status msc_sweeps(ea_msc *s, uint32_t n)
 
 ea_status msc_build_graph(ea_msc *s)
 {
+    s->graph_order = debug_grid_order();
     EA_HIP(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
     ea_status st = msc_sweeps(s, kGraphSweeps);
     hipLaunchKernelGGL(ea::advance_u32_kernel, dim3(1), dim3(64), 0, s->stream, s->t_dev, kGraphSweeps);
@@ -278,6 +281,13 @@ ea_status ea_msc_sweep(ea_msc *s, uint64_t n)
     hipLaunchKernelGGL(ea::set_u32_kernel, dim3(1), dim3(64), 0, s->stream, s->t_dev, (uint32_t)s->t);
     uint64_t left = n;
     if (left >= kGraphSweeps) {
+        if (s->graph_exec && s->graph_order != debug_grid_order()) {
+            // captured under another debug order: capture again
+            (void)hipGraphExecDestroy(s->graph_exec);
+            (void)hipGraphDestroy(s->graph);
+            s->graph_exec = nullptr;
+            s->graph = nullptr;
+        }
         if (!s->graph_exec) {
             ea_status st = msc_build_graph(s);
             if (st != EA_OK) return st;

@@ -35,6 +35,7 @@ struct MscGeom {
     int P;   // words per plane
     int q;   // threads per plane: four consecutive xh each
     Divider by_r4, by_l;  // divisions by R / 4 and by L
+    uint32_t order = 0;   // debug order of the half-step launch's blocks (debug_block)
 };
 
 struct MscLattice {
@@ -162,7 +163,7 @@ __global__ __launch_bounds__(256) void msc_half_step_kernel(MscLattice lat, MscG
                                                             uint32_t thr1, uint32_t thr2, uint32_t thr3)
 {
     constexpr int S = 32 / M;
-    const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int lb = xcd_block(debug_block((int)blockIdx.x, (int)gridDim.x, g.order), (int)gridDim.x);
     const int r = lb & 1;
     const int tid = (lb >> 1) * (int)blockDim.x + (int)threadIdx.x;
     if (tid >= g.q) return;

@@ -285,6 +285,7 @@ ea_status server_epoch(ea_server *s, int32_t *progressed)
         for (BatchJobHost *h : hs) lds = std::max(lds, (size_t)batch_lds_words(h->job.L, h->RW) * 4);
         std::vector<ea::BatchUnit> units;
         order_units(hs, bspan, units);
+        debug_order_units(hs.data(), units);
         for (auto &u : units) {
             const BatchJobHost &h = *hs[(size_t)u.job];
             u.t_stop = (uint32_t)(h.t_host + bspan[(size_t)u.job]);
@@ -296,7 +297,7 @@ ea_status server_epoch(ea_server *s, int32_t *progressed)
                               hipMemcpyHostToDevice, s->stream));
         EA_HIP(hipEventRecord(s->ev_batch[0], s->stream));
         hipLaunchKernelGGL(ea::batch_kernel, dim3((unsigned)units.size()), dim3(ea::kBatchThreads), lds, s->stream,
-                           s->d_jobs, s->d_units);
+                           s->d_jobs, s->d_units, debug_poison_word(), (int)(lds / 4));
         EA_HIP(hipGetLastError());
         EA_HIP(hipEventRecord(s->ev_batch[1], s->stream));
     }

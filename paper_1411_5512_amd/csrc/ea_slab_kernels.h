@@ -66,6 +66,8 @@ struct SlabLaunch {
     int32_t tables;      // 2: a workgroup's second piece (another run) has its own select table
     uint32_t n_half;     // half-steps in this launch (the first is half 0 of sweep t0)
     uint32_t *err;       // set when a wait timed out; every workgroup then ends
+    uint32_t order;      // debug order of the shares (debug_block); 0 = workgroup b takes share b
+    uint32_t poison;     // debug LDS fill before the loads (debug_poison); 0 = off
 };
 
 // One piece of a workgroup's share: owned planes [z0, z0 + s) of replica r
@@ -283,7 +285,7 @@ __global__ __launch_bounds__(kSlabThreads) void slab_sweep_kernel(SlabLaunch a)
     const int L = a.L, RW = a.RW, PL = L * RW, R = L / 2;
     const int g = a.g, EM = a.emax;
     SlabPiece p0, p1;
-    const int np = slab_pieces(a, (int)blockIdx.x, p0, p1);
+    const int np = slab_pieces(a, debug_block((int)blockIdx.x, (int)gridDim.x, a.order), p0, p1);
     // LDS: [colour][EM][PL] spins, [direction][colour][EM][PL] couplings,
     // 16 flag words, then (tables = 2) the second piece's select table
     uint32_t *lspin = slab_lds;
@@ -302,6 +304,12 @@ __global__ __launch_bounds__(kSlabThreads) void slab_sweep_kernel(SlabLaunch a)
     const int qym = (y == 0 ? L - 1 : y - 1) * RW + w;
     const int qyp = (y == L - 1 ? 0 : y + 1) * RW + w;
 
+    if (a.poison) {
+        debug_poison(slab_lds, 8 * EM * PL + 16 + (a.tables == 2 ? kSelectTableWords : 0), a.poison, tid,
+                     kSlabThreads);
+        debug_poison(slab_select_tables, kSelectTableWords, a.poison, tid, kSlabThreads);
+        __syncthreads();
+    }
     if (tid == 0) {
         flag[0] = slab_err_seen(a.err);
         flag[1] = 0;

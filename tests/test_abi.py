@@ -96,3 +96,22 @@ def test_msc_footprint_and_bad_arguments(ealib):
             ea.Msc.footprint(L, B)
     with pytest.raises(ea.EAError):
         ea.Msc.footprint(16, 32, 65)
+
+
+def test_debug_mode_flags(ealib):
+    """ea_set_debug / ea_get_debug: any combination of the three flags with a
+    seed is kept process-wide; unknown bits are rejected and leave the mode
+    unchanged; 0 switches it off (host only: no launch)."""
+    import paper_1411_5512_amd as ea
+    try:
+        assert ea.get_debug() == (0, 0)
+        ea.set_debug(ea.DEBUG_REVERSE | ea.DEBUG_POISON, 0xDEADBEEF)
+        assert ea.get_debug() == (5, 0xDEADBEEF)
+        with pytest.raises(ea.EAError):
+            ea.set_debug(8, 1)
+        assert ea.get_debug() == (5, 0xDEADBEEF)
+        ea.set_debug(ea.DEBUG_ROTATE, 3)
+        assert ea.get_debug() == (2, 3)
+    finally:
+        ea.set_debug(0, 0)
+    assert ea.get_debug() == (0, 0)
