@@ -56,16 +56,41 @@ __device__ __forceinline__ Words4 philox10(uint32_t x0, uint32_t x1, uint32_t x2
     return r;
 }
 
-// Two blocks whose counters differ only in word 1, computed round by round
-// side by side: the two dependency chains interleave, so each round's
-// multiplies of one block issue while the other's are in flight.
-__device__ __forceinline__ void philox10_pair(uint32_t x0, uint32_t x1a, uint32_t x1b, uint32_t x2, uint32_t x3,
-                                              uint32_t k0, uint32_t k1, Words4 &a, Words4 &b)
+// Counter word 1 of block J of a packed word of W sites is quad0 + J, where
+// quad0 (the word's first 4-site block) is a multiple of W/4: rows and words
+// hold whole numbers of blocks.  For W/4 a power of two the sum has no carry
+// and equals quad0 | J, which the first round folds into its XOR.
+template <int W>
+constexpr bool kQuadOr = ((W / 4) & (W / 4 - 1)) == 0;
+
+constexpr int kBitopOrXor = 0x56;  // (src0 | src1) ^ src2, bitwise
+
+// Two blocks whose counters differ only in word 1 (quad0 + Ja, quad0 + Jb),
+// computed round by round side by side: the two dependency chains
+// interleave, so each round's multiplies of one block issue while the
+// other's are in flight.  In the first round words 0, 2, 3 and the key are
+// uniform across the wavefront, so only the word-1 XOR is per lane.
+template <bool ORQ>
+__device__ __forceinline__ void philox10_pair(uint32_t x0, uint32_t quad0, uint32_t Ja, uint32_t Jb, uint32_t x2,
+                                              uint32_t x3, uint32_t k0, uint32_t k1, Words4 &a, Words4 &b)
 {
-    uint32_t a0 = x0, a1 = x1a, a2 = x2, a3 = x3;
-    uint32_t b0 = x0, b1 = x1b, b2 = x2, b3 = x3;
+    const uint64_t n0 = (uint64_t)x0 * 0xD2511F53u;
+    const uint64_t n2 = (uint64_t)x2 * 0xCD9E8D57u;
+    const uint32_t h = (uint32_t)(n2 >> 32) ^ k0;
+    uint32_t a0, b0;
+    if constexpr (ORQ) {
+        a0 = __builtin_amdgcn_bitop3_b32(quad0, Ja, h, kBitopOrXor);
+        b0 = __builtin_amdgcn_bitop3_b32(quad0, Jb, h, kBitopOrXor);
+    } else {
+        a0 = (quad0 + Ja) ^ h;
+        b0 = (quad0 + Jb) ^ h;
+    }
+    uint32_t a1 = (uint32_t)n2, a2 = xor3((uint32_t)(n0 >> 32), x3, k1), a3 = (uint32_t)n0;
+    uint32_t b1 = a1, b2 = a2, b3 = a3;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
 #pragma unroll
-    for (int round = 0; round < 10; ++round) {
+    for (int round = 1; round < 10; ++round) {
         const uint64_t ma0 = (uint64_t)a0 * 0xD2511F53u, mb0 = (uint64_t)b0 * 0xD2511F53u;
         const uint64_t ma2 = (uint64_t)a2 * 0xCD9E8D57u, mb2 = (uint64_t)b2 * 0xCD9E8D57u;
         const uint32_t ya0 = xor3((uint32_t)(ma2 >> 32), a1, k0), yb0 = xor3((uint32_t)(mb2 >> 32), b1, k0);
@@ -243,7 +268,7 @@ __device__ __forceinline__ uint32_t site_threshold(const Decision &d, uint32_t t
 // Blocks J = W/4-1 down to 0: block J covers sites 4J..4J+3 and has counter
 // word 1 equal to quad0 + J; words 0, 2, 3 (sweep, tag/colour/replica,
 // sample) are wave-uniform, so the first rounds run largely on the SALU.
-template <int J>
+template <int W, int J>
 __device__ __forceinline__ uint32_t accept_blocks(uint32_t accept, const Decision &d, uint32_t c0,
                                                   uint32_t quad0, uint32_t c2, uint32_t c3, uint32_t k0,
                                                   uint32_t k1, uint32_t thr1, uint32_t thr2, uint32_t thr3)
@@ -251,7 +276,7 @@ __device__ __forceinline__ uint32_t accept_blocks(uint32_t accept, const Decisio
     if constexpr (J > 0) {
         // blocks J and J - 1 side by side
         Words4 u, v;
-        philox10_pair(c0, quad0 + (uint32_t)J, quad0 + (uint32_t)(J - 1), c2, c3, k0, k1, u, v);
+        philox10_pair<kQuadOr<W>>(c0, quad0, (uint32_t)J, (uint32_t)(J - 1), c2, c3, k0, k1, u, v);
         accept = append_below4(accept, u.v[3], site_threshold<4 * J + 3>(d, thr1, thr2, thr3), u.v[2],
                                site_threshold<4 * J + 2>(d, thr1, thr2, thr3), u.v[1],
                                site_threshold<4 * J + 1>(d, thr1, thr2, thr3), u.v[0],
@@ -261,7 +286,7 @@ __device__ __forceinline__ uint32_t accept_blocks(uint32_t accept, const Decisio
                                site_threshold<4 * J - 3>(d, thr1, thr2, thr3), v.v[0],
                                site_threshold<4 * J - 4>(d, thr1, thr2, thr3));
         if constexpr (J > 1)
-            return accept_blocks<J - 2>(accept, d, c0, quad0, c2, c3, k0, k1, thr1, thr2, thr3);
+            return accept_blocks<W, J - 2>(accept, d, c0, quad0, c2, c3, k0, k1, thr1, thr2, thr3);
         else
             return accept;
     } else {
@@ -278,7 +303,7 @@ __device__ __forceinline__ uint32_t flip_mask(const Decision &d, uint32_t c0, ui
                                               uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,
                                               uint32_t thr1, uint32_t thr2, uint32_t thr3)
 {
-    return d.always | accept_blocks<W / 4 - 1>(0u, d, c0, quad0, c2, c3, k0, k1, thr1, thr2, thr3);
+    return d.always | accept_blocks<W, W / 4 - 1>(0u, d, c0, quad0, c2, c3, k0, k1, thr1, thr2, thr3);
 }
 
 // The same flip mask in two steps, for kernels that wait on global loads:
@@ -290,7 +315,7 @@ __device__ __forceinline__ void random_words(uint32_t c0, uint32_t quad0, uint32
 {
     if constexpr (J > 0) {
         Words4 a, b;
-        philox10_pair(c0, quad0 + (uint32_t)J, quad0 + (uint32_t)(J - 1), c2, c3, k0, k1, a, b);
+        philox10_pair<kQuadOr<W>>(c0, quad0, (uint32_t)J, (uint32_t)(J - 1), c2, c3, k0, k1, a, b);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             u[4 * J + i] = a.v[i];
@@ -319,37 +344,49 @@ __device__ __forceinline__ uint32_t accept_words(uint32_t accept, const Decision
 }
 
 // ---------------------------------------------------------------------------
-// Threshold select through LDS tables, four sites per read.  A 4-site block
-// q = 0..3 has class bits any_q (n >= 2) and odd_q (n odd); the 8-bit index
-// any_nibble | odd_nibble << 4 selects a 16-byte entry holding the four
-// thresholds (any -> thr1, else odd -> thr2, else thr3; a site with n >= 3
-// is covered by the "always" mask, its entry is 0).  Two 256-entry spread
-// tables turn a byte of each class mask (two blocks) into both blocks' entry
-// byte offsets, in the low and high 16 bits of one word: per 8 sites two
-// table reads, an OR, two extracts and two 16-byte reads.
+// Threshold select through an LDS table, four sites per read.  A 4-site
+// block has class bits any (n >= 2) and odd (n odd) for its four sites; the
+// byte any_nibble | odd_nibble << 4 indexes a 256-entry table of 16-byte
+// entries holding the block's four thresholds (any -> thr1, else odd ->
+// thr2, else thr3; a site with n >= 3 is covered by the "always" mask, its
+// entry is 0).  The index bytes of all blocks of a word come from two
+// interleaves of the class masks: lo = (any & 0x0F0F0F0F) | (odd << 4 &
+// 0xF0F0F0F0) holds those of blocks 0, 2, 4, 6, hi = (any >> 4 & 0x0F0F0F0F)
+// | (odd & 0xF0F0F0F0) those of blocks 1, 3, 5, 7, so an entry's byte offset
+// is one byte extract and shift: per 8 sites one interleave op, two extracts
+// and two 16-byte reads.
 //
-// Layout (words): [0, 1024) the quad table, [1024, 1280) the "any" spread
-// table, [1280, 1536) the "odd" spread table.
+// Layout (words): entry e at [4e, 4e + 4).
 
-constexpr int kSelectQuadWords = 4 * 256;
-constexpr int kSelectTableWords = kSelectQuadWords + 2 * 256;
+constexpr int kSelectTableWords = 4 * 256;
 
-// Fill the tables (any thread count; caller synchronises before use).
+// Fill the table (any thread count; caller synchronises before use).
 __device__ __forceinline__ void fill_select_tables(uint32_t *tab, uint32_t thr1, uint32_t thr2, uint32_t thr3,
                                                    int tid, int nthreads)
 {
     for (int i = tid; i < kSelectTableWords; i += nthreads) {
-        uint32_t v;
-        if (i < kSelectQuadWords) {
-            const int idx = i >> 2, q = i & 3;
-            const int any = (idx >> q) & 1, odd = (idx >> (4 + q)) & 1;
-            v = any ? (odd ? 0u : thr1) : (odd ? thr2 : thr3);
-        } else {
-            const int b = (i - kSelectQuadWords) & 255;
-            const int shift = i < kSelectQuadWords + 256 ? 4 : 8;  // any: bits 4..7, odd: bits 8..11
-            v = ((uint32_t)(b & 15) << shift) | ((uint32_t)(b >> 4) << (16 + shift));
-        }
-        tab[i] = v;
+        const int idx = i >> 2, q = i & 3;
+        const int any = (idx >> q) & 1, odd = (idx >> (4 + q)) & 1;
+        tab[i] = any ? (odd ? 0u : thr1) : (odd ? thr2 : thr3);
+    }
+}
+
+// The W thresholds of one word from the table (16-byte aligned).
+template <int W>
+__device__ __forceinline__ void select_thresholds(const Decision &d, const uint32_t *tab, uint32_t (&thr)[W])
+{
+    const uint32_t nib = 0x0F0F0F0Fu;
+    const uint32_t lo = __builtin_amdgcn_bitop3_b32(nib, d.any, d.odd << 4, kBitopSelect);
+    const uint32_t hi = __builtin_amdgcn_bitop3_b32(nib, d.any >> 4, d.odd, kBitopSelect);
+#pragma unroll
+    for (int g = 0; g < W / 4; ++g) {
+        const uint32_t src = (g & 1) ? hi : lo;
+        const uint32_t byte_off = ((src >> (8 * (g >> 1))) & 0xffu) << 4;
+        const uint4 q = *(const uint4 *)((const char *)tab + byte_off);
+        thr[4 * g + 0] = q.x;
+        thr[4 * g + 1] = q.y;
+        thr[4 * g + 2] = q.z;
+        thr[4 * g + 3] = q.w;
     }
 }
 
@@ -361,7 +398,7 @@ __device__ __forceinline__ uint32_t accept_blocks_lds(uint32_t accept, const uin
     if constexpr (J > 0) {
         // blocks J and J - 1 side by side
         Words4 u, v;
-        philox10_pair(c0, quad0 + (uint32_t)J, quad0 + (uint32_t)(J - 1), c2, c3, k0, k1, u, v);
+        philox10_pair<kQuadOr<W>>(c0, quad0, (uint32_t)J, (uint32_t)(J - 1), c2, c3, k0, k1, u, v);
         accept = append_below4(accept, u.v[3], thr[4 * J + 3], u.v[2], thr[4 * J + 2], u.v[1], thr[4 * J + 1],
                                u.v[0], thr[4 * J]);
         accept = append_below4(accept, v.v[3], thr[4 * J - 1], v.v[2], thr[4 * J - 2], v.v[1], thr[4 * J - 3],
@@ -376,7 +413,7 @@ __device__ __forceinline__ uint32_t accept_blocks_lds(uint32_t accept, const uin
     }
 }
 
-// Flip mask of one packed word of W sites, thresholds from the LDS tables
+// Flip mask of one packed word of W sites, thresholds from the LDS table
 // (tab = kSelectTableWords words filled by fill_select_tables, 16-byte
 // aligned).  All W thresholds are read before the random words are
 // computed, so the LDS latency overlaps the Philox rounds.
@@ -384,26 +421,8 @@ template <int W>
 __device__ __forceinline__ uint32_t flip_mask_lds(const Decision &d, uint32_t c0, uint32_t quad0, uint32_t c2,
                                                   uint32_t c3, uint32_t k0, uint32_t k1, const uint32_t *tab)
 {
-    const uint32_t *spread_any = tab + kSelectQuadWords;
-    const uint32_t *spread_odd = tab + kSelectQuadWords + 256;
     uint32_t thr[W];
-#pragma unroll
-    for (int j = 0; j < (W + 7) / 8; ++j) {
-        const uint32_t off = spread_any[__builtin_amdgcn_ubfe(d.any, 8 * j, 8)] |
-                             spread_odd[__builtin_amdgcn_ubfe(d.odd, 8 * j, 8)];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int g = 2 * j + h;  // 4-site block
-            if (g < W / 4) {
-                const uint32_t byte_off = h ? off >> 16 : off & 0xffffu;
-                const uint4 q = *(const uint4 *)((const char *)tab + byte_off);
-                thr[4 * g + 0] = q.x;
-                thr[4 * g + 1] = q.y;
-                thr[4 * g + 2] = q.z;
-                thr[4 * g + 3] = q.w;
-            }
-        }
-    }
+    select_thresholds<W>(d, tab, thr);
     return d.always | accept_blocks_lds<W / 4 - 1, W>(0u, thr, c0, quad0, c2, c3, k0, k1);
 }
 

@@ -131,31 +131,13 @@ __device__ __forceinline__ uint32_t below_each(uint32_t accept, const uint32_t (
 }
 
 // The general acceptance of a word with thresholds from the LDS select
-// tables (fill_select_tables): four sites per 16-byte read, as in
+// table (fill_select_tables): four sites per 16-byte read, as in
 // flip_mask_lds, but with the random words already drawn.
 template <int W>
 __device__ __forceinline__ uint32_t accept_words_tab(const Decision &d, const uint32_t (&u)[W], const uint32_t *tab)
 {
-    const uint32_t *spread_any = tab + kSelectQuadWords;
-    const uint32_t *spread_odd = tab + kSelectQuadWords + 256;
     uint32_t thr[W];
-#pragma unroll
-    for (int j = 0; j < (W + 7) / 8; ++j) {
-        const uint32_t off = spread_any[__builtin_amdgcn_ubfe(d.any, 8 * j, 8)] |
-                             spread_odd[__builtin_amdgcn_ubfe(d.odd, 8 * j, 8)];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int gq = 2 * j + h;  // 4-site block
-            if (gq < W / 4) {
-                const uint32_t byte_off = h ? off >> 16 : off & 0xffffu;
-                const uint4 q4 = *(const uint4 *)((const char *)tab + byte_off);
-                thr[4 * gq + 0] = q4.x;
-                thr[4 * gq + 1] = q4.y;
-                thr[4 * gq + 2] = q4.z;
-                thr[4 * gq + 3] = q4.w;
-            }
-        }
-    }
+    select_thresholds<W>(d, tab, thr);
     return below_each<W / 4 - 1, W>(0u, u, thr);
 }
 
