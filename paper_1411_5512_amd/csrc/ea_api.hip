@@ -440,18 +440,18 @@ std::mutex g_slab_mu;
 int g_slab_cus = 0, g_slab_lds_limit = 0;
 bool g_slab_attr[33] = {};
 
-template <bool SCREEN>
+template <bool SCREEN, bool SPAN>
 const void *slab_kernel_fn(int W)
 {
     switch (W) {
-    case 4: return (const void *)ea::slab_sweep_kernel<4, SCREEN>;
-    case 8: return (const void *)ea::slab_sweep_kernel<8, SCREEN>;
-    case 12: return (const void *)ea::slab_sweep_kernel<12, SCREEN>;
-    case 16: return (const void *)ea::slab_sweep_kernel<16, SCREEN>;
-    case 20: return (const void *)ea::slab_sweep_kernel<20, SCREEN>;
-    case 24: return (const void *)ea::slab_sweep_kernel<24, SCREEN>;
-    case 28: return (const void *)ea::slab_sweep_kernel<28, SCREEN>;
-    default: return (const void *)ea::slab_sweep_kernel<32, SCREEN>;
+    case 4: return (const void *)ea::slab_sweep_kernel<4, SCREEN, SPAN>;
+    case 8: return (const void *)ea::slab_sweep_kernel<8, SCREEN, SPAN>;
+    case 12: return (const void *)ea::slab_sweep_kernel<12, SCREEN, SPAN>;
+    case 16: return (const void *)ea::slab_sweep_kernel<16, SCREEN, SPAN>;
+    case 20: return (const void *)ea::slab_sweep_kernel<20, SCREEN, SPAN>;
+    case 24: return (const void *)ea::slab_sweep_kernel<24, SCREEN, SPAN>;
+    case 28: return (const void *)ea::slab_sweep_kernel<28, SCREEN, SPAN>;
+    default: return (const void *)ea::slab_sweep_kernel<32, SCREEN, SPAN>;
     }
 }
 
@@ -470,10 +470,10 @@ ea_status slab_device(int W, int *n_cu, int *lds_limit)
     }
     if (W < 4 || W > 32 || W % 4) return fail(EA_ERR_STATE, "unsupported word width %d", W);
     if (!g_slab_attr[W]) {
-        EA_HIP(hipFuncSetAttribute(slab_kernel_fn<false>(W), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   g_slab_lds_limit));
-        EA_HIP(hipFuncSetAttribute(slab_kernel_fn<true>(W), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   g_slab_lds_limit));
+        const void *fns[4] = {slab_kernel_fn<false, false>(W), slab_kernel_fn<true, false>(W),
+                              slab_kernel_fn<false, true>(W), slab_kernel_fn<true, true>(W)};
+        for (const void *fn : fns)
+            EA_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, g_slab_lds_limit));
         g_slab_attr[W] = true;
     }
     *n_cu = g_slab_cus;
@@ -573,11 +573,13 @@ ea_status launch_slab(ea_sim *const *runs, int n, uint64_t sweeps, const SlabPla
     // a second select table when some workgroup's two pieces belong to runs
     // of different temperature
     int tables = 1;
+    bool span = false;  // some share holds two pieces: the two-piece instantiation
     for (int b = 0; b < plan.B; ++b) {
         const long P = 2L * n * y.L;
         const int start = (int)((long)b * P / plan.B), end = (int)((long)(b + 1) * P / plan.B);
         const int q0 = start / y.L;
         if (end > (q0 + 1) * y.L) {
+            span = true;
             const ea_sim *u = runs[q0 / 2], *v = runs[(q0 + 1) / 2];
             if (u->thr[0] != v->thr[0] || u->thr[1] != v->thr[1] || u->thr[2] != v->thr[2]) tables = 2;
         }
@@ -623,12 +625,19 @@ ea_status launch_slab(ea_sim *const *runs, int n, uint64_t sweeps, const SlabPla
         }
         const dim3 grid((unsigned)plan.B);
         // the screen pays where every workgroup gives each SIMD four waves of work
-        if ((long)(a.P / plan.B) * y.L * y.RW >= ea::kSlabThreads) {
-            EA_DISPATCH_W(y.W, hipLaunchKernelGGL((ea::slab_sweep_kernel<WW, true>), grid, dim3(ea::kSlabThreads),
-                                                  lds, lead->stream, a));
+        const bool screen = (long)(a.P / plan.B) * y.L * y.RW >= ea::kSlabThreads;
+        if (screen && span) {
+            EA_DISPATCH_W(y.W, hipLaunchKernelGGL((ea::slab_sweep_kernel<WW, true, true>), grid,
+                                                  dim3(ea::kSlabThreads), lds, lead->stream, a));
+        } else if (screen) {
+            EA_DISPATCH_W(y.W, hipLaunchKernelGGL((ea::slab_sweep_kernel<WW, true, false>), grid,
+                                                  dim3(ea::kSlabThreads), lds, lead->stream, a));
+        } else if (span) {
+            EA_DISPATCH_W(y.W, hipLaunchKernelGGL((ea::slab_sweep_kernel<WW, false, true>), grid,
+                                                  dim3(ea::kSlabThreads), lds, lead->stream, a));
         } else {
-            EA_DISPATCH_W(y.W, hipLaunchKernelGGL((ea::slab_sweep_kernel<WW, false>), grid, dim3(ea::kSlabThreads),
-                                                  lds, lead->stream, a));
+            EA_DISPATCH_W(y.W, hipLaunchKernelGGL((ea::slab_sweep_kernel<WW, false, false>), grid,
+                                                  dim3(ea::kSlabThreads), lds, lead->stream, a));
         }
         EA_HIP(hipGetLastError());
         done += chunk;

@@ -260,8 +260,10 @@ __shared__ __align__(16) uint32_t slab_select_tables[kSelectTableWords];
 // SCREEN: launches whose slabs give every SIMD four or more waves of work
 // per half-step screen the rare uphill moves (accept_slab); smaller ones are
 // bound by one wave's chain of dependent instructions, which the screen
-// lengthens.
-template <int W, bool SCREEN>
+// lengthens.  SPAN: some workgroup's share spans two replicas (two pieces);
+// launches of whole slabs take the one-piece instantiation, whose constants
+// all stay in scalar registers across the half-steps.
+template <int W, bool SCREEN, bool SPAN>
 __global__ __launch_bounds__(kSlabThreads) void slab_sweep_kernel(SlabLaunch a)
 {
     const int L = a.L, RW = a.RW, PL = L * RW, R = L / 2;
@@ -298,7 +300,7 @@ __global__ __launch_bounds__(kSlabThreads) void slab_sweep_kernel(SlabLaunch a)
     }
     __syncthreads();
     if (flag[0]) return;
-    if (g > 1 && np > 1) {  // the host plans ghost depths above 1 with whole slabs only
+    if (np > 1 && (g > 1 || !SPAN)) {  // the host plans two-piece shares for SPAN launches at depth 1 only
         if (tid == 0) __hip_atomic_store(a.err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return;
     }
@@ -346,7 +348,9 @@ __global__ __launch_bounds__(kSlabThreads) void slab_sweep_kernel(SlabLaunch a)
             // the pieces one after the other, each with its constants uniform
             // across the workgroup; a thread's items continue its stride
             // (items zoff, zoff + zstep, ... over both pieces' planes)
-            for (int pi = 0; pi < np; ++pi) {
+#pragma unroll
+            for (int pi = 0; pi < (SPAN ? 2 : 1); ++pi) {
+                if (pi >= np) break;
                 const SlabPiece pc = pi ? p1 : p0;
                 const SlabRunDev &run = pi ? run1 : run0;
                 const uint32_t *tab = pi ? tab_1 : slab_select_tables;
