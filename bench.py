@@ -28,6 +28,14 @@ import os
 import sys
 import time
 
+# The serving leg drives its streamed jobs from four workers, each with its own
+# stream, beside the batched launch's stream; HIP maps streams onto the
+# process's hardware queues in turn (4 by default), and persistent launches
+# that share a queue run one after the other.  Eight queues let all five run
+# at once; set before anything initialises HIP (the library reads the same
+# variable to size its workers).
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)

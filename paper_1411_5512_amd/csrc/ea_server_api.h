@@ -15,13 +15,20 @@
 // the dynamics never depend on how the sweeps are split or what else runs.
 //
 // Lattices too large for one workgroup's LDS (L > 64) are "streamed" jobs:
-// each is a plain-form simulation placed in its pool region with a stream of
-// its own, advanced in the epoch by slab launches (ea_set_slab_plan) from up
-// to kStreamWorkers host threads at once, after the epoch's batched launch
-// (persistent slab workgroups beside a batched launch would wait for its
-// compute units while holding their own).  A streamed job's span is sized by
-// time (its own measured seconds per sweep), so that the streamed work of an
-// epoch takes about as long as the previous epoch's batched launch.
+// each is a plain-form simulation placed in its pool region, advanced in the
+// epoch by slab launches (ea_set_slab_plan) from up to kStreamWorkers host
+// threads at once, beside the epoch's batched launch on the compute units it
+// leaves free (each epoch's slab plans are sized to them), or after it when
+// it leaves fewer than a quarter (persistent slab workgroups beside a
+// batched launch that fills the device would wait for its compute units
+// while holding their own).  Each worker owns one stream, and a streamed job runs
+// on the stream of the worker it was given at admission (the one with the
+// least remaining work): streams share the process's hardware queues in
+// turn, and two persistent launches on one queue run one after the other,
+// so the workers are as many as the queues left beside the batched stream's
+// (GPU_MAX_HW_QUEUES, 4 by default) allow.  A streamed job's span is sized
+// by time (its own measured seconds per sweep), so that the streamed work of
+// an epoch takes about as long as the previous epoch's batched launch.
 #pragma once
 
 #include <algorithm>
@@ -38,7 +45,20 @@ namespace {
 
 using steady = std::chrono::steady_clock;
 
-constexpr int kStreamWorkers = 4;  // host threads that drive streamed jobs in an epoch
+constexpr int kStreamWorkers = 4;  // at most this many host threads drive streamed jobs
+
+// Workers that can run their persistent launches at the same time: the
+// process's hardware queues (HIP's GPU_MAX_HW_QUEUES, 4 unless set) less the
+// one the batched stream takes, at least 1 and at most kStreamWorkers.
+int server_stream_workers()
+{
+    int queues = 4;
+    if (const char *e = std::getenv("GPU_MAX_HW_QUEUES")) {
+        const int v = std::atoi(e);
+        if (v > 0) queues = v;
+    }
+    return std::max(1, std::min(kStreamWorkers, queues - 1));
+}
 
 // First-fit allocator over one device buffer (offsets, 256-byte granules).
 struct DevicePool {
@@ -97,7 +117,9 @@ struct ServerJob {
     size_t pool_off = 0;
     steady::time_point t_submit, t_done;
     std::vector<unsigned long long> results;  // [n_meas][obs_stride] after completion
-    bool streamed = false;                     // L > 64: plain-form kernels on a stream of its own
+    bool streamed = false;                     // L > 64: plain-form kernels on a worker's stream
+    int worker = 0;                            // that worker (its stream)
+    int plan_K = 0;                            // its slab plan's slabs per replica (-1: half-step launches)
     ea_sim *sim = nullptr;                     // its simulation, in the pool region
     int next_meas = 0, next_tw = 0;            // schedule positions of a streamed job
     double sweep_s = 0.0;                      // measured seconds per sweep of a streamed job
@@ -117,6 +139,8 @@ struct ea_server {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    std::vector<hipStream_t> wstreams;  // one per streamed-job worker
+    int n_cu = 0;                       // compute units of the device
     hipEvent_t ev_batch[2] = {nullptr, nullptr};  // around each batched launch
     double last_batch_s = 0.0;                    // duration of the last batched launch
     char *pool_buf = nullptr;
@@ -198,20 +222,21 @@ ea_status server_advance_streamed(ServerJob &j, uint64_t t_stop)
     return EA_OK;
 }
 
-// Streamed jobs run as slab launches (ea_set_slab_plan) from up to
-// kStreamWorkers threads at once, beside the batched launch: each job's plan
-// uses at most 1/kStreamWorkers of the compute units, so that the slab
-// launches in flight always fit the device together once the batched launch
-// has drained; a lattice whose slabs would not fit LDS at that share uses
-// one launch per half-step.
-ea_status server_slab_plan(ea_sim *sim)
+// Streamed jobs run as slab launches (ea_set_slab_plan) from the workers'
+// threads at once: each job's plan uses at most `share` compute units (two
+// workgroups of one CU per slab), so that the slab launches in flight fit
+// the CUs they are given together; a lattice whose slabs would not fit LDS
+// at that share uses one launch per half-step (no co-residency needed).
+void server_slab_plan(ServerJob &j, int share)
 {
-    int dev = 0, n_cu = 0;
-    EA_HIP(hipGetDevice(&dev));
-    EA_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-    const int K = std::max(1, n_cu / (2 * kStreamWorkers));
-    if (ea_set_slab_plan(sim, K, 0) == EA_OK) return EA_OK;
-    return ea_set_slab_plan(sim, -1, 0);
+    const int K = std::min(std::max(1, share / 2), j.h.job.L);
+    if (K == j.plan_K) return;
+    if (ea_set_slab_plan(j.sim, K, 0) == EA_OK) {
+        j.plan_K = K;
+    } else if (j.plan_K != -1) {
+        (void)ea_set_slab_plan(j.sim, -1, 0);
+        j.plan_K = -1;
+    }
 }
 
 // One epoch: retire, admit, launch, wait.  Returns EA_OK with *progressed = 0
@@ -243,12 +268,19 @@ ea_status server_epoch(ea_server *s, int32_t *progressed)
                 c.seed = j->h.job.seed;
                 c.sample = j->h.job.sample;
                 c.n_tw_slots = j->h.job.n_tw;
-                c.stream = nullptr;  // a stream of its own
+                // the worker with the least remaining work takes it, on its stream
+                std::vector<double> load(s->wstreams.size(), 0.0);
+                for (auto &r : s->resident)
+                    if (r->streamed && r.get() != j)
+                        load[(size_t)r->worker] += (double)r->h.job.L * r->h.job.L * r->h.job.L *
+                                                   (double)(r->h.job.n_sweeps - r->h.t_host);
+                j->worker = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                c.stream = s->wstreams[(size_t)j->worker];
                 c.dev_buf = j->h.base;
                 c.dev_buf_bytes = j->h.bytes;
                 c.words_per_row = j->h.RW;  // the packing its footprint was planned with
                 st = ea_create_ex(&c, &j->sim);
-                if (st == EA_OK) st = server_slab_plan(j->sim);
+                if (st == EA_OK) server_slab_plan(*j, s->n_cu / (int)s->wstreams.size());
                 j->results.assign((size_t)j->h.job.n_meas * (size_t)j->h.obs_stride, 0ull);
             } else {
                 st = upload_schedule(j->h, s->stream);
@@ -301,15 +333,13 @@ ea_status server_epoch(ea_server *s, int32_t *progressed)
         EA_HIP(hipGetLastError());
         EA_HIP(hipEventRecord(s->ev_batch[1], s->stream));
     }
-    // streamed jobs, each on its own stream, while the batched launch runs:
-    // kStreamWorkers host threads share them out, each thread's jobs splitting
-    // the expected epoch time
+    // streamed jobs, on their workers' streams: one host thread per worker
+    // with jobs, each thread's jobs splitting the expected epoch time
     if (!streamed.empty()) {
-        // The streamed phase follows the batched launch (which may hold few
-        // jobs and leave most compute units idle), so it gets the batched
-        // launch's time scaled by the ratio of the streamed jobs' remaining
-        // site-updates to the batched jobs', between 1x and 16x (and at least
-        // 2 ms): both forms then progress in proportion to their work.
+        // The streamed phase gets the batched launch's time scaled by the
+        // ratio of the streamed jobs' remaining site-updates to the batched
+        // jobs', between 1x and 16x (and at least 2 ms): both forms then
+        // progress in proportion to their work.
         double rem_streamed = 0.0, rem_batched = 0.0;
         for (ServerJob *j : run) {
             const double N = (double)j->h.job.L * j->h.job.L * j->h.job.L;
@@ -318,18 +348,33 @@ ea_status server_epoch(ea_server *s, int32_t *progressed)
         }
         const double ratio = rem_batched > 0.0 ? std::min(16.0, std::max(1.0, rem_streamed / rem_batched)) : 16.0;
         const double target = std::max(s->last_batch_s * ratio, 2e-3);
-        const int n_workers = std::min<int>(kStreamWorkers, (int)streamed.size());
-        std::vector<std::vector<size_t>> lists((size_t)n_workers);
-        int n = 0;
-        for (size_t i = 0; i < run.size(); ++i)
-            if (run[i]->streamed) lists[(size_t)(n++ % n_workers)].push_back(i);
+        // each worker's jobs, in admission order, on its stream
+        std::vector<std::vector<size_t>> lists;
+        {
+            std::vector<std::vector<size_t>> by_worker(s->wstreams.size());
+            for (size_t i = 0; i < run.size(); ++i)
+                if (run[i]->streamed) by_worker[(size_t)run[i]->worker].push_back(i);
+            for (auto &l : by_worker)
+                if (!l.empty()) lists.push_back(std::move(l));
+        }
+        const int n_workers = (int)lists.size();
+        // Plans of this epoch: the workers with jobs share the compute units
+        // that the batched launch leaves free, so that they can start beside
+        // it; where it leaves fewer than a quarter, they wait for it and
+        // share all of them.  (Plans never change results.)
+        const int busy = batched.empty() ? 0 : (int)(2 * batched.size());
+        const bool overlap = busy > 0 && 4 * (s->n_cu - busy) >= s->n_cu;
+        const int share = (overlap ? s->n_cu - busy : s->n_cu) / n_workers;
+        for (auto &l : lists)
+            for (size_t i : l) server_slab_plan(*run[i], share);
         std::vector<std::string> errs((size_t)n_workers);
         auto advance = [&](int k) {
             (void)hipSetDevice(s->device);
-            // after the batched launch: slab workgroups that became resident
-            // beside it would wait for its compute units (and the per-sweep
-            // timing below would include that wait)
-            if (!batched.empty() && hipEventSynchronize(s->ev_batch[1]) != hipSuccess) {
+            // unless the plans leave the batched launch its compute units,
+            // after it: slab workgroups that became resident beside it would
+            // wait for its CUs (and the per-sweep timing below would include
+            // that wait)
+            if (!batched.empty() && !overlap && hipEventSynchronize(s->ev_batch[1]) != hipSuccess) {
                 errs[(size_t)k] = "hipEventSynchronize failed";
                 return;
             }
@@ -489,6 +534,20 @@ ea_status ea_server_create(const ea_server_opts *opts, ea_server **out)
         }
         s->own_stream = true;
     }
+    e = hipDeviceGetAttribute(&s->n_cu, hipDeviceAttributeMultiprocessorCount, s->device);
+    if (e != hipSuccess) {
+        ea_server_destroy(s);
+        return fail(EA_ERR_DEVICE, "hipDeviceGetAttribute: %s", hipGetErrorString(e));
+    }
+    s->wstreams.assign((size_t)server_stream_workers(), nullptr);
+    for (hipStream_t &ws : s->wstreams) {
+        e = hipStreamCreateWithFlags(&ws, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            ws = nullptr;
+            ea_server_destroy(s);
+            return fail(EA_ERR_DEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+        }
+    }
     for (int k = 0; k < 2; ++k) {
         e = hipEventCreate(&s->ev_batch[k]);
         if (e != hipSuccess) {
@@ -525,6 +584,8 @@ void ea_server_destroy(ea_server *s)
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     if (s->pool_buf) (void)hipFree(s->pool_buf);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    for (hipStream_t ws : s->wstreams)
+        if (ws) (void)hipStreamDestroy(ws);
     for (hipEvent_t ev : s->ev_batch)
         if (ev) (void)hipEventDestroy(ev);
     delete s;
