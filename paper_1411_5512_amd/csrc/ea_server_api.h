@@ -239,6 +239,29 @@ void server_slab_plan(ServerJob &j, int share)
     }
 }
 
+// An LDS-sized job (L >= kLoneStreamL) admitted while some worker has no
+// streamed job runs as a streamed job instead: alone in the batched kernel
+// its two replicas would hold two CUs for the whole run while the rest of
+// the device idles (an L = 64 job: 24.8 us per sweep there, about 2.3 us as
+// a slab job on many CUs).  Re-plans j.h for the plain form's layout and
+// returns true if it did.  Results never depend on the form.
+constexpr int kLoneStreamL = 48;
+
+bool stream_small_job(const ea_server *s, ServerJob &j)
+{
+    if (j.streamed || j.h.job.L < kLoneStreamL) return false;
+    size_t n_streamed = 0;
+    for (const auto &r : s->resident) n_streamed += r->streamed ? 1 : 0;
+    if (n_streamed >= s->wstreams.size()) return false;
+    const Layout lay = make_layout(j.h.job.L, j.h.job.n_tw, plain_rw(j.h.job.L));
+    j.streamed = true;
+    j.h.RW = lay.RW;
+    j.h.W = lay.W;
+    j.h.POS = j.h.job.L * j.h.job.L * lay.RW;
+    j.h.bytes = align256(lay.total);
+    return true;
+}
+
 // One epoch: retire, admit, launch, wait.  Returns EA_OK with *progressed = 0
 // when nothing was resident or admissible.
 ea_status server_epoch(ea_server *s, int32_t *progressed)
@@ -252,7 +275,14 @@ ea_status server_epoch(ea_server *s, int32_t *progressed)
         while (!s->pending.empty() && (int32_t)s->resident.size() < s->opts.max_resident) {
             ServerJob *j = s->pending.front().get();
             size_t off = 0;
-            if (!s->pool.alloc(j->h.bytes, &off)) break;
+            const BatchJobHost planned = j->h;
+            const bool restreamed = stream_small_job(s, *j);
+            if (!s->pool.alloc(j->h.bytes, &off)) {
+                if (!restreamed) break;
+                j->h = planned;  // the batched form's region may still fit
+                j->streamed = false;
+                if (!s->pool.alloc(j->h.bytes, &off)) break;
+            }
             j->pool_off = off;
             j->h.base = s->pool_buf + off;
             s->resident.push_back(std::move(s->pending.front()));
