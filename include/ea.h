@@ -401,6 +401,8 @@ typedef struct {
     double wall_s;        /* since the first submit */
     double ps_per_flip;   /* busy_s / flips */
     size_t hbm_in_use, hbm_peak;
+    uint64_t streamed_small; /* jobs with L <= 64 admitted to the slab path (a worker was free) */
+    uint64_t moved;          /* jobs moved from the batched launch to the slab path mid-run */
 } ea_server_report;
 
 enum { EA_JOB_PENDING = 0, EA_JOB_RUNNING = 1, EA_JOB_DONE = 2 };

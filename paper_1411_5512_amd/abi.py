@@ -126,6 +126,8 @@ class ServerReport(ctypes.Structure):
         ("ps_per_flip", ctypes.c_double),
         ("hbm_in_use", ctypes.c_size_t),
         ("hbm_peak", ctypes.c_size_t),
+        ("streamed_small", ctypes.c_uint64),
+        ("moved", ctypes.c_uint64),
     ]
 
 

@@ -270,12 +270,12 @@ ea_status fill_obs(const BatchJobHost &h, const unsigned long long *m, int32_t k
     return EA_OK;
 }
 
-// Unpack replica r's spins from a device region into int8 +-1.
-ea_status read_job_spins(const BatchJobHost &h, int32_t r, int8_t *pm1, hipStream_t stream)
+// Canonical +-1 spins of one configuration in the job's packed layout
+// ([colour][POS] words at dev).
+ea_status read_packed_pm1(const BatchJobHost &h, const char *dev, int8_t *pm1, hipStream_t stream)
 {
     std::vector<uint32_t> words(2 * (size_t)h.POS);
-    EA_HIP(hipMemcpyAsync(words.data(), h.base + h.off_spins + 4 * (size_t)r * 2 * h.POS, 4 * words.size(),
-                          hipMemcpyDeviceToHost, stream));
+    EA_HIP(hipMemcpyAsync(words.data(), dev, 4 * words.size(), hipMemcpyDeviceToHost, stream));
     EA_HIP(hipStreamSynchronize(stream));
     Layout y = make_layout(h.job.L, 0, h.RW);
     const int64_t N = (int64_t)h.job.L * h.job.L * h.job.L;
@@ -285,6 +285,12 @@ ea_status read_job_spins(const BatchJobHost &h, int32_t r, int8_t *pm1, hipStrea
         pm1[i] = bit ? (int8_t)-1 : (int8_t)1;
     }
     return EA_OK;
+}
+
+// Replica r's current spins as int8 +-1.
+ea_status read_job_spins(const BatchJobHost &h, int32_t r, int8_t *pm1, hipStream_t stream)
+{
+    return read_packed_pm1(h, h.base + h.off_spins + 4 * (size_t)r * 2 * h.POS, pm1, stream);
 }
 
 // Check that a launch with this much dynamic LDS fits one workgroup, and

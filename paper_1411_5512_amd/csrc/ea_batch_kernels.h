@@ -114,13 +114,15 @@ __device__ __forceinline__ uint32_t *lds_bond(int d, int c)
     return batch_lds + (2 + 2 * d + c) * S::POS;
 }
 
-// Update the colour-c words of this workgroup's replica (eq. 9), reading the
-// other colour and the couplings from LDS.
-template <int L, int RW, int SEL>
-__device__ __forceinline__ void batch_half_step(const BatchJobDev &J, int r, int c, uint32_t t)
+// Update the colour-C words of this workgroup's replica (eq. 9), reading the
+// other colour and the couplings from LDS.  The colour is a template
+// argument so that every plane's LDS offset is a compile-time constant.
+template <int L, int RW, int SEL, int C>
+__device__ __forceinline__ void batch_half_step(const BatchJobDev &J, int r, uint32_t t)
 {
     using S = Shape<L, RW>;
     constexpr int W = S::W;
+    constexpr int c = C;
     uint32_t *own = lds_spin<S>(c);
     const uint32_t *oth = lds_spin<S>(c ^ 1);
     const uint32_t *bx_own = lds_bond<S>(0, c), *by_own = lds_bond<S>(1, c), *bz_own = lds_bond<S>(2, c);
@@ -334,9 +336,15 @@ __device__ void batch_run_unit(const BatchJobDev &J, int r, uint32_t t_stop, boo
             __syncthreads();
         }
         if (t >= t_stop) break;
-        batch_half_step<L, RW, SEL>(J, r, r, t);
-        __syncthreads();
-        batch_half_step<L, RW, SEL>(J, r, r ^ 1, t);
+        if (r == 0) {
+            batch_half_step<L, RW, SEL, 0>(J, r, t);
+            __syncthreads();
+            batch_half_step<L, RW, SEL, 1>(J, r, t);
+        } else {
+            batch_half_step<L, RW, SEL, 1>(J, r, t);
+            __syncthreads();
+            batch_half_step<L, RW, SEL, 0>(J, r, t);
+        }
         __syncthreads();
         ++t;
     }

@@ -117,7 +117,7 @@ struct ServerJob {
     size_t pool_off = 0;
     steady::time_point t_submit, t_done;
     std::vector<unsigned long long> results;  // [n_meas][obs_stride] after completion
-    bool streamed = false;                     // L > 64: plain-form kernels on a worker's stream
+    bool streamed = false;                     // on the slab path (L > 64, or given it), on a worker's stream
     int worker = 0;                            // that worker (its stream)
     int plan_K = 0;                            // its slab plan's slabs per replica (-1: half-step launches)
     ea_sim *sim = nullptr;                     // its simulation, in the pool region
@@ -155,7 +155,7 @@ struct ea_server {
     std::vector<std::unique_ptr<ServerJob>> resident;
     std::unordered_map<uint64_t, std::unique_ptr<ServerJob>> done;
     std::unordered_map<uint64_t, int> state_of;
-    uint64_t next_id = 1, submitted = 0, admitted = 0, completed = 0, epochs = 0;
+    uint64_t next_id = 1, submitted = 0, admitted = 0, completed = 0, epochs = 0, streamed_small = 0, moved = 0;
     std::vector<double> latencies;
     double flips = 0.0, busy_s = 0.0;
     bool have_first = false;
@@ -262,6 +262,101 @@ bool stream_small_job(const ea_server *s, ServerJob &j)
     return true;
 }
 
+// A batched job with at least this many site-sweeps left (about 50 ms of an
+// L = 64 job in the batched kernel) may move to the slab path.
+constexpr double kMoveMinSiteSweeps = 64.0 * 64 * 64 * 2000;
+
+// Move batched job j to the slab path mid-run, on worker `worker`'s stream
+// (a batched job that outlasts the rest would hold two CUs while the device
+// idles).  The plain run is rebuilt through the ABI from the job's packed
+// state: its snapshots taken so far, each restored at its time, then the
+// current spins and time; the couplings are regenerated from the same keys.
+// The measurements taken so far go to the host as the job's first result
+// rows.  *moved = false (and nothing changes) if the pool has no room for
+// the plain form's region now.  The job's last batched launch has finished.
+ea_status move_to_slabs(ea_server *s, ServerJob &j, int worker, bool *moved)
+{
+    *moved = false;
+    const int L = j.h.job.L, n_tw = j.h.job.n_tw, n_meas = j.h.job.n_meas;
+    const Layout lay = make_layout(L, n_tw, plain_rw(L));
+    BatchJobHost nh = j.h;
+    nh.RW = lay.RW;
+    nh.W = lay.W;
+    nh.POS = L * L * lay.RW;
+    nh.bytes = align256(lay.total);
+    size_t off = 0;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (!s->pool.alloc(nh.bytes, &off)) return EA_OK;
+    }
+    nh.base = s->pool_buf + off;
+    auto give_back = [&](ea_sim *sim, ea_status st) {
+        if (sim) ea_destroy(sim);
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->pool.release(off, nh.bytes);
+        return st;
+    };
+    const uint64_t t = j.h.t_host;
+    std::vector<unsigned long long> results((size_t)n_meas * (size_t)j.h.obs_stride);
+    if (!results.empty()) {
+        const hipError_t e = hipMemcpy(results.data(), j.h.base + j.h.off_obs, 8 * results.size(),
+                                       hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return give_back(nullptr, fail(EA_ERR_DEVICE, "hipMemcpy: %s", hipGetErrorString(e)));
+    }
+    ea_config c{};
+    c.L = L;
+    c.p = j.h.job.p;
+    c.T = j.h.job.T;
+    c.seed = j.h.job.seed;
+    c.sample = j.h.job.sample;
+    c.n_tw_slots = n_tw;
+    c.stream = s->wstreams[(size_t)worker];
+    c.dev_buf = nh.base;
+    c.dev_buf_bytes = nh.bytes;
+    c.words_per_row = nh.RW;
+    ea_sim *sim = nullptr;
+    ea_status st = ea_create_ex(&c, &sim);
+    if (st != EA_OK) return give_back(nullptr, st);
+    const size_t rep = 4 * 2 * (size_t)j.h.POS;  // bytes of one replica's two colour planes
+    std::vector<int8_t> pm1((size_t)L * L * L);
+    int next_tw = 0;
+    while (next_tw < n_tw && j.h.tw[(size_t)next_tw] <= t) ++next_tw;
+    for (int k = 0; k < next_tw && st == EA_OK; ++k) {
+        for (int r = 0; r < 2 && st == EA_OK; ++r) {
+            st = read_packed_pm1(j.h, j.h.base + j.h.off_snaps + ((size_t)k * 2 + (size_t)r) * rep, pm1.data(),
+                                 s->stream);
+            if (st == EA_OK) st = ea_set_spins(sim, r, pm1.data());
+        }
+        if (st == EA_OK) st = ea_set_time(sim, j.h.tw[(size_t)k]);
+        if (st == EA_OK) st = ea_snapshot(sim, k);
+    }
+    for (int r = 0; r < 2 && st == EA_OK; ++r) {
+        st = read_packed_pm1(j.h, j.h.base + j.h.off_spins + (size_t)r * rep, pm1.data(), s->stream);
+        if (st == EA_OK) st = ea_set_spins(sim, r, pm1.data());
+    }
+    if (st == EA_OK) st = ea_set_time(sim, t);
+    if (st == EA_OK) st = ea_sync(sim);
+    if (st != EA_OK) return give_back(sim, st);
+    int next_meas = 0;
+    while (next_meas < n_meas && j.h.meas_t[(size_t)next_meas] <= t) ++next_meas;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->pool.release(j.pool_off, j.h.bytes);
+    }
+    j.pool_off = off;
+    j.h = std::move(nh);
+    j.sim = sim;
+    j.streamed = true;
+    j.worker = worker;
+    j.results = std::move(results);
+    j.next_meas = next_meas;
+    j.next_tw = next_tw;
+    j.sweep_s = 0.0;
+    j.plan_K = 0;
+    *moved = true;
+    return EA_OK;
+}
+
 // One epoch: retire, admit, launch, wait.  Returns EA_OK with *progressed = 0
 // when nothing was resident or admissible.
 ea_status server_epoch(ea_server *s, int32_t *progressed)
@@ -276,13 +371,14 @@ ea_status server_epoch(ea_server *s, int32_t *progressed)
             ServerJob *j = s->pending.front().get();
             size_t off = 0;
             const BatchJobHost planned = j->h;
-            const bool restreamed = stream_small_job(s, *j);
+            bool restreamed = stream_small_job(s, *j);
             if (!s->pool.alloc(j->h.bytes, &off)) {
                 if (!restreamed) break;
                 j->h = planned;  // the batched form's region may still fit
-                j->streamed = false;
+                j->streamed = restreamed = false;
                 if (!s->pool.alloc(j->h.bytes, &off)) break;
             }
+            s->streamed_small += restreamed ? 1 : 0;
             j->pool_off = off;
             j->h.base = s->pool_buf + off;
             s->resident.push_back(std::move(s->pending.front()));
@@ -321,6 +417,33 @@ ea_status server_epoch(ea_server *s, int32_t *progressed)
         for (auto &p : s->resident) run.push_back(p.get());
     }
     if (run.empty()) return EA_OK;
+
+    // a long batched job moves to the slab path when some worker has no job
+    {
+        std::vector<int> per_worker(s->wstreams.size(), 0);
+        for (ServerJob *j : run)
+            if (j->streamed) ++per_worker[(size_t)j->worker];
+        const auto idle = std::find(per_worker.begin(), per_worker.end(), 0);
+        ServerJob *best = nullptr;
+        double best_rem = 0.0;
+        for (ServerJob *j : run) {
+            if (idle == per_worker.end() || j->streamed || !j->h.started || j->h.job.L < kLoneStreamL) continue;
+            const double rem = (double)j->h.job.L * j->h.job.L * j->h.job.L * (double)(j->h.job.n_sweeps - j->h.t_host);
+            if (rem >= kMoveMinSiteSweeps && rem > best_rem) {
+                best = j;
+                best_rem = rem;
+            }
+        }
+        if (best) {
+            bool moved = false;
+            ea_status st = move_to_slabs(s, *best, (int)(idle - per_worker.begin()), &moved);
+            if (st != EA_OK) return st;
+            if (moved) {
+                std::lock_guard<std::mutex> lk(s->mu);
+                ++s->moved;
+            }
+        }
+    }
 
     // spans: about opts.epoch_site_sweeps site-updates per replica, at least one sweep
     std::vector<BatchJobHost *> hs;
@@ -795,6 +918,8 @@ ea_status ea_server_stats(ea_server *s, ea_server_report *out)
     r.ps_per_flip = s->flips > 0 ? s->busy_s / s->flips * 1e12 : 0.0;
     r.hbm_in_use = s->pool.in_use;
     r.hbm_peak = s->pool.peak;
+    r.streamed_small = s->streamed_small;
+    r.moved = s->moved;
     *out = r;
     return EA_OK;
 }

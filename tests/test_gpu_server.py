@@ -210,3 +210,48 @@ def test_server_streamed_job_matches_oracle(ea_gpu, oracle_mod):
             _same_obs(srv.result(jid, k), o.measure(), f"meas {k}")
             k += 1
     assert k == len(job.meas_t)
+
+
+def test_server_moves_a_long_batched_job_to_slabs(ea_gpu):
+    """A long L = 48 job admitted to the batched launch while every worker
+    has a streamed job moves to the slab path once a worker is free (its
+    state, snapshots and first measurements carried over); an L = 64 job
+    admitted to an idle server goes to the slab path at once; every job's
+    results equal its run alone."""
+    from paper_1411_5512_amd.workloads import Job
+    first = [Job(72, 0.5, 0.8, seed=80 + i, sample=i, n_sweeps=30, meas_t=[30], tw=[]) for i in range(5)]
+    long48 = Job(48, 0.4, 0.7, seed=90, sample=1, n_sweeps=6000, meas_t=[0, 100, 700, 3000, 6000],
+                 tw=[10, 5000])
+    small = Job(16, 0.5, 0.9, seed=91, sample=0, n_sweeps=400, meas_t=[400], tw=[50])
+    jobs = first + [long48, small]
+    srv = ea_gpu.Server(hbm_budget=1 << 28, max_resident=16)
+    ids = [srv.submit(j) for j in jobs]
+    n = 0
+    while srv.step():
+        n += 1
+        assert n < 100000
+    st = srv.stats()
+    _say(f"server stats {st}")
+    assert st["moved"] >= 1 and st["completed"] == len(jobs)
+    for jid, job in zip(ids, jobs):
+        alone = ea_gpu.Batch([job]) if job.L <= 64 else None
+        if alone is not None:
+            alone.run()
+            for k in range(len(job.meas_t)):
+                _same_obs(srv.result(jid, k), alone.result(0, k), f"L={job.L} meas {k}")
+            alone.close()
+        else:
+            ref = _alone_plain(ea_gpu, job)
+            for k, want in enumerate(ref):
+                _same_obs(srv.result(jid, k), want, f"L={job.L} meas {k}")
+    idle = ea_gpu.Server(hbm_budget=1 << 28, max_resident=4)
+    job = Job(64, 0.5, 0.7, seed=92, sample=0, n_sweeps=300, meas_t=[0, 37, 300], tw=[37])
+    jid = idle.submit(job)
+    while idle.step():
+        pass
+    assert idle.stats()["streamed_small"] == 1
+    alone = ea_gpu.Batch([job])
+    alone.run()
+    for k in range(len(job.meas_t)):
+        _same_obs(idle.result(jid, k), alone.result(0, k), f"idle L=64 meas {k}")
+    alone.close()
