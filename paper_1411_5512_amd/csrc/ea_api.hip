@@ -138,30 +138,37 @@ void read_plain_tune_file()
 bool slab_capable(int L, int rw) { return L * rw <= ea::kSlabThreads; }
 
 // Modelled time per sweep (us) of a plan whose workgroups own at most s
-// planes each, used to pick one, with constants
-// measured on MI355X: a packed word costs ~(13.2 W + 40) VALU
-// lane-instructions, ~370 words of 32 sites per us on one compute unit, and
-// no less than one word's chain of dependent instructions per half-step.
-// With g = 1 a half-step costs ~0.9 us of exchange and barrier beyond its
-// slab's words; a cycle of g >= 2 half-steps costs ~3 us
-// beyond its words (the ghost planes are read only after the neighbours'
-// whole cycle, with a barrier on either side).
+// planes each, used to pick one, with constants measured on MI355X.  A
+// workgroup updates 1024 / (L rw) planes at once; in each such round its
+// waves share the four SIMDs, and a SIMD runs the dependent chains of its
+// waves' words about one after the other, one chain being ~(13.2 W + 40)
+// instructions at ~4 cycles each.  With g = 1 a half-step costs ~0.9 us of
+// exchange and barrier beyond its rounds; a cycle of g >= 2 half-steps costs
+// ~3 us beyond its rounds (the ghost planes are read only after the
+// neighbours' whole cycle, with a barrier on either side).  Measured per
+// sweep against the model: L = 64 one plane of 4 words of 8 sites 2.36 us
+// (2.29), L = 96 one plane of 2 words 2.97 (2.99) and of 3 words 3.34
+// (3.48), L = 128 one plane 3.41 (3.34), five L = 128 runs on shares of 5
+// planes 9.96 (9.50).
 double slab_model_us(int L, int rw, int s, int g)
 {
     const int W = L / 2 / rw, PL = L * rw;
-    const double per_word = 13.2 * W + 40.0;
-    const double rate = 370.0 * (13.2 * 32 + 40.0) / per_word;  // words per us on one compute unit
-    const double chain = per_word * 4.0 / 2400.0;  // one word's dependent instructions alone on a SIMD, us
-    if (g == 1) return 2.0 * (0.9 + std::max(chain, (double)s * PL / rate));
+    const double chain = (13.2 * W + 40.0) * 4.0 / 2400.0;  // one word's chain on a SIMD, us
+    const int zstep = std::max(1, ea::kSlabThreads / PL);
+    auto planes_us = [&](int n) {
+        double t = 0.0;
+        for (int left = n; left > 0; left -= zstep) {
+            const int waves = (std::min(left, zstep) * PL + 63) / 64;
+            t += (double)((waves + 3) / 4) * chain;
+        }
+        return t;
+    };
+    if (g == 1) return 2.0 * (0.9 + planes_us(s));
     double cycle = 3.0;
-    for (int k = 1; k <= g; ++k) cycle += std::max(chain, (double)(s + 2 * g - 2 * k) * PL / rate);
+    for (int k = 1; k <= g; ++k) cycle += planes_us(s + 2 * g - 2 * k);
     return 2.0 * cycle / g;
 }
 
-// Modelled time per sweep of the best plan for one run of side L in packing
-// rw on a device of 256 compute units with 160 KiB of LDS per workgroup
-// (the plan itself is chosen per launch from the real device), or a negative
-// value when the packing cannot run as slabs.
 double slab_best_model_us(int L, int rw)
 {
     if (!slab_capable(L, rw)) return -1.0;
