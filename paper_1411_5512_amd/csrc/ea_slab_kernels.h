@@ -268,8 +268,11 @@ __global__ __launch_bounds__(kSlabThreads) void slab_sweep_kernel(SlabLaunch a)
 {
     const int L = a.L, RW = a.RW, PL = L * RW, R = L / 2;
     const int g = a.g, EM = a.emax;
+    // consecutive shares (z neighbours) on the same XCD, whose exchange is
+    // faster than one across XCDs (xcd_block); the debug order permutes first
     SlabPiece p0, p1;
-    const int np = slab_pieces(a, debug_block((int)blockIdx.x, (int)gridDim.x, a.order), p0, p1);
+    const int share = xcd_block(debug_block((int)blockIdx.x, (int)gridDim.x, a.order), (int)gridDim.x);
+    const int np = slab_pieces(a, share, p0, p1);
     // LDS: [colour][EM][PL] spins, [direction][colour][EM][PL] couplings,
     // 16 flag words, then (tables = 2) the second piece's select table
     uint32_t *lspin = slab_lds;
