@@ -416,6 +416,8 @@ def bench_serving(ea, torch, wl, n_jobs: int, load: float, sweep_hi: int, calib_
         "ps_per_flip_capacity_burst": round(ps_capacity, 4),
         "flips": total,
         "epochs": int(st["epochs"]),
+        "small_jobs_on_slabs": int(st["streamed_small"]),
+        "jobs_moved_to_slabs": int(st["moved"]),
         "hbm_peak_mib": round(st["hbm_peak"] / 2 ** 20, 1),
         "wall_s": round(wall, 3),
     }

@@ -255,3 +255,37 @@ def test_server_moves_a_long_batched_job_to_slabs(ea_gpu):
     for k in range(len(job.meas_t)):
         _same_obs(idle.result(jid, k), alone.result(0, k), f"idle L=64 meas {k}")
     alone.close()
+
+
+def test_server_long_jobs_equal_alone(ea_gpu):
+    """Long jobs of the serving configuration's sizes (L = 128 for 4 x 10^4
+    sweeps, L = 96 for 3 x 10^4, and a long L = 64 job that starts in the
+    batched launch and moves to the slab path mid-run) through the worker
+    thread: every measurement, late ones included, equals the job run alone."""
+    from paper_1411_5512_amd.workloads import Job, log_schedule
+    jobs = []
+    for i, (L, n) in enumerate([(72, 40), (72, 40), (72, 40), (72, 40), (72, 40),
+                                (128, 40_000), (96, 30_000), (64, 20_000)]):
+        tw = [t for t in (100, 1000) if t <= n]
+        meas = sorted(set(log_schedule(n, 12)) | set(tw))
+        jobs.append(Job(L, 0.2 + 0.05 * (i % 5), 0.6 + 0.1 * (i % 4), seed=300 + i, sample=i % 3,
+                        n_sweeps=n, meas_t=meas, tw=tw))
+    srv = ea_gpu.Server(hbm_budget=1 << 29, max_resident=16)
+    ids = [srv.submit(j) for j in jobs]  # all admitted at the first epoch, in this order
+    srv.start()
+    srv.drain(600)
+    srv.stop()
+    st = srv.stats()
+    _say(f"server stats {st}")
+    assert st["completed"] == len(jobs) and st["moved"] >= 1
+    for jid, job in zip(ids, jobs):
+        if job.L <= 64:
+            alone = ea_gpu.Batch([job])
+            alone.run()
+            ref = [alone.result(0, k) for k in range(len(job.meas_t))]
+            alone.close()
+        else:
+            ref = _alone_plain(ea_gpu, job)
+        _say(f"long job L={job.L} sweeps={job.n_sweeps}")
+        for k, want in enumerate(ref):
+            _same_obs(srv.result(jid, k), want, f"L={job.L} meas {k} t={job.meas_t[k]}")
