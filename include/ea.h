@@ -373,9 +373,17 @@ ea_status ea_batch_parts(ea_batch *b, int32_t job, int32_t *parts);
  *     job in LDS; its span is about epoch_site_sweeps site updates per
  *     replica (at least one sweep);
  *   - 64 < L <= 256 (multiple of 8): the job is a plain-form simulation in
- *     its pool region, advanced through the HBM-streaming kernels on a second
- *     library stream while the batched launch runs; its span is sized so
- *     that the streamed work takes about as long as the last batched launch.
+ *     its pool region, advanced by persistent slab launches (as ea_sweep)
+ *     from one of a few worker threads, each with a library stream of its
+ *     own (as many as the process's hardware queues, GPU_MAX_HW_QUEUES,
+ *     allow beside the batched stream, at most four), on the compute units
+ *     the batched launch leaves free; its span is sized so that the streamed
+ *     work takes about as long as the last batched launch;
+ *   - a job with 48 <= L <= 64 takes that slab path too when it is admitted
+ *     while some worker has no job, and a batched one with much work left
+ *     moves to it mid-run when a worker frees up (its state, snapshots and
+ *     measurements so far carried over), so that a lone small job does not
+ *     run on two compute units while the device idles.
  * Finished jobs hand their results to the host and free their memory;
  * waiting jobs join at the next epoch.  A job's results are identical to a
  * run alone (ea_create, or ea_batch_create for L <= 64) with the same

@@ -16,8 +16,8 @@
 //
 // Lattices too large for one workgroup's LDS (L > 64) are "streamed" jobs:
 // each is a plain-form simulation placed in its pool region, advanced in the
-// epoch by slab launches (ea_set_slab_plan) from up to kStreamWorkers host
-// threads at once, beside the epoch's batched launch on the compute units it
+// epoch by slab launches (ea_set_slab_plan) from up to kStreamWorkers
+// worker threads at once, beside the epoch's batched launch on the compute units it
 // leaves free (each epoch's slab plans are sized to them), or after it when
 // it leaves fewer than a quarter (persistent slab workgroups beside a
 // batched launch that fills the device would wait for its compute units
