@@ -242,6 +242,39 @@ def alu_probe():
     return out
 
 
+def shells_probe(ea, sizes=(32, 64, 128, 256), reps=3):
+    """Wall time of one full-vector C4 call (ea_c4_shells over every
+    displacement, synchronous) by the FFT route and by the direct route, on
+    a quenched run of each size after 20 sweeps; the two results must be
+    identical.  The FFT route's first call allocates its work array, so the
+    best of `reps` later calls is reported."""
+    out = {}
+    try:
+        for L in sizes:
+            g = ea.Sim(L, 0.5, 0.7, seed=1)
+            g.sweep(20)
+            n_all = 3 * (L // 2) ** 2 + 1
+            row, res = {}, {}
+            for name, route in (("fft", ea.SHELLS_FFT), ("direct", ea.SHELLS_DIRECT)):
+                ea.set_shell_route(route)
+                res[name] = g.c4_shells(n_all)
+                best = float("inf")
+                for _ in range(reps if name == "fft" or L <= 128 else 1):
+                    t0 = time.perf_counter()
+                    g.c4_shells(n_all)
+                    best = min(best, time.perf_counter() - t0)
+                row[f"{name}_ms"] = round(best * 1e3, 3)
+            if not (res["fft"] == res["direct"]).all():
+                raise RuntimeError(f"full-vector C4 routes differ at L={L}")
+            row["speedup"] = round(row["direct_ms"] / row["fft_ms"], 1)
+            out[f"L{L}"] = row
+            print(json.dumps({"shells_probe_progress": L, **row}), flush=True)
+            g.close()
+    finally:
+        ea.set_shell_route(ea.SHELLS_AUTO)
+    return out
+
+
 def bench_msc(ea, torch, job, burst: int):
     """The multispin-coded batch (asynchronous multispin coding, shared random
     words) on the paper's production configuration: the whole schedule once
@@ -460,6 +493,9 @@ def main():
     ap.add_argument("--alu-probe", action="store_true",
                     help="only measure the lane rate of v_mad_u64_u32, v_bitop3_b32 and whole Philox4x32-10 "
                          "blocks against the integer-ALU peak (the roofline's op count) and exit")
+    ap.add_argument("--shells-probe", action="store_true",
+                    help="only time the full-vector C4 shells (every displacement) by the FFT and the direct "
+                         "route at L = 32, 64, 128, 256, check that they agree, and exit")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (a known-size kernel "
                          "for calibrating hardware byte counters) and exit")
@@ -480,6 +516,10 @@ def main():
 
     if args.alu_probe:
         print(json.dumps({"alu_probe": alu_probe()}), flush=True)
+        return
+
+    if args.shells_probe:
+        print(json.dumps({"shells_probe": shells_probe(ea)}), flush=True)
         return
 
     if args.copy_probe_mib:

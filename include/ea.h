@@ -166,11 +166,32 @@ ea_status ea_words_per_row(const ea_sim *sim, int32_t *rw);
  * k = 0 .. n_shells - 1.  n_shells = (L/2)^2 + 1 covers |r| <= L/2, the range
  * of the integral estimators (eqs. 5, 6); 3 (L/2)^2 + 1 covers every r.
  * Dividing a shell by N and by the number of lattice vectors in it gives the
- * shell average of C4.  The work grows as L^6 / 64: about 20 ms at L = 128,
- * over a second at L = 256.  Synchronises; allocates a device scratch buffer
- * of 8 (2 L^2 ceil(L/64) + 3 (L/2)^2 + 1) bytes on the first call, kept
- * until ea_destroy.  EA_ERR_ARG for n_shells outside [1, 3 (L/2)^2 + 1]. */
+ * shell average of C4.  Two routes give the same integers (ea_set_shell_route):
+ * the direct one counts differing bits for every displacement (work ~ L^6 /
+ * 64: about 20 ms at L = 128, over a second at L = 256); for power-of-two L
+ * the FFT route takes the fp64 3D DFT of q, its squared modulus and the
+ * inverse DFT (the Wiener-Khinchin theorem), rounds each sum to the nearest
+ * integer and bins it (work ~ L^3 log L).  Synchronises; allocates a device
+ * scratch buffer of 8 (2 L^2 ceil(L/64) + 3 (L/2)^2 + 1) bytes on the first
+ * call, and on the first FFT-route call one of 16 L^3 + 256 bytes (256 MiB
+ * at L = 256), both kept until ea_destroy.  EA_ERR_ARG for n_shells outside
+ * [1, 3 (L/2)^2 + 1]; EA_ERR_NOMEM if a scratch buffer cannot be allocated;
+ * EA_ERR_DEVICE if a sum of the FFT route is not within 1/4 of an integer
+ * (outside the fp64 error bound, which is below 1e-7 here). */
 ea_status ea_c4_shells(ea_sim *sim, int32_t n_shells, int64_t *out);
+
+/* Route of the full-vector C4 shells (ea_c4_shells, ea_batch_c4_shells,
+ * ea_msc_c4_shells; ea_c4_shells_into always takes the direct route):
+ *   EA_SHELLS_AUTO    the FFT route for power-of-two L >= 64, else direct
+ *                     (the default);
+ *   EA_SHELLS_DIRECT  the direct route for every L;
+ *   EA_SHELLS_FFT     the FFT route for every power-of-two L (8 .. 256); other
+ *                     L take the direct route.
+ * Both routes give identical results.  Process-wide, read at each call.
+ * EA_ERR_ARG for another value. */
+enum { EA_SHELLS_AUTO = 0, EA_SHELLS_DIRECT = 1, EA_SHELLS_FFT = 2 };
+ea_status ea_set_shell_route(int32_t route);
+ea_status ea_get_shell_route(int32_t *route);
 
 /* ea_c4_shells for callers that cannot allocate device memory: code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
@@ -351,7 +372,7 @@ ea_status ea_batch_result(ea_batch *b, int32_t job, int32_t k, ea_obs *out);
  * job `job` at its measurement k, from the configuration of both replicas
  * that the batched kernel publishes at each measurement: out[n_shells].
  * Synchronises; allocates and frees a scratch buffer of
- * 8 (2 L^2 + n_shells) bytes for the call.  EA_ERR_ARG for a job or k out of
+ * 8 (2 L^2 + n_shells) bytes for the call (16 L^3 more on the FFT route).  EA_ERR_ARG for a job or k out of
  * range or n_shells outside [1, 3 (L/2)^2 + 1]; EA_ERR_STATE if measurement
  * k has not been reached. */
 ea_status ea_batch_c4_shells(ea_batch *b, int32_t job, int32_t k, int32_t n_shells, int64_t *out);
@@ -516,7 +537,7 @@ ea_status ea_msc_measure(ea_msc *batch, ea_obs *out);
 /* Full-vector C4 shells (as ea_c4_shells) of sample `sample` (0 .. B-1) of
  * the batch at the current time: out[n_shells].  Synchronises; allocates and
  * frees a scratch buffer of 8 (2 L^2 ceil(L/64) + n_shells) bytes for the
- * call.  EA_ERR_ARG for a sample out of range or n_shells outside
+ * call (16 L^3 more on the FFT route).  EA_ERR_ARG for a sample out of range or n_shells outside
  * [1, 3 (L/2)^2 + 1]. */
 ea_status ea_msc_c4_shells(ea_msc *m, int32_t sample, int32_t n_shells, int64_t *out);
 

@@ -16,7 +16,8 @@ from . import abi
 from .abi import EAError
 
 __all__ = ["Sim", "Batch", "Server", "EAError", "thresholds", "footprint", "version", "tune", "sweep_group", "run_group", "Msc",
-           "set_debug", "get_debug", "DEBUG_REVERSE", "DEBUG_ROTATE", "DEBUG_POISON"]
+           "set_debug", "get_debug", "DEBUG_REVERSE", "DEBUG_ROTATE", "DEBUG_POISON",
+           "set_shell_route", "get_shell_route", "SHELLS_AUTO", "SHELLS_DIRECT", "SHELLS_FFT"]
 
 
 def version() -> str:
@@ -43,6 +44,22 @@ def get_debug() -> tuple:
     f, s = ctypes.c_uint32(0), ctypes.c_uint32(0)
     abi.check(abi.lib().ea_get_debug(ctypes.byref(f), ctypes.byref(s)))
     return int(f.value), int(s.value)
+
+
+SHELLS_AUTO, SHELLS_DIRECT, SHELLS_FFT = 0, 1, 2
+
+
+def set_shell_route(route: int = SHELLS_AUTO) -> None:
+    """Route of the full-vector C4 shells (ea_set_shell_route): automatic
+    (FFT for power-of-two L >= 64), direct bit counting, or FFT wherever L
+    is a power of two.  Both give identical results."""
+    abi.check(abi.lib().ea_set_shell_route(int(route)))
+
+
+def get_shell_route() -> int:
+    r = ctypes.c_int32(0)
+    abi.check(abi.lib().ea_get_shell_route(ctypes.byref(r)))
+    return int(r.value)
 
 
 def footprint(L: int, n_tw: int = 0, words_per_row: int = 0) -> int:

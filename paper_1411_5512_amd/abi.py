@@ -139,6 +139,8 @@ _SIGS = {
     "ea_thresholds": (ctypes.c_int, [ctypes.c_double, ctypes.POINTER(ctypes.c_uint32)]),
     "ea_set_debug": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32]),
     "ea_get_debug": (ctypes.c_int, [ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32)]),
+    "ea_set_shell_route": (ctypes.c_int, [ctypes.c_int32]),
+    "ea_get_shell_route": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int32)]),
     "ea_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
                                  ctypes.POINTER(ctypes.c_void_p)]),
     "ea_create_ex": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_void_p)]),

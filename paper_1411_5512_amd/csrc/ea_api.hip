@@ -5,6 +5,7 @@
 #include "ea_batch_kernels.h"
 #include "ea_slab_kernels.h"
 #include "ea_shells.h"
+#include "ea_fft.h"
 
 #include <chrono>
 #include <cmath>
@@ -280,8 +281,10 @@ struct ea_sim {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     uint32_t graph_order = 0;  // debug order the graph was captured with
-    // scratch of ea_c4_shells (allocated on first use)
+    // scratch of ea_c4_shells (allocated on first use): dense rows and
+    // shells, and the FFT route's complex array
     unsigned long long *c4_scratch = nullptr;
+    void *fft_work = nullptr;
     // event ordering this run's stream with a group sweep (created on first use)
     hipEvent_t group_event = nullptr;
     // persistent slab path: plan (slabs per replica: 0 automatic, -1 off;
@@ -686,6 +689,79 @@ ea_status launch_shell_rows(const unsigned long long *qd, int L, int n_shells, u
     return EA_OK;
 }
 
+// Route of the full-vector C4 shells (ea_set_shell_route).
+std::atomic<int32_t> g_shell_route{EA_SHELLS_AUTO};
+// automatic route: FFT for power-of-two L from this side on (at L = 32 the
+// direct kernel is faster: 0.07 against 0.10 ms per call)
+constexpr int kFftAutoMinL = 64;
+
+int log2_pow2(int L)
+{
+    for (int k = 3; k <= 8; ++k)
+        if (L == (1 << k)) return k;
+    return -1;
+}
+
+bool shells_by_fft(int L)
+{
+    const int32_t r = g_shell_route.load();
+    if (log2_pow2(L) < 0 || r == EA_SHELLS_DIRECT) return false;
+    return r == EA_SHELLS_FFT || L >= kFftAutoMinL;
+}
+
+// Device bytes of the FFT route: the complex array, then the error word.
+size_t fft_work_bytes(int L) { return 16 * (size_t)L * L * L + 256; }
+
+template <int LOG2L>
+void launch_fft_passes(const ea::FftArgs &a, hipStream_t stream)
+{
+    constexpr int L = 1 << LOG2L;
+    const dim3 grid((unsigned)(L * L / ea::FftShape<LOG2L>::B)), block(ea::kFftThreads);
+    hipLaunchKernelGGL((ea::fft_pass_kernel<LOG2L, ea::kFftFwdBitsX>), grid, block, 0, stream, a);
+    hipLaunchKernelGGL((ea::fft_pass_kernel<LOG2L, ea::kFftFwdY>), grid, block, 0, stream, a);
+    hipLaunchKernelGGL((ea::fft_pass_kernel<LOG2L, ea::kFftSquareZ>), grid, block, 0, stream, a);
+    hipLaunchKernelGGL((ea::fft_pass_kernel<LOG2L, ea::kFftInvY>), grid, block, 0, stream, a);
+    hipLaunchKernelGGL((ea::fft_pass_kernel<LOG2L, ea::kFftInvBinX>), grid, block, 0, stream, a);
+}
+
+// Shell sums of dense overlap rows (dw words per row) through the FFT route
+// (ea_fft.h), added to `shells`; `work` holds fft_work_bytes(L) bytes.
+ea_status launch_fft_shells(const unsigned long long *qd, int dw, int L, int n_shells, unsigned long long *shells,
+                            void *work, hipStream_t stream)
+{
+    ea::FftArgs a{};
+    a.z = (double2 *)work;
+    a.qd = qd;
+    a.dw = dw;
+    a.n_shells = n_shells;
+    a.shells = shells;
+    unsigned long long *err = (unsigned long long *)((char *)work + 16 * (size_t)L * L * L);
+    a.err = (unsigned int *)err;
+    hipLaunchKernelGGL(ea::zero_u64_kernel, dim3(1), dim3(256), 0, stream, err, (size_t)1);
+    switch (log2_pow2(L)) {
+    case 3: launch_fft_passes<3>(a, stream); break;
+    case 4: launch_fft_passes<4>(a, stream); break;
+    case 5: launch_fft_passes<5>(a, stream); break;
+    case 6: launch_fft_passes<6>(a, stream); break;
+    case 7: launch_fft_passes<7>(a, stream); break;
+    case 8: launch_fft_passes<8>(a, stream); break;
+    default: return fail(EA_ERR_ARG, "the FFT route of full-vector C4 needs a power-of-two L in 8..256 (L=%d)", L);
+    }
+    EA_HIP(hipGetLastError());
+    return EA_OK;
+}
+
+// After the stream has passed launch_fft_shells: EA_ERR_DEVICE if a sum was
+// not within 1/4 of an integer (it never is within the fp64 error bound).
+ea_status fft_shells_check(const void *work, int L, hipStream_t stream)
+{
+    uint32_t e = 0;
+    EA_HIP(hipMemcpyAsync(&e, (const char *)work + 16 * (size_t)L * L * L, 4, hipMemcpyDeviceToHost, stream));
+    EA_HIP(hipStreamSynchronize(stream));
+    if (e) return fail(EA_ERR_DEVICE, "full-vector C4 (FFT route, L=%d): a correlation sum was not an integer", L);
+    return EA_OK;
+}
+
 void host_thresholds(double T, uint32_t out[3])
 {
     for (int k = 1; k <= 3; ++k) {
@@ -879,6 +955,7 @@ void ea_destroy(ea_sim *s)
     if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
     if (s->graph) (void)hipGraphDestroy(s->graph);
     if (s->c4_scratch) (void)hipFree(s->c4_scratch);
+    if (s->fft_work) (void)hipFree(s->fft_work);
     if (s->group_event) (void)hipEventDestroy(s->group_event);
     if (s->own_buf && s->buf) (void)hipFree(s->buf);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
@@ -1123,7 +1200,19 @@ ea_status ea_c4_shells(ea_sim *s, int32_t n_shells, int64_t *out)
     ea::Geom g = s->geom();
     EA_DISPATCH_W(s->lay.W, hipLaunchKernelGGL((ea::dense_q_kernel<WW>), dim3(blocks_for(q_words)), dim3(256), 0,
                                                s->stream, s->lat, g, dw, qd));
-    if (nw <= 2) {
+    const bool fft = shells_by_fft(L);
+    if (fft) {
+        if (!s->fft_work) {
+            hipError_t e = hipMalloc(&s->fft_work, fft_work_bytes(L));
+            if (e != hipSuccess) {
+                s->fft_work = nullptr;
+                return fail(EA_ERR_NOMEM, "hipMalloc(c4 FFT work, %zu bytes): %s", fft_work_bytes(L),
+                            hipGetErrorString(e));
+            }
+        }
+        ea_status st = launch_fft_shells(qd, dw, L, n_shells, shells, s->fft_work, s->stream);
+        if (st != EA_OK) return st;
+    } else if (nw <= 2) {
         const dim3 grid((unsigned)((L + ea::kShellRx - 1) / ea::kShellRx), (unsigned)(L * L));
         if (nw == 1)
             hipLaunchKernelGGL((ea::c4_shell_kernel<1>), grid, dim3(256), 0, s->stream, qd, L, n_shells, shells);
@@ -1135,7 +1224,23 @@ ea_status ea_c4_shells(ea_sim *s, int32_t n_shells, int64_t *out)
     }
     EA_HIP(hipGetLastError());
     EA_HIP(hipMemcpyAsync(out, shells, 8 * (size_t)n_shells, hipMemcpyDeviceToHost, s->stream));
+    if (fft) return fft_shells_check(s->fft_work, L, s->stream);
     EA_HIP(hipStreamSynchronize(s->stream));
+    return EA_OK;
+}
+
+ea_status ea_set_shell_route(int32_t route)
+{
+    if (route != EA_SHELLS_AUTO && route != EA_SHELLS_DIRECT && route != EA_SHELLS_FFT)
+        return fail(EA_ERR_ARG, "unknown shell route %d", route);
+    g_shell_route.store(route);
+    return EA_OK;
+}
+
+ea_status ea_get_shell_route(int32_t *route)
+{
+    if (!route) return fail(EA_ERR_ARG, "NULL argument");
+    *route = g_shell_route.load();
     return EA_OK;
 }
 

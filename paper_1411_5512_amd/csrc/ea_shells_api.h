@@ -14,30 +14,40 @@ struct CallScratch {
     }
 };
 
-// Zero the shells, sum them from the dense rows, copy them to the host and
-// wait.
-ea_status shells_to_host(const unsigned long long *qd, unsigned long long *shells, int L, int n_shells, int64_t *out,
-                         hipStream_t stream)
+// Sum the shells from the dense rows (FFT route for power-of-two L unless
+// ea_set_shell_route says otherwise, else the rows kernel), copy them to the
+// host and wait.
+ea_status shells_to_host(const unsigned long long *qd, int dw, unsigned long long *shells, void *fft_work, int L,
+                         int n_shells, int64_t *out, hipStream_t stream)
 {
-    ea_status st = launch_shell_rows(qd, L, n_shells, shells, stream);
+    const bool fft = fft_work != nullptr;
+    ea_status st = fft ? launch_fft_shells(qd, dw, L, n_shells, shells, fft_work, stream)
+                       : launch_shell_rows(qd, L, n_shells, shells, stream);
     if (st != EA_OK) return st;
     EA_HIP(hipMemcpyAsync(out, shells, 8 * (size_t)n_shells, hipMemcpyDeviceToHost, stream));
+    if (fft) return fft_shells_check(fft_work, L, stream);
     EA_HIP(hipStreamSynchronize(stream));
     return EA_OK;
 }
 
+// One allocation for the call: the dense rows, the shells and (FFT route)
+// the complex array; the shells zeroed on `stream`.
 ea_status shell_scratch(CallScratch &sc, int L, int n_shells, unsigned long long **qd, unsigned long long **shells,
-                        int *dw, hipStream_t stream)
+                        void **fft_work, int *dw, hipStream_t stream)
 {
     *dw = 2 * ((L + 63) / 64);
     const size_t q_words = (size_t)L * L * (size_t)*dw;
-    const hipError_t e = hipMalloc((void **)&sc.p, 8 * (q_words + (size_t)n_shells));
+    const size_t fft_bytes = shells_by_fft(L) ? fft_work_bytes(L) : 0;
+    const size_t words = q_words + (size_t)n_shells, head = (8 * words + 255) / 256 * 256;
+    const hipError_t e = hipMalloc((void **)&sc.p, head + fft_bytes);
     if (e != hipSuccess) {
         sc.p = nullptr;
-        return fail(EA_ERR_NOMEM, "hipMalloc(C4 shell scratch): %s", hipGetErrorString(e));
+        return fail(EA_ERR_NOMEM, "hipMalloc(C4 shell scratch, %zu bytes): %s", head + fft_bytes,
+                    hipGetErrorString(e));
     }
     *qd = sc.p;
     *shells = sc.p + q_words;
+    *fft_work = fft_bytes ? (void *)((char *)sc.p + head) : nullptr;
     hipLaunchKernelGGL(ea::zero_u64_kernel, dim3(blocks_for((size_t)n_shells)), dim3(256), 0, stream, *shells,
                        (size_t)n_shells);
     EA_HIP(hipGetLastError());
@@ -62,8 +72,9 @@ ea_status ea_batch_c4_shells(ea_batch *b, int32_t job, int32_t k, int32_t n_shel
         return fail(EA_ERR_ARG, "n_shells=%d outside [1, %d]", n_shells, max_shells);
     CallScratch sc;
     unsigned long long *qd = nullptr, *shells = nullptr;
+    void *fft_work = nullptr;
     int dw = 0;
-    ea_status st = shell_scratch(sc, L, n_shells, &qd, &shells, &dw, b->stream);
+    ea_status st = shell_scratch(sc, L, n_shells, &qd, &shells, &fft_work, &dw, b->stream);
     if (st != EA_OK) return st;
     // the configuration published at measurement k: [replica][colour][POS]
     ea::Lattice lat{};
@@ -78,7 +89,7 @@ ea_status ea_batch_c4_shells(ea_batch *b, int32_t job, int32_t k, int32_t n_shel
     EA_DISPATCH_W(h.W, hipLaunchKernelGGL((ea::dense_q_kernel<WW>), dim3(blocks_for(q_words)), dim3(256), 0,
                                           b->stream, lat, g, dw, qd));
     EA_HIP(hipGetLastError());
-    return shells_to_host(qd, shells, L, n_shells, out, b->stream);
+    return shells_to_host(qd, dw, shells, fft_work, L, n_shells, out, b->stream);
 }
 
 ea_status ea_msc_c4_shells(ea_msc *m, int32_t sample, int32_t n_shells, int64_t *out)
@@ -91,14 +102,15 @@ ea_status ea_msc_c4_shells(ea_msc *m, int32_t sample, int32_t n_shells, int64_t 
         return fail(EA_ERR_ARG, "n_shells=%d outside [1, %d]", n_shells, max_shells);
     CallScratch sc;
     unsigned long long *qd = nullptr, *shells = nullptr;
+    void *fft_work = nullptr;
     int dw = 0;
-    ea_status st = shell_scratch(sc, L, n_shells, &qd, &shells, &dw, m->stream);
+    ea_status st = shell_scratch(sc, L, n_shells, &qd, &shells, &fft_work, &dw, m->stream);
     if (st != EA_OK) return st;
     const size_t q_words = (size_t)L * L * (size_t)dw;
     hipLaunchKernelGGL(ea::msc_dense_q_kernel, dim3(blocks_for(q_words)), dim3(256), 0, m->stream, m->lat, m->geom,
                        m->M, sample / m->M, sample % m->M, dw, qd);
     EA_HIP(hipGetLastError());
-    return shells_to_host(qd, shells, L, n_shells, out, m->stream);
+    return shells_to_host(qd, dw, shells, fft_work, L, n_shells, out, m->stream);
 }
 
 }  // extern "C"

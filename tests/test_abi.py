@@ -115,3 +115,23 @@ def test_debug_mode_flags(ealib):
     finally:
         ea.set_debug(0, 0)
     assert ea.get_debug() == (0, 0)
+
+
+def test_shell_route_setting(ealib):
+    """ea_set_shell_route / ea_get_shell_route: the three routes are kept
+    process-wide, another value is rejected and leaves the route unchanged
+    (host only: no launch)."""
+    import paper_1411_5512_amd as ea
+    try:
+        assert ea.get_shell_route() == ea.SHELLS_AUTO
+        ea.set_shell_route(ea.SHELLS_FFT)
+        assert ea.get_shell_route() == ea.SHELLS_FFT
+        for bad in (-1, 3):
+            with pytest.raises(ea.EAError):
+                ea.set_shell_route(bad)
+        assert ea.get_shell_route() == ea.SHELLS_FFT
+        ea.set_shell_route(ea.SHELLS_DIRECT)
+        assert ea.get_shell_route() == ea.SHELLS_DIRECT
+    finally:
+        ea.set_shell_route(ea.SHELLS_AUTO)
+    assert ea.get_shell_route() == ea.SHELLS_AUTO
