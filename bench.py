@@ -242,7 +242,7 @@ def alu_probe():
     return out
 
 
-def shells_probe(ea, sizes=(32, 64, 128, 256), reps=3):
+def shells_probe(ea, sizes=(32, 64, 128, 256), reps=3, direct=True):
     """Wall time of one full-vector C4 call (ea_c4_shells over every
     displacement, synchronous) by the FFT route and by the direct route, on
     a quenched run of each size after 20 sweeps; the two results must be
@@ -255,7 +255,8 @@ def shells_probe(ea, sizes=(32, 64, 128, 256), reps=3):
             g.sweep(20)
             n_all = 3 * (L // 2) ** 2 + 1
             row, res = {}, {}
-            for name, route in (("fft", ea.SHELLS_FFT), ("direct", ea.SHELLS_DIRECT)):
+            routes = (("fft", ea.SHELLS_FFT), ("direct", ea.SHELLS_DIRECT)) if direct else (("fft", ea.SHELLS_FFT),)
+            for name, route in routes:
                 ea.set_shell_route(route)
                 res[name] = g.c4_shells(n_all)
                 best = float("inf")
@@ -264,9 +265,10 @@ def shells_probe(ea, sizes=(32, 64, 128, 256), reps=3):
                     g.c4_shells(n_all)
                     best = min(best, time.perf_counter() - t0)
                 row[f"{name}_ms"] = round(best * 1e3, 3)
-            if not (res["fft"] == res["direct"]).all():
-                raise RuntimeError(f"full-vector C4 routes differ at L={L}")
-            row["speedup"] = round(row["direct_ms"] / row["fft_ms"], 1)
+            if direct:
+                if not (res["fft"] == res["direct"]).all():
+                    raise RuntimeError(f"full-vector C4 routes differ at L={L}")
+                row["speedup"] = round(row["direct_ms"] / row["fft_ms"], 1)
             out[f"L{L}"] = row
             print(json.dumps({"shells_probe_progress": L, **row}), flush=True)
             g.close()
@@ -496,6 +498,8 @@ def main():
     ap.add_argument("--shells-probe", action="store_true",
                     help="only time the full-vector C4 shells (every displacement) by the FFT and the direct "
                          "route at L = 32, 64, 128, 256, check that they agree, and exit")
+    ap.add_argument("--shells-probe-l", type=int, default=0, help="with --shells-probe: this L only")
+    ap.add_argument("--shells-fft-only", action="store_true", help="with --shells-probe: the FFT route only")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (a known-size kernel "
                          "for calibrating hardware byte counters) and exit")
@@ -519,7 +523,8 @@ def main():
         return
 
     if args.shells_probe:
-        print(json.dumps({"shells_probe": shells_probe(ea)}), flush=True)
+        sizes = (args.shells_probe_l,) if args.shells_probe_l else (32, 64, 128, 256)
+        print(json.dumps({"shells_probe": shells_probe(ea, sizes, direct=not args.shells_fft_only)}), flush=True)
         return
 
     if args.copy_probe_mib:

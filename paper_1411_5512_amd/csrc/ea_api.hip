@@ -715,13 +715,15 @@ size_t fft_work_bytes(int L) { return 16 * (size_t)L * L * L + 256; }
 template <int LOG2L>
 void launch_fft_passes(const ea::FftArgs &a, hipStream_t stream)
 {
-    constexpr int L = 1 << LOG2L;
-    const dim3 grid((unsigned)(L * L / ea::FftShape<LOG2L>::B)), block(ea::kFftThreads);
+    constexpr int L = 1 << LOG2L, H = L / 2, B = ea::FftShape<LOG2L>::B;
+    const dim3 grid((unsigned)(L * L / B)), block(ea::kFftThreads);
+    const dim3 half((unsigned)((H + 1) * (L / B)));  // tiles of the planes z <= L/2
+    const dim3 bins((unsigned)((H + 1) * ((H + ea::kFftBinY) / ea::kFftBinY)));
     hipLaunchKernelGGL((ea::fft_pass_kernel<LOG2L, ea::kFftFwdBitsX>), grid, block, 0, stream, a);
     hipLaunchKernelGGL((ea::fft_pass_kernel<LOG2L, ea::kFftFwdY>), grid, block, 0, stream, a);
     hipLaunchKernelGGL((ea::fft_pass_kernel<LOG2L, ea::kFftSquareZ>), grid, block, 0, stream, a);
-    hipLaunchKernelGGL((ea::fft_pass_kernel<LOG2L, ea::kFftInvY>), grid, block, 0, stream, a);
-    hipLaunchKernelGGL((ea::fft_pass_kernel<LOG2L, ea::kFftInvBinX>), grid, block, 0, stream, a);
+    hipLaunchKernelGGL((ea::fft_pass_kernel<LOG2L, ea::kFftInvY>), half, block, 0, stream, a);
+    hipLaunchKernelGGL((ea::fft_bin_kernel<LOG2L>), bins, block, 0, stream, a);
 }
 
 // Shell sums of dense overlap rows (dw words per row) through the FFT route

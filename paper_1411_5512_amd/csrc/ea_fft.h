@@ -9,7 +9,8 @@
 // The forward transforms are decimation in frequency (natural order in,
 // bit-reversed order out along each axis) and the inverse ones decimation in
 // time (bit-reversed in, natural out); |F|^2 is taken pointwise in between,
-// so no pass permutes its data.  The sums are integers of magnitude <= N and
+// so no pass permutes its data.  The autocorrelation is even, so the last two
+// passes transform only the planes z <= L/2.  The sums are integers of magnitude <= N and
 // the rounding error of the fp64 transforms is ~1e-16 log2(N) of the largest
 // |F|^2 (<= N^2), i.e. below 1e-7 after the division by N at L = 256: each
 // sum is rounded to the nearest integer, and a sum found farther than 1/4
@@ -25,7 +26,7 @@ constexpr int kFftThreads = 256;
 
 // The passes, in order: forward along x from the dense q rows, forward along
 // y, forward along z + |.|^2 + inverse along z, inverse along y, inverse along
-// x + rounding and shell sums.
+// x + rounding and shell sums (fft_bin_kernel).
 enum FftOp { kFftFwdBitsX = 0, kFftFwdY = 1, kFftSquareZ = 2, kFftInvY = 3, kFftInvBinX = 4 };
 
 struct FftArgs {
@@ -51,47 +52,114 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 w)
     return make_double2(a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x);
 }
 
-// One radix-2 stage of span h = 2^s on every line of the tile.  DIF: (a, b)
-// -> (a + b, (a - b) w); DIT: t = b w, (a, b) -> (a + t, a - t); w =
-// exp(-+2 pi i pos / 2h) from the table tw[m] = exp(-2 pi i m / L).
-template <int LOG2L, bool DIT>
-__device__ __forceinline__ void fft_stage(double2 *s, const double2 *tw, int st, int tid)
+__device__ __forceinline__ double2 cmulc(double2 a, double2 w)  // a conj(w)
 {
-    using S = FftShape<LOG2L>;
-    constexpr int H = S::L / 2;
+    return make_double2(a.x * w.x + a.y * w.y, a.y * w.x - a.x * w.y);
+}
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+
+// One radix-2 stage of span h = 2^st on the NL lines of a tile (stride LP).
+// DIF: (a, b) -> (a + b, (a - b) w); DIT: t = b conj(w), (a, b) -> (a + t,
+// a - t); w = exp(-2 pi i pos / 2h) = tw[pos L / 2h] from the table tw[m] =
+// exp(-2 pi i m / L).
+template <int LOG2L, int NL, bool DIT>
+__device__ __forceinline__ void fft_stage2(double2 *s, const double2 *tw, int st, int tid)
+{
+    constexpr int L = 1 << LOG2L, H = L / 2, LP = L + 1;
     const int h = 1 << st;
-    for (int t = tid; t < S::B * H; t += kFftThreads) {
+    for (int t = tid; t < NL * H; t += kFftThreads) {
         const int b = t >> (LOG2L - 1), kk = t & (H - 1);
         const int pos = kk & (h - 1);
-        const int i0 = ((kk >> st) << (st + 1)) | pos;
-        double2 w = tw[pos << (LOG2L - 1 - st)];
-        double2 *p0 = s + b * S::LP + i0, *p1 = p0 + h;
-        const double2 a = *p0, c = *p1;
+        double2 *p0 = s + b * LP + (((kk >> st) << (st + 1)) | pos), *p1 = p0 + h;
+        const double2 w = tw[pos << (LOG2L - 1 - st)];
+        const double2 x0 = *p0, x1 = *p1;
         if constexpr (DIT) {
-            w.y = -w.y;
-            const double2 u = cmul(c, w);
-            *p0 = make_double2(a.x + u.x, a.y + u.y);
-            *p1 = make_double2(a.x - u.x, a.y - u.y);
+            const double2 u = cmulc(x1, w);
+            *p0 = cadd(x0, u);
+            *p1 = csub(x0, u);
         } else {
-            *p0 = make_double2(a.x + c.x, a.y + c.y);
-            *p1 = cmul(make_double2(a.x - c.x, a.y - c.y), w);
+            *p0 = cadd(x0, x1);
+            *p1 = cmul(csub(x0, x1), w);
         }
     }
 }
 
-template <int LOG2L, bool DIT>
+// Two radix-2 stages, of spans 2h and h (h = 2^sl), in registers on each
+// quad {p, p + h, p + 2h, p + 3h}, p = g 4h + pos, pos < h: the span-2h
+// butterflies pair (p, p + 2h) at position pos and (p + h, p + 3h) at pos + h,
+// the span-h ones (p, p + h) and (p + 2h, p + 3h), both at pos.  DIF takes
+// span 2h first, DIT span h first; the same as the two radix-2 stages in
+// turn, with half the LDS traffic and barriers.
+template <int LOG2L, int NL, bool DIT>
+__device__ __forceinline__ void fft_stage4(double2 *s, const double2 *tw, int sl, int tid)
+{
+    constexpr int L = 1 << LOG2L, Q = L / 4, LP = L + 1;
+    const int h = 1 << sl;
+    for (int t = tid; t < NL * Q; t += kFftThreads) {
+        const int b = t >> (LOG2L - 2), kk = t & (Q - 1);
+        const int pos = kk & (h - 1);
+        double2 *p = s + b * LP + (((kk >> sl) << (sl + 2)) | pos);
+        const double2 wa0 = tw[pos << (LOG2L - 2 - sl)], wa1 = tw[(pos + h) << (LOG2L - 2 - sl)];
+        const double2 wb = tw[pos << (LOG2L - 1 - sl)];
+        const double2 x0 = p[0], x1 = p[h], x2 = p[2 * h], x3 = p[3 * h];
+        if constexpr (DIT) {
+            const double2 u1 = cmulc(x1, wb), u3 = cmulc(x3, wb);
+            const double2 y0 = cadd(x0, u1), y1 = csub(x0, u1), y2 = cadd(x2, u3), y3 = csub(x2, u3);
+            const double2 v2 = cmulc(y2, wa0), v3 = cmulc(y3, wa1);
+            p[0] = cadd(y0, v2);
+            p[2 * h] = csub(y0, v2);
+            p[h] = cadd(y1, v3);
+            p[3 * h] = csub(y1, v3);
+        } else {
+            const double2 y0 = cadd(x0, x2), y2 = cmul(csub(x0, x2), wa0);
+            const double2 y1 = cadd(x1, x3), y3 = cmul(csub(x1, x3), wa1);
+            p[0] = cadd(y0, y1);
+            p[h] = cmul(csub(y0, y1), wb);
+            p[2 * h] = cadd(y2, y3);
+            p[3 * h] = cmul(csub(y2, y3), wb);
+        }
+    }
+}
+
+// The whole transform of the NL lines: DIF spans L/2 .. 1 (natural order in,
+// bit-reversed out), DIT spans 1 .. L/2 (bit-reversed in, natural out), two
+// stages per round and a radix-2 stage for odd log2 L; ends with a barrier.
+template <int LOG2L, int NL, bool DIT>
 __device__ __forceinline__ void fft_lines(double2 *s, const double2 *tw, int tid)
 {
     if constexpr (DIT) {
-        for (int st = 0; st < LOG2L; ++st) {
-            fft_stage<LOG2L, true>(s, tw, st, tid);
+        int st = 0;
+        for (; st + 1 < LOG2L; st += 2) {
+            fft_stage4<LOG2L, NL, true>(s, tw, st, tid);
+            __syncthreads();
+        }
+        if (st < LOG2L) {
+            fft_stage2<LOG2L, NL, true>(s, tw, st, tid);
             __syncthreads();
         }
     } else {
-        for (int st = LOG2L - 1; st >= 0; --st) {
-            fft_stage<LOG2L, false>(s, tw, st, tid);
+        int st = LOG2L - 1;
+        for (; st >= 1; st -= 2) {
+            fft_stage4<LOG2L, NL, false>(s, tw, st - 1, tid);
             __syncthreads();
         }
+        if (st == 0) {
+            fft_stage2<LOG2L, NL, false>(s, tw, 0, tid);
+            __syncthreads();
+        }
+    }
+}
+
+template <int LOG2L>
+__device__ __forceinline__ void fft_twiddles(double2 *tw, int tid)
+{
+    constexpr int L = 1 << LOG2L;
+    for (int m = tid; m < L / 2; m += kFftThreads) {
+        double sn, cs;
+        sincospi(2.0 * (double)m / (double)L, &sn, &cs);
+        tw[m] = make_double2(cs, -sn);
     }
 }
 
@@ -116,22 +184,22 @@ __device__ __forceinline__ void fft_element(int w, int j, int &b, int &i, size_t
     }
 }
 
-// One pass (FftOp) over the L^2 / B tiles, one per workgroup.
+// Passes kFftFwdBitsX .. kFftInvY, one tile per workgroup: L^2 / B tiles,
+// except kFftInvY, which needs only the planes z <= L/2 ((L/2 + 1) L / B
+// tiles; kFftSquareZ stores only those): the autocorrelation is even, A(-r)
+// = A(r), so the shells follow from half of it (fft_bin_kernel).
 template <int LOG2L, int OP>
 __global__ __launch_bounds__(kFftThreads) void fft_pass_kernel(FftArgs a)
 {
     using S = FftShape<LOG2L>;
     constexpr int L = S::L, B = S::B, TILE = B * L;
-    constexpr int AXIS = OP == kFftFwdBitsX || OP == kFftInvBinX ? 0 : (OP == kFftSquareZ ? 2 : 1);
+    constexpr int AXIS = OP == kFftFwdBitsX ? 0 : (OP == kFftSquareZ ? 2 : 1);
+    static_assert(OP != kFftInvBinX, "the last pass is fft_bin_kernel");
     __shared__ double2 s[B * S::LP];
     __shared__ double2 tw[L / 2];
     const int tid = (int)threadIdx.x, w = (int)blockIdx.x;
 
-    for (int m = tid; m < L / 2; m += kFftThreads) {
-        double sn, cs;
-        sincospi(2.0 * (double)m / (double)L, &sn, &cs);
-        tw[m] = make_double2(cs, -sn);
-    }
+    fft_twiddles<LOG2L>(tw, tid);
     for (int j = tid; j < TILE; j += kFftThreads) {
         int b, i;
         size_t pos;
@@ -149,51 +217,80 @@ __global__ __launch_bounds__(kFftThreads) void fft_pass_kernel(FftArgs a)
     __syncthreads();
 
     if constexpr (OP == kFftFwdBitsX || OP == kFftFwdY) {
-        fft_lines<LOG2L, false>(s, tw, tid);
+        fft_lines<LOG2L, B, false>(s, tw, tid);
     } else if constexpr (OP == kFftSquareZ) {
-        fft_lines<LOG2L, false>(s, tw, tid);
+        fft_lines<LOG2L, B, false>(s, tw, tid);
         for (int j = tid; j < TILE; j += kFftThreads) {
             double2 *p = s + (j >> LOG2L) * S::LP + (j & (L - 1));
             const double2 v = *p;
             *p = make_double2(v.x * v.x + v.y * v.y, 0.0);
         }
         __syncthreads();
-        fft_lines<LOG2L, true>(s, tw, tid);
+        fft_lines<LOG2L, B, true>(s, tw, tid);
     } else {
-        fft_lines<LOG2L, true>(s, tw, tid);
+        fft_lines<LOG2L, B, true>(s, tw, tid);
     }
 
-    if constexpr (OP != kFftInvBinX) {
-        for (int j = tid; j < TILE; j += kFftThreads) {
-            int b, i;
-            size_t pos;
-            fft_element<LOG2L, AXIS>(w, j, b, i, pos);
-            a.z[pos] = s[b * S::LP + i];
-        }
-    } else {
-        // rows w B .. w B + B - 1: row y + L z holds N sum_x q(x) q(x + r) at
-        // r = (i, y, z).  Displacements i and L - i share a shell: one atomic
-        // for both.
-        constexpr int HALF = L / 2 + 1;
-        for (int t = tid; t < B * HALF; t += kFftThreads) {
-            const int b = t / HALF, i = t - b * HALF;
-            const int row = w * B + b, y = row & (L - 1), z = row >> LOG2L;
-            const int my = y < L - y ? y : L - y, mz = z < L - z ? z : L - z;
-            const int k = i * i + my * my + mz * mz;
-            if (k >= a.n_shells) continue;
-            long long sum = 0;
-            bool bad = false;
+    for (int j = tid; j < TILE; j += kFftThreads) {
+        int b, i;
+        size_t pos;
+        fft_element<LOG2L, AXIS>(w, j, b, i, pos);
+        if (OP == kFftSquareZ && i > L / 2) continue;
+        a.z[pos] = s[b * S::LP + i];
+    }
+}
+
+constexpr int kFftBinY = 4;  // y values per workgroup of the last pass
+
+// The last pass, on the planes z = 0 .. L/2: a workgroup takes kFftBinY
+// values y <= L/2 of one z and, for each, the rows y and L - y (one row if y
+// is 0 or L/2), transforms them along x (DIT), and for every |x| = i <= L/2
+// adds the rounded sums at x = +-i of both rows to the shell i^2 + y^2 + z^2
+// (these are the minimum images) in one atomic.  A row (y, z) and the row
+// (L - y, L - z) hold A(x, y, z) and A(-x, y, z), so for 0 < z < L/2 the
+// sums count twice for the planes L - z that are not transformed.
+template <int LOG2L>
+__global__ __launch_bounds__(kFftThreads) void fft_bin_kernel(FftArgs a)
+{
+    constexpr int L = 1 << LOG2L, H = L / 2, LP = L + 1, NL = 2 * kFftBinY;
+    constexpr int YB = (H + 1 + kFftBinY - 1) / kFftBinY;  // workgroups per plane
+    __shared__ double2 s[NL * LP];
+    __shared__ double2 tw[H];
+    const int tid = (int)threadIdx.x, w = (int)blockIdx.x;
+    const int z = w / YB, y0 = (w - z * YB) * kFftBinY;
+
+    fft_twiddles<LOG2L>(tw, tid);
+    // line 2j: row (y0 + j, z); line 2j + 1: row (L - y0 - j, z) if 0 < y0 + j < L/2
+    for (int j = tid; j < NL * L; j += kFftThreads) {
+        const int line = j >> LOG2L, x = j & (L - 1), y = y0 + (line >> 1);
+        const bool mirror = (line & 1) != 0;
+        double2 v = make_double2(0.0, 0.0);
+        if (y <= H && (!mirror || (y != 0 && y != H)))
+            v = a.z[((size_t)z * L + (size_t)(mirror ? L - y : y)) * L + (size_t)x];
+        s[line * LP + x] = v;
+    }
+    __syncthreads();
+    fft_lines<LOG2L, NL, true>(s, tw, tid);
+
+    const long long weight = (z == 0 || z == H) ? 1 : 2;
+    for (int t = tid; t < kFftBinY * (H + 1); t += kFftThreads) {
+        const int j = t / (H + 1), i = t - j * (H + 1), y = y0 + j;
+        if (y > H) continue;
+        const int k = i * i + y * y + z * z;
+        if (k >= a.n_shells) continue;
+        long long sum = 0;
+        bool bad = false;
 #pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                if (e == 1 && (i == 0 || i == L / 2)) break;
-                const double v = ldexp(s[b * S::LP + (e ? L - i : i)].x, -3 * LOG2L);
-                const double r = rint(v);
-                bad |= !(fabs(v - r) <= 0.25);  // NaN included
-                sum += (long long)r;
-            }
-            if (bad) atomicOr(a.err, 1u);
-            atomicAdd(a.shells + k, (unsigned long long)sum);
+        for (int e = 0; e < 4; ++e) {  // bit 0: x -> L - x, bit 1: y -> L - y
+            if ((e & 1) && (i == 0 || i == H)) continue;
+            if ((e & 2) && (y == 0 || y == H)) continue;
+            const double v = ldexp(s[(2 * j + (e >> 1)) * LP + ((e & 1) ? L - i : i)].x, -3 * LOG2L);
+            const double r = rint(v);
+            bad |= !(fabs(v - r) <= 0.25);  // NaN included
+            sum += (long long)r;
         }
+        if (bad) atomicOr(a.err, 1u);
+        atomicAdd(a.shells + k, (unsigned long long)(sum * weight));
     }
 }
 
