@@ -371,8 +371,9 @@ ea_status ea_batch_result(ea_batch *b, int32_t job, int32_t k, ea_obs *out);
 /* Full-vector C4 shells (as ea_c4_shells, eq. 3 over every displacement) of
  * job `job` at its measurement k, from the configuration of both replicas
  * that the batched kernel publishes at each measurement: out[n_shells].
- * Synchronises; allocates and frees a scratch buffer of
- * 8 (2 L^2 + n_shells) bytes for the call (16 L^3 more on the FFT route).  EA_ERR_ARG for a job or k out of
+ * Synchronises; allocates a scratch buffer of 8 (2 L^2 ceil(L/64) +
+ * n_shells) bytes (16 L^3 more on the FFT route) on the first call, grown
+ * when a later call needs more, kept until ea_batch_destroy.  EA_ERR_ARG for a job or k out of
  * range or n_shells outside [1, 3 (L/2)^2 + 1]; EA_ERR_STATE if measurement
  * k has not been reached. */
 ea_status ea_batch_c4_shells(ea_batch *b, int32_t job, int32_t k, int32_t n_shells, int64_t *out);
@@ -535,9 +536,10 @@ ea_status ea_msc_snapshot(ea_msc *batch, int32_t slot);
 ea_status ea_msc_measure(ea_msc *batch, ea_obs *out);
 
 /* Full-vector C4 shells (as ea_c4_shells) of sample `sample` (0 .. B-1) of
- * the batch at the current time: out[n_shells].  Synchronises; allocates and
- * frees a scratch buffer of 8 (2 L^2 ceil(L/64) + n_shells) bytes for the
- * call (16 L^3 more on the FFT route).  EA_ERR_ARG for a sample out of range or n_shells outside
+ * the batch at the current time: out[n_shells].  Synchronises; allocates a
+ * scratch buffer of 8 (2 L^2 ceil(L/64) + n_shells) bytes (16 L^3 more on
+ * the FFT route) on the first call, grown when a later call needs more, kept
+ * until ea_msc_destroy.  EA_ERR_ARG for a sample out of range or n_shells outside
  * [1, 3 (L/2)^2 + 1]. */
 ea_status ea_msc_c4_shells(ea_msc *m, int32_t sample, int32_t n_shells, int64_t *out);
 

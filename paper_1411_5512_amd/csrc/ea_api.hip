@@ -709,6 +709,36 @@ bool shells_by_fft(int L)
     return r == EA_SHELLS_FFT || L >= kFftAutoMinL;
 }
 
+// Device scratch of a handle's full-vector C4 calls (ea_batch_c4_shells,
+// ea_msc_c4_shells): allocated on the first call, grown when a call needs
+// more, freed with the handle.  The calls synchronise before they return, so
+// the next call may reuse it.
+struct ShellScratch {
+    void *p = nullptr;
+    size_t bytes = 0;
+    ShellScratch() = default;
+    ShellScratch(const ShellScratch &) = delete;
+    ShellScratch &operator=(const ShellScratch &) = delete;
+    ~ShellScratch()
+    {
+        if (p) (void)hipFree(p);
+    }
+    ea_status reserve(size_t n)
+    {
+        if (n <= bytes) return EA_OK;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        const hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) {
+            p = nullptr;
+            return fail(EA_ERR_NOMEM, "hipMalloc(C4 shell scratch, %zu bytes): %s", n, hipGetErrorString(e));
+        }
+        bytes = n;
+        return EA_OK;
+    }
+};
+
 // Device bytes of the FFT route: the complex array, then the error word.
 size_t fft_work_bytes(int L) { return 16 * (size_t)L * L * L + 256; }
 

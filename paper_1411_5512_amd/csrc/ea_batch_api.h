@@ -464,6 +464,7 @@ void choose_split(std::vector<BatchJobHost> &jobs, int n_cu, bool always)
 
 struct ea_batch {
     std::vector<BatchJobHost> jobs;
+    ShellScratch shell_scratch;  // ea_batch_c4_shells
     hipStream_t stream = nullptr;
     bool own_stream = false;
     char *buf = nullptr;

@@ -5,6 +5,7 @@
 #include "ea_msc_kernels.h"
 
 struct ea_msc {
+    ShellScratch shell_scratch;  // ea_msc_c4_shells
     int L = 0, B = 0, M = 0, S = 0, G = 0;
     ea::MscGeom geom{};
     double p = 0, T = 0;

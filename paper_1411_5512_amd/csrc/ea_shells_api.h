@@ -5,15 +5,6 @@
 
 namespace {
 
-// A device buffer for one call, freed on every return path.
-struct CallScratch {
-    unsigned long long *p = nullptr;
-    ~CallScratch()
-    {
-        if (p) (void)hipFree(p);
-    }
-};
-
 // Sum the shells from the dense rows (FFT route for power-of-two L unless
 // ea_set_shell_route says otherwise, else the rows kernel), copy them to the
 // host and wait.
@@ -30,23 +21,20 @@ ea_status shells_to_host(const unsigned long long *qd, int dw, unsigned long lon
     return EA_OK;
 }
 
-// One allocation for the call: the dense rows, the shells and (FFT route)
-// the complex array; the shells zeroed on `stream`.
-ea_status shell_scratch(CallScratch &sc, int L, int n_shells, unsigned long long **qd, unsigned long long **shells,
+// The call's scratch in the handle's buffer: the dense rows, the shells and
+// (FFT route) the complex array; the shells zeroed on `stream`.
+ea_status shell_scratch(ShellScratch &sc, int L, int n_shells, unsigned long long **qd, unsigned long long **shells,
                         void **fft_work, int *dw, hipStream_t stream)
 {
     *dw = 2 * ((L + 63) / 64);
     const size_t q_words = (size_t)L * L * (size_t)*dw;
     const size_t fft_bytes = shells_by_fft(L) ? fft_work_bytes(L) : 0;
     const size_t words = q_words + (size_t)n_shells, head = (8 * words + 255) / 256 * 256;
-    const hipError_t e = hipMalloc((void **)&sc.p, head + fft_bytes);
-    if (e != hipSuccess) {
-        sc.p = nullptr;
-        return fail(EA_ERR_NOMEM, "hipMalloc(C4 shell scratch, %zu bytes): %s", head + fft_bytes,
-                    hipGetErrorString(e));
-    }
-    *qd = sc.p;
-    *shells = sc.p + q_words;
+    ea_status st = sc.reserve(head + fft_bytes);
+    if (st != EA_OK) return st;
+    unsigned long long *base = (unsigned long long *)sc.p;
+    *qd = base;
+    *shells = base + q_words;
     *fft_work = fft_bytes ? (void *)((char *)sc.p + head) : nullptr;
     hipLaunchKernelGGL(ea::zero_u64_kernel, dim3(blocks_for((size_t)n_shells)), dim3(256), 0, stream, *shells,
                        (size_t)n_shells);
@@ -70,11 +58,10 @@ ea_status ea_batch_c4_shells(ea_batch *b, int32_t job, int32_t k, int32_t n_shel
     const int max_shells = 3 * (L / 2) * (L / 2) + 1;
     if (n_shells < 1 || n_shells > max_shells)
         return fail(EA_ERR_ARG, "n_shells=%d outside [1, %d]", n_shells, max_shells);
-    CallScratch sc;
     unsigned long long *qd = nullptr, *shells = nullptr;
     void *fft_work = nullptr;
     int dw = 0;
-    ea_status st = shell_scratch(sc, L, n_shells, &qd, &shells, &fft_work, &dw, b->stream);
+    ea_status st = shell_scratch(b->shell_scratch, L, n_shells, &qd, &shells, &fft_work, &dw, b->stream);
     if (st != EA_OK) return st;
     // the configuration published at measurement k: [replica][colour][POS]
     ea::Lattice lat{};
@@ -100,11 +87,10 @@ ea_status ea_msc_c4_shells(ea_msc *m, int32_t sample, int32_t n_shells, int64_t 
     const int max_shells = 3 * (L / 2) * (L / 2) + 1;
     if (n_shells < 1 || n_shells > max_shells)
         return fail(EA_ERR_ARG, "n_shells=%d outside [1, %d]", n_shells, max_shells);
-    CallScratch sc;
     unsigned long long *qd = nullptr, *shells = nullptr;
     void *fft_work = nullptr;
     int dw = 0;
-    ea_status st = shell_scratch(sc, L, n_shells, &qd, &shells, &fft_work, &dw, m->stream);
+    ea_status st = shell_scratch(m->shell_scratch, L, n_shells, &qd, &shells, &fft_work, &dw, m->stream);
     if (st != EA_OK) return st;
     const size_t q_words = (size_t)L * L * (size_t)dw;
     hipLaunchKernelGGL(ea::msc_dense_q_kernel, dim3(blocks_for(q_words)), dim3(256), 0, m->stream, m->lat, m->geom,
