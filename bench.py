@@ -242,12 +242,12 @@ def alu_probe():
     return out
 
 
-def shells_probe(ea, sizes=(32, 64, 128, 256), reps=3, direct=True):
+def shells_probe(ea, sizes=(32, 64, 128, 256), reps=3, direct_sizes=(32, 64, 128, 256)):
     """Wall time of one full-vector C4 call (ea_c4_shells over every
-    displacement, synchronous) by the FFT route and by the direct route, on
-    a quenched run of each size after 20 sweeps; the two results must be
-    identical.  The FFT route's first call allocates its work array, so the
-    best of `reps` later calls is reported."""
+    displacement, synchronous) by the FFT route, and by the direct route at
+    `direct_sizes`, on a quenched run of each size after 20 sweeps; where both
+    run, the results must be identical.  The first call of each route
+    allocates its scratch, so the best of `reps` later calls is reported."""
     out = {}
     try:
         for L in sizes:
@@ -255,7 +255,7 @@ def shells_probe(ea, sizes=(32, 64, 128, 256), reps=3, direct=True):
             g.sweep(20)
             n_all = 3 * (L // 2) ** 2 + 1
             row, res = {}, {}
-            routes = (("fft", ea.SHELLS_FFT), ("direct", ea.SHELLS_DIRECT)) if direct else (("fft", ea.SHELLS_FFT),)
+            routes = [("fft", ea.SHELLS_FFT)] + ([("direct", ea.SHELLS_DIRECT)] if L in direct_sizes else [])
             for name, route in routes:
                 ea.set_shell_route(route)
                 res[name] = g.c4_shells(n_all)
@@ -265,12 +265,12 @@ def shells_probe(ea, sizes=(32, 64, 128, 256), reps=3, direct=True):
                     g.c4_shells(n_all)
                     best = min(best, time.perf_counter() - t0)
                 row[f"{name}_ms"] = round(best * 1e3, 3)
-            if direct:
+            if "direct" in res:
                 if not (res["fft"] == res["direct"]).all():
                     raise RuntimeError(f"full-vector C4 routes differ at L={L}")
                 row["speedup"] = round(row["direct_ms"] / row["fft_ms"], 1)
             out[f"L{L}"] = row
-            print(json.dumps({"shells_probe_progress": L, **row}), flush=True)
+            log(json.dumps({"shells_probe_progress": L, **row}))
             g.close()
     finally:
         ea.set_shell_route(ea.SHELLS_AUTO)
@@ -472,6 +472,7 @@ def main():
     ap.add_argument("--cpu-agg-sweeps", type=int, default=20,
                     help="sweeps per process of the all-core oracle rate (0 = skip)")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-shells", action="store_true", help="skip the full-vector C4 leg")
     ap.add_argument("--no-autotune", action="store_true", help="run every size with its default configuration")
     ap.add_argument("--serve-jobs", type=int, default=300, help="jobs in the serving leg (0 = skip)")
     ap.add_argument("--serve-load", type=float, default=0.8, help="offered load of the serving leg")
@@ -524,7 +525,8 @@ def main():
 
     if args.shells_probe:
         sizes = (args.shells_probe_l,) if args.shells_probe_l else (32, 64, 128, 256)
-        print(json.dumps({"shells_probe": shells_probe(ea, sizes, direct=not args.shells_fft_only)}), flush=True)
+        print(json.dumps({"shells_probe": shells_probe(ea, sizes, direct_sizes=() if args.shells_fft_only
+                                                       else sizes)}), flush=True)
         return
 
     if args.copy_probe_mib:
@@ -672,6 +674,12 @@ def main():
         plain = bench_plain(ea, torch, wl.mid_job(args.sweeps), args.plain_steps, args.burst)
         out["plain"] = plain
         out["batched_speedup_vs_plain"] = round(plain["ps_per_flip"] / ps_per_flip, 2)
+    if not args.no_shells:
+        log("full-vector C4 shells ...")
+        out["shells"] = {"workload": "ea_c4_shells over every displacement (3 (L/2)^2 + 1 shells) of one run "
+                                     "after 20 sweeps, one synchronous call, best of 3",
+                         "per_pass_roofline": "profiles/fft_shells_L256.md",
+                         **shells_probe(ea, sizes=(128, 256), direct_sizes=(128,))}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         n_cpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
