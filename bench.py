@@ -199,6 +199,10 @@ def bench_plain(ea, torch, job, steps: int, burst: int):
     plan = sim.slab_plan
     sim.close()
     alu = ALG_OPS_PER_FLIP * 2 * job.L ** 3 / (sweep_us * 1e-6) / 1e12
+    # the latency that bounds one-plane slabs: every half-step waits for one
+    # exchange with the neighbouring slabs, whose chain crosses XCDs
+    xchg = exchange_probe()
+    floor_us = 2 * xchg.get("one_way_us_other_xcd", xchg.get("one_way_us_same_xcd", 0.0))
     return {
         "workload": f"L={job.L} p={job.p} T={job.T}, 1 sample x 2 replicas, {job.n_sweeps} sweeps, "
                     f"{len(job.meas_t)} measurements, tw={job.tw}; persistent slab launches between events",
@@ -210,6 +214,11 @@ def bench_plain(ea, torch, job, steps: int, burst: int):
         "sweep_avg_us": round(sweep_us, 3),
         "ps_per_flip_sweeps": round(sweep_us * 1e-6 / (2 * job.L ** 3) * 1e12, 4),
         "alu_frac": round(alu / VALU_PEAK_TOPS, 5),
+        "latency_floor": {"bound": "exchange latency", "exchange": xchg,
+                          "floor_us_per_sweep": round(floor_us, 3),
+                          "note": "two one-way exchanges per sweep (one per half-step), measured live; the "
+                                  "update of a slab's words adds one dependent chain per half-step",
+                          "frac": round(floor_us / sweep_us, 4) if sweep_us > 0 else None},
     }
 
 
@@ -274,6 +283,29 @@ def shells_probe(ea, sizes=(32, 64, 128, 256), reps=3, direct_sizes=(32, 64, 128
             g.close()
     finally:
         ea.set_shell_route(ea.SHELLS_AUTO)
+    return out
+
+
+def exchange_probe(words: int = 64, iters: int = 2000) -> dict:
+    """One-way latency of the slab path's exchange (64-bit {word, epoch}
+    entries, agent-scope stores and polled loads) between two workgroups on
+    one XCD and on two (libea_probe.so, ea_probe_exchange): `words` entries
+    per message, one per lane as in the slab path, averaged over `iters`."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1411_5512_amd", "libea_probe.so"))
+    lib.ea_probe_exchange.restype = ctypes.c_int
+    lib.ea_probe_exchange.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_uint32)]
+    out = {"words": words, "messages": iters}
+    for partner in (8, 1):  # workgroups are dealt to the eight XCDs in turn
+        us = ctypes.c_double(0.0)
+        xcc = (ctypes.c_uint32 * 2)()
+        rc = lib.ea_probe_exchange(partner, words, iters, ctypes.byref(us), xcc)
+        if rc != 0:
+            raise RuntimeError(f"ea_probe_exchange(partner={partner}) failed: {rc}")
+        key = "same_xcd" if xcc[0] == xcc[1] else "other_xcd"
+        out[f"one_way_us_{key}"] = round(us.value, 3)
+        out[f"xcds_{key}"] = [int(xcc[0]), int(xcc[1])]
     return out
 
 
@@ -501,6 +533,9 @@ def main():
                          "route at L = 32, 64, 128, 256, check that they agree, and exit")
     ap.add_argument("--shells-probe-l", type=int, default=0, help="with --shells-probe: this L only")
     ap.add_argument("--shells-fft-only", action="store_true", help="with --shells-probe: the FFT route only")
+    ap.add_argument("--xchg-probe", action="store_true",
+                    help="only measure the one-way latency of the slab path's exchange between two workgroups "
+                         "on one XCD and on two, and exit")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (a known-size kernel "
                          "for calibrating hardware byte counters) and exit")
@@ -527,6 +562,10 @@ def main():
         sizes = (args.shells_probe_l,) if args.shells_probe_l else (32, 64, 128, 256)
         print(json.dumps({"shells_probe": shells_probe(ea, sizes, direct_sizes=() if args.shells_fft_only
                                                        else sizes)}), flush=True)
+        return
+
+    if args.xchg_probe:
+        print(json.dumps({"exchange_probe": {str(w): exchange_probe(w) for w in (64, 256)}}), flush=True)
         return
 
     if args.copy_probe_mib:

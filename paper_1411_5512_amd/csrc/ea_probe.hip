@@ -8,7 +8,10 @@
 // (v_mad_u64_u32) and a three-input bitwise op (v_bitop3_b32) as one VALU
 // issue each.  These kernels measure the sustained lane rate of each
 // instruction and of whole Philox blocks on the device, for comparison with
-// 256 CUs x 4 SIMDs x 16 lanes x clock.
+// 256 CUs x 4 SIMDs x 32 lanes x clock.
+//
+// A second probe measures the latency of the exchange the slab path makes
+// between workgroups on different compute units (ea_probe_exchange).
 //
 // Every thread runs 8 independent chains (enough to cover the pipeline
 // latency with a few waves per SIMD) for `iters` iterations of 16 steps; the
@@ -107,6 +110,62 @@ __global__ __launch_bounds__(256) void philox_probe(uint32_t iters, uint32_t see
     sink[tid] = acc;
 }
 
+// Exchange latency between two workgroups in the form the slab path uses:
+// 64-bit entries {word, epoch} written with agent-scope stores (through to
+// the level all XCDs share) and polled with agent-scope loads until the
+// epoch matches.  Workgroup 0 and workgroup `partner` (of kXchgBlocks one-wave
+// workgroups, dealt to the XCDs in turn) send `words` entries back and forth
+// `iters` times, one way per iteration.  Every wait gives up after
+// kXchgTimeout ticks of the 100 MHz real-time counter and sets err (2), so
+// the kernel always ends; a wrong word sets err (1).
+constexpr int kXchgBlocks = 16;
+constexpr unsigned long long kXchgTimeout = 100000000ull;  // 1 s
+
+__global__ __launch_bounds__(64) void xchg_probe(int partner, int iters, int words, unsigned long long *buf,
+                                                 uint32_t *err, unsigned long long *res, uint32_t *xcc)
+{
+    uint32_t x;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(x));
+    if (threadIdx.x == 0) xcc[blockIdx.x] = x;
+    int me;
+    if (blockIdx.x == 0)
+        me = 0;
+    else if ((int)blockIdx.x == partner)
+        me = 1;
+    else
+        return;
+    const int lane = (int)threadIdx.x;
+    const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+    for (int i = 0; i < iters; ++i) {
+        const int sender = i & 1;
+        unsigned long long *b = buf + (size_t)sender * (size_t)words;
+        const uint32_t epoch = (uint32_t)i + 1u;
+        if (sender == me) {
+            for (int j = lane; j < words; j += 64)
+                __hip_atomic_store(b + j, ((unsigned long long)epoch << 32) | (uint32_t)(i * 7919 + j),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const unsigned long long start = __builtin_amdgcn_s_memrealtime();
+            uint32_t bad = 0;
+            for (int j = lane; j < words && !bad; j += 64) {
+                unsigned long long v;
+                for (;;) {
+                    v = __hip_atomic_load(b + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if ((uint32_t)(v >> 32) == epoch) break;
+                    if (__builtin_amdgcn_s_memrealtime() - start > kXchgTimeout) {
+                        bad = 2;
+                        break;
+                    }
+                }
+                if (!bad && (uint32_t)v != (uint32_t)(i * 7919 + j)) bad = 1;
+            }
+            if (bad) atomicOr(err, bad);
+            if (__any(bad == 2)) break;  // the partner stopped: end
+        }
+    }
+    if (lane == 0) res[me] = __builtin_amdgcn_s_memrealtime() - t0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -161,6 +220,46 @@ int ea_probe_alu(int kind, int blocks, unsigned iters, double *ms, double *ops)
     if (e != hipSuccess) return (int)e;
     *ms = t;
     *ops = per_iter * (double)iters * (double)blocks * 256.0;
+    return 0;
+}
+
+// One-way latency (microseconds) of the slab path's exchange between
+// workgroup 0 and workgroup `partner` (1 .. 15), `words` entries (1 .. 1024)
+// per message, averaged over `iters` (2 .. 100000) messages; the XCDs the two
+// ran on go to xcc[0], xcc[1].  0 on success, 1 on a bad argument, 2 on a
+// HIP error, 3 if a word came back wrong or a wait timed out.
+int ea_probe_exchange(int partner, int words, int iters, double *one_way_us, uint32_t *xcc_out)
+{
+    if (partner < 1 || partner >= kXchgBlocks || words < 1 || words > 1024 || iters < 2 || iters > 100000 ||
+        !one_way_us || !xcc_out)
+        return 1;
+    unsigned long long *buf = nullptr, *res = nullptr;
+    uint32_t *err = nullptr, *xcc = nullptr;
+    hipError_t e = hipMalloc((void **)&buf, 2 * (size_t)words * 8);
+    if (e == hipSuccess) e = hipMalloc((void **)&res, 2 * 8);
+    if (e == hipSuccess) e = hipMalloc((void **)&err, 4);
+    if (e == hipSuccess) e = hipMalloc((void **)&xcc, kXchgBlocks * 4);
+    if (e == hipSuccess) e = hipMemset(buf, 0, 2 * (size_t)words * 8);
+    if (e == hipSuccess) e = hipMemset(err, 0, 4);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(xchg_probe, dim3(kXchgBlocks), dim3(64), 0, 0, partner, iters, words, buf, err, res, xcc);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    unsigned long long r[2] = {0, 0};
+    uint32_t bad = 0, xc[kXchgBlocks] = {};
+    if (e == hipSuccess) e = hipMemcpy(r, res, sizeof r, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(&bad, err, 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(xc, xcc, sizeof xc, hipMemcpyDeviceToHost);
+    (void)hipFree(buf);
+    (void)hipFree(res);
+    (void)hipFree(err);
+    (void)hipFree(xcc);
+    if (e != hipSuccess) return 2;
+    if (bad) return 3;
+    *one_way_us = (double)r[0] * 0.01 / iters;  // 100 MHz ticks
+    xcc_out[0] = xc[0];
+    xcc_out[1] = xc[partner];
     return 0;
 }
 
