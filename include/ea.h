@@ -168,8 +168,8 @@ ea_status ea_words_per_row(const ea_sim *sim, int32_t *rw);
  * Dividing a shell by N and by the number of lattice vectors in it gives the
  * shell average of C4.  Two routes give the same integers (ea_set_shell_route):
  * the direct one counts differing bits for every displacement (work ~ L^6 /
- * 64: about 20 ms at L = 128, over a second at L = 256); for power-of-two L
- * the FFT route takes the fp64 3D DFT of q, its squared modulus and the
+ * 64: about 20 ms at L = 128, over a second at L = 256); for L = 2^k or
+ * 3 2^k the FFT route takes the fp64 3D DFT of q, its squared modulus and the
  * inverse DFT (the Wiener-Khinchin theorem), rounds each sum to the nearest
  * integer and bins it (work ~ L^3 log L).  Synchronises; allocates a device
  * scratch buffer of 8 (2 L^2 ceil(L/64) + 3 (L/2)^2 + 1) bytes on the first
@@ -182,10 +182,10 @@ ea_status ea_c4_shells(ea_sim *sim, int32_t n_shells, int64_t *out);
 
 /* Route of the full-vector C4 shells (ea_c4_shells, ea_batch_c4_shells,
  * ea_msc_c4_shells; ea_c4_shells_into always takes the direct route):
- *   EA_SHELLS_AUTO    the FFT route for power-of-two L >= 64, else direct
+ *   EA_SHELLS_AUTO    the FFT route for L = 2^k or 3 2^k >= 64, else direct
  *                     (the default);
  *   EA_SHELLS_DIRECT  the direct route for every L;
- *   EA_SHELLS_FFT     the FFT route for every power-of-two L (8 .. 256); other
+ *   EA_SHELLS_FFT     the FFT route for every L = 2^k (8 .. 256) or 3 2^k (24 .. 192); other
  *                     L take the direct route.
  * Both routes give identical results.  Process-wide, read at each call.
  * EA_ERR_ARG for another value. */

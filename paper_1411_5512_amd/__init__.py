@@ -51,8 +51,8 @@ SHELLS_AUTO, SHELLS_DIRECT, SHELLS_FFT = 0, 1, 2
 
 def set_shell_route(route: int = SHELLS_AUTO) -> None:
     """Route of the full-vector C4 shells (ea_set_shell_route): automatic
-    (FFT for power-of-two L >= 64), direct bit counting, or FFT wherever L
-    is a power of two.  Both give identical results."""
+    (FFT for L = 2^k or 3 2^k >= 64), direct bit counting, or FFT wherever
+    L = 2^k or 3 2^k.  Both give identical results."""
     abi.check(abi.lib().ea_set_shell_route(int(route)))
 
 

@@ -691,21 +691,14 @@ ea_status launch_shell_rows(const unsigned long long *qd, int L, int n_shells, u
 
 // Route of the full-vector C4 shells (ea_set_shell_route).
 std::atomic<int32_t> g_shell_route{EA_SHELLS_AUTO};
-// automatic route: FFT for power-of-two L from this side on (at L = 32 the
+// automatic route: FFT for L = 2^k or 3 2^k from this side on (at L = 32 the
 // direct kernel is faster: 0.07 against 0.10 ms per call)
 constexpr int kFftAutoMinL = 64;
-
-int log2_pow2(int L)
-{
-    for (int k = 3; k <= 8; ++k)
-        if (L == (1 << k)) return k;
-    return -1;
-}
 
 bool shells_by_fft(int L)
 {
     const int32_t r = g_shell_route.load();
-    if (log2_pow2(L) < 0 || r == EA_SHELLS_DIRECT) return false;
+    if (!ea::fft_side(L) || r == EA_SHELLS_DIRECT) return false;
     return r == EA_SHELLS_FFT || L >= kFftAutoMinL;
 }
 
@@ -742,18 +735,18 @@ struct ShellScratch {
 // Device bytes of the FFT route: the complex array, then the error word.
 size_t fft_work_bytes(int L) { return 16 * (size_t)L * L * L + 256; }
 
-template <int LOG2L>
+template <int L>
 void launch_fft_passes(const ea::FftArgs &a, hipStream_t stream)
 {
-    constexpr int L = 1 << LOG2L, H = L / 2, B = ea::FftShape<LOG2L>::B;
+    constexpr int H = L / 2, B = ea::FftShape<L>::B;
     const dim3 grid((unsigned)(L * L / B)), block(ea::kFftThreads);
     const dim3 half((unsigned)((H + 1) * (L / B)));  // tiles of the planes z <= L/2
     const dim3 bins((unsigned)((H + 1) * ((H + ea::kFftBinY) / ea::kFftBinY)));
-    hipLaunchKernelGGL((ea::fft_pass_kernel<LOG2L, ea::kFftFwdBitsX>), grid, block, 0, stream, a);
-    hipLaunchKernelGGL((ea::fft_pass_kernel<LOG2L, ea::kFftFwdY>), grid, block, 0, stream, a);
-    hipLaunchKernelGGL((ea::fft_pass_kernel<LOG2L, ea::kFftSquareZ>), grid, block, 0, stream, a);
-    hipLaunchKernelGGL((ea::fft_pass_kernel<LOG2L, ea::kFftInvY>), half, block, 0, stream, a);
-    hipLaunchKernelGGL((ea::fft_bin_kernel<LOG2L>), bins, block, 0, stream, a);
+    hipLaunchKernelGGL((ea::fft_pass_kernel<L, ea::kFftFwdBitsX>), grid, block, 0, stream, a);
+    hipLaunchKernelGGL((ea::fft_pass_kernel<L, ea::kFftFwdY>), grid, block, 0, stream, a);
+    hipLaunchKernelGGL((ea::fft_pass_kernel<L, ea::kFftSquareZ>), grid, block, 0, stream, a);
+    hipLaunchKernelGGL((ea::fft_pass_kernel<L, ea::kFftInvY>), half, block, 0, stream, a);
+    hipLaunchKernelGGL((ea::fft_bin_kernel<L>), bins, block, 0, stream, a);
 }
 
 // Shell sums of dense overlap rows (dw words per row) through the FFT route
@@ -770,14 +763,18 @@ ea_status launch_fft_shells(const unsigned long long *qd, int dw, int L, int n_s
     unsigned long long *err = (unsigned long long *)((char *)work + 16 * (size_t)L * L * L);
     a.err = (unsigned int *)err;
     hipLaunchKernelGGL(ea::zero_u64_kernel, dim3(1), dim3(256), 0, stream, err, (size_t)1);
-    switch (log2_pow2(L)) {
-    case 3: launch_fft_passes<3>(a, stream); break;
-    case 4: launch_fft_passes<4>(a, stream); break;
-    case 5: launch_fft_passes<5>(a, stream); break;
-    case 6: launch_fft_passes<6>(a, stream); break;
-    case 7: launch_fft_passes<7>(a, stream); break;
+    switch (L) {
     case 8: launch_fft_passes<8>(a, stream); break;
-    default: return fail(EA_ERR_ARG, "the FFT route of full-vector C4 needs a power-of-two L in 8..256 (L=%d)", L);
+    case 16: launch_fft_passes<16>(a, stream); break;
+    case 32: launch_fft_passes<32>(a, stream); break;
+    case 64: launch_fft_passes<64>(a, stream); break;
+    case 128: launch_fft_passes<128>(a, stream); break;
+    case 256: launch_fft_passes<256>(a, stream); break;
+    case 24: launch_fft_passes<24>(a, stream); break;
+    case 48: launch_fft_passes<48>(a, stream); break;
+    case 96: launch_fft_passes<96>(a, stream); break;
+    case 192: launch_fft_passes<192>(a, stream); break;
+    default: return fail(EA_ERR_ARG, "the FFT route of full-vector C4 needs L = 2^k or 3 2^k in 8..256 (L=%d)", L);
     }
     EA_HIP(hipGetLastError());
     return EA_OK;

@@ -5,7 +5,7 @@
 
 namespace {
 
-// Sum the shells from the dense rows (FFT route for power-of-two L unless
+// Sum the shells from the dense rows (FFT route for L = 2^k or 3 2^k unless
 // ea_set_shell_route says otherwise, else the rows kernel), copy them to the
 // host and wait.
 ea_status shells_to_host(const unsigned long long *qd, int dw, unsigned long long *shells, void *fft_work, int L,

@@ -51,10 +51,10 @@ def _numpy_shells(q, L, n_shells):
     return out
 
 
-@pytest.mark.parametrize("L,rw", [(8, 0), (16, 0), (16, 1), (32, 0), (32, 2)])
+@pytest.mark.parametrize("L,rw", [(8, 0), (16, 0), (16, 1), (24, 0), (24, 1), (32, 0), (32, 2)])
 def test_fft_shells_match_oracle(ea_route, oracle_mod, L, rw):
-    """Every power-of-two size the route takes below 64, in several packings:
-    equal to the oracle's shells (every displacement, the |r| <= L/2
+    """The sizes the route takes up to 32 (2^k, and 24 = 3 x 8 with its
+    radix-3 stage), in several packings: equal to the oracle's shells (every displacement, the |r| <= L/2
     default, and truncations to 5 and 1 shells), and to the direct route."""
     ea = ea_route
     g = ea.Sim(L, 0.5, 0.8, seed=8, sample=2, words_per_row=rw)
@@ -69,7 +69,7 @@ def test_fft_shells_match_oracle(ea_route, oracle_mod, L, rw):
         assert np.array_equal(direct, want), (L, n)
 
 
-@pytest.mark.parametrize("L", [64, 128, 256])
+@pytest.mark.parametrize("L", [48, 64, 96, 128, 192, 256])
 def test_fft_shells_equal_direct_full_size(ea_route, L):
     """At full size (no oracle): the FFT route equals the direct route and
     numpy's FFT of the GPU's own q, over every displacement and |r| <= L/2;
@@ -88,7 +88,7 @@ def test_fft_shells_equal_direct_full_size(ea_route, L):
     assert np.array_equal(g.c4_shells(), fft[:(L // 2) ** 2 + 1])
 
 
-@pytest.mark.parametrize("L", [8, 64, 256])
+@pytest.mark.parametrize("L", [8, 24, 64, 96, 256])
 def test_fft_shells_extreme_spectra(ea_route, L):
     """q = 1 everywhere (replica 1 a copy of replica 0): shell k = N times the
     number of displacements in it.  q = (-1)^(x+y+z): every product
@@ -114,17 +114,24 @@ def test_fft_shells_extreme_spectra(ea_route, L):
 
 
 def test_fft_shells_batch_and_msc(ea_route, oracle_mod):
-    """The batched form's published configurations (L = 16 and 32) and
+    """The batched form's published configurations (L = 16, 24, 32) and
     multispin samples (L = 32, two word sets) by the FFT route against the
-    oracle's shells of the same runs; a multispin L = 64 batch, FFT against
-    direct."""
+    oracle's shells of the same runs; an L = 48 job and a multispin L = 64
+    batch, FFT against direct."""
     ea = ea_route
     from paper_1411_5512_amd.workloads import Job
     jobs = [Job(16, 0.5, 0.8, seed=51, sample=0, n_sweeps=9, meas_t=[4, 9], tw=[]),
-            Job(32, 0.25, 0.7, seed=52, sample=3, n_sweeps=7, meas_t=[7], tw=[7])]
+            Job(32, 0.25, 0.7, seed=52, sample=3, n_sweeps=7, meas_t=[7], tw=[7]),
+            Job(24, 0.4, 0.9, seed=53, sample=1, n_sweeps=5, meas_t=[5], tw=[]),
+            Job(48, 0.3, 0.6, seed=54, sample=2, n_sweeps=4, meas_t=[4], tw=[])]
     b = ea.Batch(jobs)
     b.run()
     for j, job in enumerate(jobs):
+        if job.L > 32:  # beyond the oracle's brute-force shells in test time
+            _say(f"fft shells batch job {j} L={job.L}: FFT against direct")
+            fft, direct = _routes(ea, lambda: b.c4_shells(j, 0, 3 * (job.L // 2) ** 2 + 1))
+            assert np.array_equal(fft, direct) and fft[0] == job.L ** 3, j
+            continue
         o = oracle_mod.Sim(job.L, job.p, job.T, seed=job.seed, sample=job.sample)
         t = 0
         n_all = 3 * (job.L // 2) ** 2 + 1
