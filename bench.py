@@ -690,6 +690,11 @@ def main():
             "valu_issue_measured": valu_issue,  # SQ_INSTS_VALU over the device's issue slots (record)
             "hbm_frac": round(((traffic or alg_bytes) / launch_s / 1e9) / 8000.0, 5),
             "flips_per_launch": flips_per_step,
+            "pricing": (f"{ALG_OPS_PER_FLIP:g} lane-op slots per flip (a quarter Philox4x32-10 block with its "
+                        f"multiply-adds at the half rate --alu-probe measures, plus the compare) against "
+                        f"{VALU_PEAK_TOPS:.2f} T slots/s; the earlier pricing, 11 ops per flip against a 16-lane "
+                        f"39.32 T ops/s, gives {11 * flips_per_step / launch_s / 1e12 / 39.32:.3f} for the same "
+                        f"launch"),
         },
     }
     batch.close()
