@@ -747,6 +747,8 @@ void launch_fft_passes(const ea::FftArgs &a, hipStream_t stream)
     hipLaunchKernelGGL((ea::fft_pass_kernel<L, ea::kFftSquareZ>), grid, block, 0, stream, a);
     hipLaunchKernelGGL((ea::fft_pass_kernel<L, ea::kFftInvY>), half, block, 0, stream, a);
     hipLaunchKernelGGL((ea::fft_bin_kernel<L>), bins, block, 0, stream, a);
+    hipLaunchKernelGGL((ea::fft_shell_sum_kernel<L>), dim3(blocks_for((size_t)(H + 1) * (H + 1) * (H + 1))),
+                       dim3(256), 0, stream, a);
 }
 
 // Shell sums of dense overlap rows (dw words per row) through the FFT route

@@ -28,7 +28,7 @@ constexpr int kFftThreads = 256;
 
 // The passes, in order: forward along x from the dense q rows, forward along
 // y, forward along z + |.|^2 + inverse along z, inverse along y, inverse along
-// x + rounding and shell sums (fft_bin_kernel).
+// x + rounding (fft_bin_kernel); then the shell sums (fft_shell_sum_kernel).
 enum FftOp { kFftFwdBitsX = 0, kFftFwdY = 1, kFftSquareZ = 2, kFftInvY = 3, kFftInvBinX = 4 };
 
 struct FftArgs {
@@ -322,11 +322,21 @@ __global__ __launch_bounds__(kFftThreads) void fft_pass_kernel(FftArgs a)
 
 constexpr int kFftBinY = 4;  // y values per workgroup of the last pass
 
-// The last pass, on the planes z = 0 .. L/2: a workgroup takes kFftBinY
-// values y <= L/2 of one z and, for each, the rows y and L - y (one row if y
-// is 0 or L/2), transforms them along x (DIT), and for every |x| = i <= L/2
-// adds the rounded sums at x = +-i of both rows to the shell i^2 + y^2 + z^2
-// (these are the minimum images) in one atomic.  A row (y, z) and the row
+// The sums T(i, y, z) of the last pass, one per |x| = i, |y|, |z| <= L/2,
+// at [(z (L/2 + 1) + y) (L/2 + 1) + i], in the planes z > L/2 of the complex
+// array (no pass reads those after kFftSquareZ; they hold 16 (L/2 - 1) L^2
+// bytes, more than the 8 (L/2 + 1)^3 needed).
+template <int L>
+__device__ __forceinline__ long long *fft_sums(double2 *z)
+{
+    return reinterpret_cast<long long *>(z + (size_t)(L / 2 + 1) * L * L);
+}
+
+// The last transform pass, on the planes z = 0 .. L/2: a workgroup takes
+// kFftBinY values y <= L/2 of one z and, for each, the rows y and L - y (one
+// row if y is 0 or L/2), transforms them along x (DIT), and for every
+// |x| = i <= L/2 stores the rounded sums at x = +-i of both rows as T(i, y, z),
+// the sum over the minimum images (+-i, +-y, z).  A row (y, z) and the row
 // (L - y, L - z) hold A(x, y, z) and A(-x, y, z), so for 0 < z < L/2 the
 // sums count twice for the planes L - z that are not transformed.
 template <int L>
@@ -355,11 +365,10 @@ __global__ __launch_bounds__(kFftThreads) void fft_bin_kernel(FftArgs a)
     fft_lines<L, NL, true>(s, tw, tid);
 
     const long long weight = (z == 0 || z == H) ? 1 : 2;
+    long long *T = fft_sums<L>(a.z);
     for (int t = tid; t < kFftBinY * (H + 1); t += kFftThreads) {
         const int j = t / (H + 1), i = t - j * (H + 1), y = y0 + j;
         if (y > H) continue;
-        const int k = i * i + y * y + z * z;
-        if (k >= a.n_shells) continue;
         long long sum = 0;
         bool bad = false;
 #pragma unroll
@@ -372,8 +381,36 @@ __global__ __launch_bounds__(kFftThreads) void fft_bin_kernel(FftArgs a)
             sum += (long long)r;
         }
         if (bad) atomicOr(a.err, 1u);
-        atomicAdd(a.shells + k, (unsigned long long)(sum * weight));
+        T[((size_t)z * (H + 1) + (size_t)y) * (H + 1) + (size_t)i] = sum * weight;
     }
+}
+
+// Shell sums from T: one thread per sorted triple p <= q <= r of |x|, |y|,
+// |z| values adds T over the triple's distinct orderings (all of which lie in
+// the shell p^2 + q^2 + r^2) in one atomic, a sixth as many as one per
+// ordering.  One thread per point of the (L/2 + 1)^3 cube; the others return.
+template <int L>
+__global__ __launch_bounds__(256) void fft_shell_sum_kernel(FftArgs a)
+{
+    constexpr int H1 = L / 2 + 1;
+    const long long *T = fft_sums<L>(a.z);
+    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t >= H1 * H1 * H1) return;
+    const int p = t % H1, q = (t / H1) % H1, r = t / (H1 * H1);
+    if (p > q || q > r) return;
+    const int k = p * p + q * q + r * r;
+    if (k >= a.n_shells) return;
+    auto at = [T](int i, int y, int z) { return T[((size_t)z * H1 + (size_t)y) * H1 + (size_t)i]; };
+    long long sum = at(p, q, r);
+    if (p == q && q == r) {
+    } else if (p == q) {  // (p, p, r): also (p, r, p), (r, p, p)
+        sum += at(p, r, p) + at(r, p, p);
+    } else if (q == r) {  // (p, q, q): also (q, p, q), (q, q, p)
+        sum += at(q, p, q) + at(q, q, p);
+    } else {
+        sum += at(p, r, q) + at(q, p, r) + at(q, r, p) + at(r, p, q) + at(r, q, p);
+    }
+    atomicAdd(a.shells + k, (unsigned long long)sum);
 }
 
 }  // namespace ea
