@@ -329,6 +329,8 @@ constexpr int kFftBinY = 4;  // y values per workgroup of the last pass
 template <int L>
 __device__ __forceinline__ long long *fft_sums(double2 *z)
 {
+    static_assert((size_t)16 * (L / 2 - 1) * L * L >= (size_t)8 * (L / 2 + 1) * (L / 2 + 1) * (L / 2 + 1),
+                  "the sums fit in the planes z > L/2");
     return reinterpret_cast<long long *>(z + (size_t)(L / 2 + 1) * L * L);
 }
 
