@@ -158,6 +158,75 @@ __device__ __forceinline__ void fft_stage4(double2 *s, const double2 *tw, int sl
     }
 }
 
+// Three radix-2 stages, of spans 4h, 2h and h (h = 2^sl), in registers on
+// each octet {p + m h : m = 0 .. 7}, p = g 8h + pos, pos < h, of a P-point
+// block: span 4h pairs (m, m + 4) at positions pos + m h, span 2h pairs
+// (m, m + 2) of each half at pos + (m & 1) h, span h pairs (m, m + 1) at
+// pos.  DIF takes the spans in decreasing order, DIT in increasing order;
+// the same as the three radix-2 stages in turn, with a third of their LDS
+// round trips and barriers.
+template <int L, int NL, bool DIT>
+__device__ __forceinline__ void fft_stage8(double2 *s, const double2 *tw, int sl, int tid)
+{
+    using S = FftShape<L>;
+    constexpr int O = S::P / 8;
+    const int h = 1 << sl;
+    for (int t = tid; t < NL * S::SC * O; t += kFftThreads) {
+        const int sb = t >> (S::LOG2P - 3), kk = t & (O - 1);
+        const int pos = kk & (h - 1);
+        double2 *p = s + fft_block_base<L>(sb) + (((kk >> sl) << (sl + 3)) | pos);
+        double2 x[8], wa[4], wb[2];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) x[m] = p[m * h];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) wa[m] = tw[S::SC * ((pos + m * h) << (S::LOG2P - 3 - sl))];
+#pragma unroll
+        for (int m = 0; m < 2; ++m) wb[m] = tw[S::SC * ((pos + m * h) << (S::LOG2P - 2 - sl))];
+        const double2 wc = tw[S::SC * (pos << (S::LOG2P - 1 - sl))];
+        if constexpr (DIT) {
+#pragma unroll
+            for (int m = 0; m < 8; m += 2) {
+                const double2 u = cmulc(x[m + 1], wc);
+                x[m + 1] = csub(x[m], u);
+                x[m] = cadd(x[m], u);
+            }
+#pragma unroll
+            for (int m = 0; m < 8; m += (m & 1) ? 3 : 1) {  // 0, 1, 4, 5
+                const double2 u = cmulc(x[m + 2], wb[m & 1]);
+                x[m + 2] = csub(x[m], u);
+                x[m] = cadd(x[m], u);
+            }
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const double2 u = cmulc(x[m + 4], wa[m]);
+                x[m + 4] = csub(x[m], u);
+                x[m] = cadd(x[m], u);
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const double2 a = x[m], b = x[m + 4];
+                x[m] = cadd(a, b);
+                x[m + 4] = cmul(csub(a, b), wa[m]);
+            }
+#pragma unroll
+            for (int m = 0; m < 8; m += (m & 1) ? 3 : 1) {  // 0, 1, 4, 5
+                const double2 a = x[m], b = x[m + 2];
+                x[m] = cadd(a, b);
+                x[m + 2] = cmul(csub(a, b), wb[m & 1]);
+            }
+#pragma unroll
+            for (int m = 0; m < 8; m += 2) {
+                const double2 a = x[m], b = x[m + 1];
+                x[m] = cadd(a, b);
+                x[m + 1] = cmul(csub(a, b), wc);
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < 8; ++m) p[m * h] = x[m];
+    }
+}
+
 // The radix-3 stage of span P = L / 3 on each line: (x0, x1, x2) at
 // (pos, pos + P, pos + 2P).  With w3 = exp(-2 pi i / 3) and W = exp(-2 pi i
 // / L), DIF writes x0 + x1 + x2, (x0 + w3 x1 + w3^2 x2) W^pos and (x0 + w3^2 x1
@@ -194,22 +263,29 @@ __device__ __forceinline__ void fft_stage3(double2 *s, const double2 *tw, int ti
 }
 
 // The whole transform of the NL lines; ends with a barrier.  DIF: the
-// radix-3 stage (L = 3P), then spans P/2 .. 1 on each P-point block, two
-// stages per round and a radix-2 stage for odd log2 P; DIT: the same in the
-// opposite order.
+// radix-3 stage (L = 3P), then spans P/2 .. 1 on each P-point block, three
+// stages per round, the last one or two in a radix-4 or radix-2 round; DIT:
+// the same rounds in the opposite order, then the radix-3 stage.
 template <int L, int NL, bool DIT>
 __device__ __forceinline__ void fft_lines(double2 *s, const double2 *tw, int tid)
 {
     using S = FftShape<L>;
     constexpr int LOG2P = S::LOG2P;
     if constexpr (DIT) {
+        // the mirror of the DIF grouping: the radix-2 or radix-4 remainder on
+        // the smallest spans first, then radix-8 rounds
         int st = 0;
-        for (; st + 1 < LOG2P; st += 2) {
-            fft_stage4<L, NL, true>(s, tw, st, tid);
+        if constexpr (LOG2P % 3 == 1) {
+            fft_stage2<L, NL, true>(s, tw, 0, tid);
             __syncthreads();
+            st = 1;
+        } else if constexpr (LOG2P % 3 == 2) {
+            fft_stage4<L, NL, true>(s, tw, 0, tid);
+            __syncthreads();
+            st = 2;
         }
-        if (st < LOG2P) {
-            fft_stage2<L, NL, true>(s, tw, st, tid);
+        for (; st + 2 < LOG2P; st += 3) {
+            fft_stage8<L, NL, true>(s, tw, st, tid);
             __syncthreads();
         }
         if constexpr (S::R3) {
@@ -222,9 +298,14 @@ __device__ __forceinline__ void fft_lines(double2 *s, const double2 *tw, int tid
             __syncthreads();
         }
         int st = LOG2P - 1;
-        for (; st >= 1; st -= 2) {
+        for (; st >= 2; st -= 3) {
+            fft_stage8<L, NL, false>(s, tw, st - 2, tid);
+            __syncthreads();
+        }
+        if (st >= 1) {
             fft_stage4<L, NL, false>(s, tw, st - 1, tid);
             __syncthreads();
+            st -= 2;
         }
         if (st == 0) {
             fft_stage2<L, NL, false>(s, tw, 0, tid);
